@@ -1,0 +1,477 @@
+/*
+ * saba_oracle.c -- CPU oracle for the random-bouquet walk generator and the
+ * TGT+ all-edges spanning-centrality estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code with the GPU
+ * library (no headers, helpers or tables); both are written from the paper
+ * and from the published definition of MurmurHash2.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled on them):
+ *  - Hash (Sec. 3.1 and the AESC experiments, which name Murmur2): 32-bit
+ *    MurmurHash2 over little-endian 32-bit words.
+ *  - Neighbour choice (Eq. (5), with divisions replaced by multiplications as
+ *    in Sec. 4): k = floor(u * d / 2^32) for a 32-bit u, i.e. h_max is the
+ *    exclusive bound 2^32.
+ *  - Per-walk seed (Eq. (4)/(5), Sec. 3.3): a keyed form.  A walk with
+ *    address (a0,a1,a2) and index k in its bouquet schedule (G, S) has
+ *    key_hi = Murmur2(a0|a1|a2|floor(k/G), seed) and key_lo = (k mod G) << S;
+ *    step l at vertex cur draws u = Murmur2(cur|l, key_hi) XOR key_lo.
+ *  - Walk semantics (Alg. 2): position 0 is the start; positions 1..L are
+ *    filled by steps l = 1..L; visits are counted at positions 1..L and the
+ *    endpoint is position L.
+ *  - TGT+ (Alg. 1) as read: truncation tau from the spectral tail bound,
+ *    deterministic pull recursion for the p-vectors, the Alg. 1 while-loop
+ *    stop rule, NWalks from a Hoeffding bound, and per-pair Monte-Carlo
+ *    accumulation as in the paper's inner loop.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see build.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* MurmurHash2, 32-bit (Austin Appleby's public-domain algorithm), written
+ * from its published description: multiplier 0x5bd1e995, shift 24, seed
+ * XOR length, 4-byte little-endian blocks, byte tail, final avalanche
+ * (>>13, *m, >>15). */
+uint32_t orc_murmur2(const uint8_t *data, int32_t len, uint32_t seed)
+{
+    const uint32_t m = 0x5bd1e995u;
+    uint32_t h = seed ^ (uint32_t)len;
+    int32_t i = 0;
+    for (; i + 4 <= len; i += 4) {
+        uint32_t k = (uint32_t)data[i] | ((uint32_t)data[i + 1] << 8) |
+                     ((uint32_t)data[i + 2] << 16) | ((uint32_t)data[i + 3] << 24);
+        k *= m;
+        k ^= k >> 24;
+        k *= m;
+        h *= m;
+        h ^= k;
+    }
+    int32_t rest = len - i;
+    if (rest == 3) h ^= (uint32_t)data[i + 2] << 16;
+    if (rest >= 2) h ^= (uint32_t)data[i + 1] << 8;
+    if (rest >= 1) {
+        h ^= (uint32_t)data[i];
+        h *= m;
+    }
+    h ^= h >> 13;
+    h *= m;
+    h ^= h >> 15;
+    return h;
+}
+
+static void put_le32(uint8_t *p, uint32_t v)
+{
+    p[0] = (uint8_t)(v & 0xffu);
+    p[1] = (uint8_t)((v >> 8) & 0xffu);
+    p[2] = (uint8_t)((v >> 16) & 0xffu);
+    p[3] = (uint8_t)((v >> 24) & 0xffu);
+}
+
+/* Murmur2 of a sequence of 32-bit words, serialised little-endian. */
+uint32_t orc_hash_words(const uint32_t *w, int32_t nw, uint32_t seed)
+{
+    uint8_t buf[64];
+    for (int32_t i = 0; i < nw; ++i) put_le32(buf + 4 * i, w[i]);
+    return orc_murmur2(buf, 4 * nw, seed);
+}
+
+/* Batch form used by the statistical tests: out[i] = Murmur2(a[i]|b[i], seed). */
+void orc_hash2_batch(const uint32_t *a, const uint32_t *b, int64_t n, uint32_t seed, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w[2];
+        w[0] = a[i];
+        w[1] = b[i];
+        out[i] = orc_hash_words(w, 2, seed);
+    }
+}
+
+/* Eq. (5): scale the hashed value to [0, d) without a modulo. */
+uint32_t orc_choice(uint32_t u, uint32_t d)
+{
+    return (uint32_t)(((uint64_t)u * (uint64_t)d) >> 32);
+}
+
+/* Sec. 3.3 (SABA arrangement) in keyed form: walks k of one address are
+ * grouped G at a time; members of a group share key_hi and differ in key_lo. */
+void orc_walk_key(uint32_t seed, uint32_t a0, uint32_t a1, uint32_t a2, uint64_t k,
+                  uint32_t G, uint32_t S, uint32_t *key_hi, uint32_t *key_lo)
+{
+    uint32_t w[4];
+    uint64_t g = k / G;
+    uint32_t r = (uint32_t)(k % G);
+    w[0] = a0;
+    w[1] = a1;
+    w[2] = a2;
+    w[3] = (uint32_t)g;
+    *key_hi = orc_hash_words(w, 4, seed);
+    *key_lo = (G > 1) ? (r << S) : 0u;
+}
+
+/* Alg. 2 step: pick the next vertex of a walk standing at `cur` while
+ * filling position l. */
+static int32_t orc_step(const int32_t *row_ptr, const int32_t *col_idx, int32_t cur,
+                        uint32_t l, uint32_t key_hi, uint32_t key_lo)
+{
+    uint32_t w[2];
+    w[0] = (uint32_t)cur;
+    w[1] = l;
+    uint32_t u = orc_hash_words(w, 2, key_hi) ^ key_lo;
+    uint32_t d = (uint32_t)(row_ptr[cur + 1] - row_ptr[cur]);
+    uint32_t k = orc_choice(u, d);
+    return col_idx[row_ptr[cur] + (int32_t)k];
+}
+
+/* Alg. 2: the whole path of one walk, positions 0..L (path has L+1 slots). */
+int32_t orc_walk_path(const int32_t *row_ptr, const int32_t *col_idx, int32_t start,
+                      int32_t L, uint32_t key_hi, uint32_t key_lo, int32_t *path)
+{
+    int32_t cur = start;
+    path[0] = cur;
+    for (int32_t l = 1; l <= L; ++l) {
+        if (row_ptr[cur + 1] == row_ptr[cur]) return -1; /* isolated vertex */
+        cur = orc_step(row_ptr, col_idx, cur, (uint32_t)l, key_hi, key_lo);
+        path[l] = cur;
+    }
+    return 0;
+}
+
+/* Synthetic random-walk benchmark (Sec. 5.4): walks from the given start
+ * vertices, counting vertex visits at positions 1..L and endpoints at L.
+ * Walk j starting at s is the r-th walk of s in list order (r counts the
+ * earlier list entries with the same start); its key is that of address
+ * (s, 0, 0) and index r. */
+int32_t orc_walks_histogram(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                            const int32_t *sources, int64_t n_walks, int32_t L,
+                            uint32_t seed, uint32_t G, uint32_t S,
+                            int64_t *endpoint, int64_t *visits, int32_t nthreads)
+{
+    int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_walks > 0 ? n_walks : 1));
+    int64_t *seen = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!rank || !seen) {
+        free(rank);
+        free(seen);
+        return -2;
+    }
+    for (int64_t j = 0; j < n_walks; ++j) {
+        int32_t s = sources[j];
+        if (s < 0 || s >= n || row_ptr[s + 1] == row_ptr[s]) {
+            free(rank);
+            free(seen);
+            return -1;
+        }
+        rank[j] = seen[s]++;
+    }
+    memset(endpoint, 0, sizeof(int64_t) * (size_t)n);
+    memset(visits, 0, sizeof(int64_t) * (size_t)n);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4096)
+#endif
+    for (int64_t j = 0; j < n_walks; ++j) {
+        uint32_t khi, klo;
+        orc_walk_key(seed, (uint32_t)sources[j], 0u, 0u, (uint64_t)rank[j], G, S, &khi, &klo);
+        int32_t cur = sources[j];
+        for (int32_t l = 1; l <= L; ++l) {
+            cur = orc_step(row_ptr, col_idx, cur, (uint32_t)l, khi, klo);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            visits[cur] += 1;
+        }
+        if (L > 0) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            endpoint[cur] += 1;
+        }
+    }
+    free(rank);
+    free(seen);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* TGT+ as read (Alg. 1). */
+
+/* CalculateTau(e, eps/2): smallest tau >= 0 with
+ * (1/d_s + 1/d_t) * lambda^(tau+1) <= (eps/2) * (1 - lambda),
+ * the spectral tail bound of the truncated resistance series; powers by
+ * repeated multiplication. Capped at tau_cap. */
+int32_t orc_tau(int32_t ds, int32_t dt, double lambda, double eps, int32_t tau_cap)
+{
+    double w = 1.0 / (double)ds + 1.0 / (double)dt;
+    double rhs = (eps / 2.0) * (1.0 - lambda);
+    double p = lambda;
+    int32_t tau = 0;
+    while (w * p > rhs && tau < tau_cap) {
+        p = p * lambda;
+        tau += 1;
+    }
+    return tau;
+}
+
+/* NWalks: number of walk pairs so that the Monte-Carlo part of one directed
+ * estimate is within eps/4 with probability 1 - delta/(2m) (Hoeffding: each
+ * pair's statistic lies in a range of width 2*L*hmax/d_s). c is
+ * 32*ln(4m/delta)/eps^2. */
+int64_t orc_nwalks(int32_t L, double hmax, int32_t ds, double c)
+{
+    double q = ((double)L * hmax) / (double)ds;
+    double x = c * q * q;
+    if (!(x < 4.0e18)) return -1;
+    int64_t r = (int64_t)ceil(x);
+    return r < 1 ? 1 : r;
+}
+
+double orc_cconst(double eps, double delta, int64_t m)
+{
+    return 32.0 * log(4.0 * (double)m / delta) / (eps * eps);
+}
+
+typedef struct {
+    int32_t *tau;    /* [nnz] per directed edge (CSR position) */
+    int32_t *ttau;   /* [nnz] tilde-tau of the edge's source */
+    int64_t *nreq;   /* [nnz] walk pairs */
+    double *D;       /* [nnz] deterministic part sum_{l<=min(ttau,tau)} (h_l(s)-h_l(t)) */
+    double *MC;      /* [nnz] sum over pairs of X_k */
+    int64_t *vis0;   /* [nnz] walk positions from s landing in supp(h_ttau) */
+    int64_t *vis1;   /* [nnz] walk positions from t landing in supp(h_ttau) */
+    double *g;       /* [nnz] directed estimate g(s,t) */
+} orc_edge_out;
+
+/* Per-source part of Alg. 1 (its outer loop body) for source s: push levels
+ * while the support volume is below the walks still needed, then the walk
+ * pairs for the directed edges s->t that are wanted (want[e] != 0). */
+static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                          int32_t s, double lambda, double eps, double c, int32_t tau_cap,
+                          int32_t tilde_tau_max, int32_t push_all, uint32_t seed,
+                          uint32_t G, uint32_t S, const uint8_t *want, orc_edge_out *o,
+                          double *hcur, double *hnext)
+{
+    int32_t e0 = row_ptr[s], e1 = row_ptr[s + 1];
+    int32_t ds = e1 - e0;
+    int32_t maxtau = 0;
+    for (int32_t e = e0; e < e1; ++e) {
+        int32_t t = col_idx[e];
+        int32_t dt = row_ptr[t + 1] - row_ptr[t];
+        o->tau[e] = orc_tau(ds, dt, lambda, eps, tau_cap);
+        if (o->tau[e] > maxtau) maxtau = o->tau[e];
+        o->D[e] = 0.0;
+    }
+    for (int32_t x = 0; x < n; ++x) hcur[x] = 0.0;
+    hcur[s] = 1.0; /* p_0(., v_i) = e_{v_i} */
+    int32_t l = 0;
+    double hmax = 0.0;
+    for (;;) {
+        /* support volume and maximum of p_l */
+        int64_t vol = 0;
+        hmax = 0.0;
+        for (int32_t x = 0; x < n; ++x) {
+            if (hcur[x] != 0.0) {
+                vol += row_ptr[x + 1] - row_ptr[x];
+                if (hcur[x] > hmax) hmax = hcur[x];
+            }
+        }
+        /* deterministic terms of level l */
+        for (int32_t e = e0; e < e1; ++e) {
+            if (l <= o->tau[e]) o->D[e] += hcur[s] - hcur[col_idx[e]];
+        }
+        /* walks still needed if the push stopped here */
+        int64_t need = 0;
+        for (int32_t e = e0; e < e1; ++e) {
+            if (o->tau[e] > l) {
+                int64_t nw = orc_nwalks(o->tau[e] - l, hmax, ds, c);
+                if (nw < 0) return -3;
+                need += nw;
+            }
+        }
+        int stop;
+        if (push_all)
+            stop = (l >= maxtau);
+        else
+            stop = !(vol < need);
+        if (tilde_tau_max >= 0 && l >= tilde_tau_max) stop = 1;
+        if (stop) break;
+        /* one more level: p_{l+1}(x) = (sum_{y in Gamma(x)} p_l(y)) / d(x) */
+        for (int32_t x = 0; x < n; ++x) {
+            double acc = 0.0;
+            for (int32_t i = row_ptr[x]; i < row_ptr[x + 1]; ++i) acc += hcur[col_idx[i]];
+            int32_t dx = row_ptr[x + 1] - row_ptr[x];
+            hnext[x] = dx > 0 ? acc / (double)dx : 0.0;
+        }
+        double *tmp = hcur;
+        hcur = hnext;
+        hnext = tmp;
+        l += 1;
+    }
+    int32_t ttau = l;
+    for (int32_t e = e0; e < e1; ++e) {
+        o->ttau[e] = ttau;
+        o->nreq[e] = 0;
+        o->MC[e] = 0.0;
+        o->vis0[e] = 0;
+        o->vis1[e] = 0;
+        if (!want[e]) continue;
+        int32_t t = col_idx[e];
+        double g = o->D[e] / (double)ds;
+        int32_t L = o->tau[e] - ttau;
+        if (L > 0) {
+            int64_t nr = orc_nwalks(L, hmax, ds, c);
+            if (nr < 0) return -3;
+            o->nreq[e] = nr;
+            double mc = 0.0;
+            for (int64_t k = 0; k < nr; ++k) {
+                /* one walk from s (side 0) and one from t (side 1), as in the
+                 * inner loop of Alg. 1 */
+                double sum[2];
+                for (int side = 0; side < 2; ++side) {
+                    uint32_t khi, klo;
+                    orc_walk_key(seed, (uint32_t)s, (uint32_t)t, (uint32_t)side, (uint64_t)k, G, S,
+                                 &khi, &klo);
+                    int32_t cur = side == 0 ? s : t;
+                    double acc = 0.0;
+                    int64_t hits = 0;
+                    for (int32_t b = 1; b <= L; ++b) {
+                        cur = orc_step(row_ptr, col_idx, cur, (uint32_t)b, khi, klo);
+                        acc += hcur[cur];
+                        hits += hcur[cur] != 0.0;
+                    }
+                    sum[side] = acc;
+                    if (side == 0)
+                        o->vis0[e] += hits;
+                    else
+                        o->vis1[e] += hits;
+                }
+                double X = sum[0] - sum[1];
+                mc += X;
+                g += X / ((double)nr * (double)ds);
+            }
+            o->MC[e] = mc;
+        }
+        o->g[e] = g;
+    }
+    return 0;
+}
+
+/* Alg. 1 driver.  If query == NULL all edges are estimated and sc_out[i] is
+ * the estimate of the i-th canonical edge (u < v, lexicographic); otherwise
+ * sc_out[j] is the estimate of query edge j = (query[2j], query[2j+1]).
+ * Per-directed-edge diagnostics go to the arrays of `o` (may be NULL). */
+int32_t orc_aesc(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, double eps,
+                 double delta, double lambda, uint32_t seed, uint32_t G, uint32_t S,
+                 int32_t tau_cap, int32_t tilde_tau_max, int32_t push_all,
+                 const int32_t *query, int64_t q, double *sc_out,
+                 int32_t *tau, int32_t *ttau, int64_t *nreq, double *D, double *MC,
+                 int64_t *vis0, int64_t *vis1, double *gout, int32_t nthreads)
+{
+    int64_t nnz = row_ptr[n];
+    int64_t m = nnz / 2;
+    double c = orc_cconst(eps, delta, m);
+    orc_edge_out o;
+    int own = 0;
+    if (!tau) {
+        own = 1;
+        tau = (int32_t *)malloc(sizeof(int32_t) * nnz);
+        ttau = (int32_t *)malloc(sizeof(int32_t) * nnz);
+        nreq = (int64_t *)malloc(sizeof(int64_t) * nnz);
+        D = (double *)malloc(sizeof(double) * nnz);
+        MC = (double *)malloc(sizeof(double) * nnz);
+        vis0 = (int64_t *)malloc(sizeof(int64_t) * nnz);
+        vis1 = (int64_t *)malloc(sizeof(int64_t) * nnz);
+        gout = (double *)malloc(sizeof(double) * nnz);
+    }
+    o.tau = tau; o.ttau = ttau; o.nreq = nreq; o.D = D; o.MC = MC;
+    o.vis0 = vis0; o.vis1 = vis1; o.g = gout;
+    uint8_t *want = (uint8_t *)calloc((size_t)nnz, 1);
+    uint8_t *srcw = (uint8_t *)calloc((size_t)n, 1);
+    int32_t rc = 0;
+    if (query == NULL) {
+        memset(want, 1, (size_t)nnz);
+        memset(srcw, 1, (size_t)n);
+    } else {
+        for (int64_t j = 0; j < q && rc == 0; ++j) {
+            int32_t u = query[2 * j], v = query[2 * j + 1];
+            int32_t euv = -1, evu = -1;
+            if (u < 0 || v < 0 || u >= n || v >= n) { rc = -1; break; }
+            for (int32_t i = row_ptr[u]; i < row_ptr[u + 1]; ++i) if (col_idx[i] == v) euv = i;
+            for (int32_t i = row_ptr[v]; i < row_ptr[v + 1]; ++i) if (col_idx[i] == u) evu = i;
+            if (euv < 0 || evu < 0) { rc = -1; break; }
+            want[euv] = want[evu] = 1;
+            srcw[u] = srcw[v] = 1;
+        }
+    }
+    if (rc == 0) {
+#ifdef _OPENMP
+        if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+        {
+            double *ha = (double *)malloc(sizeof(double) * (size_t)n);
+            double *hb = (double *)malloc(sizeof(double) * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int32_t s = 0; s < n; ++s) {
+                if (!srcw[s]) continue;
+                int32_t r = orc_source(row_ptr, col_idx, n, s, lambda, eps, c, tau_cap,
+                                       tilde_tau_max, push_all, seed, G, S, want, &o, ha, hb);
+                if (r != 0) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+                    rc = r;
+                }
+            }
+            free(ha);
+            free(hb);
+        }
+    }
+    if (rc == 0) {
+        /* final combine: s(e_ij) = g(v_i, v_j) + g(v_j, v_i) */
+        if (query == NULL) {
+            int64_t i = 0;
+            for (int32_t u = 0; u < n; ++u) {
+                for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    int32_t v = col_idx[e];
+                    if (v <= u) continue;
+                    int32_t evu = -1;
+                    for (int32_t f = row_ptr[v]; f < row_ptr[v + 1]; ++f) if (col_idx[f] == u) evu = f;
+                    sc_out[i++] = o.g[e] + o.g[evu];
+                }
+            }
+        } else {
+            for (int64_t j = 0; j < q; ++j) {
+                int32_t u = query[2 * j], v = query[2 * j + 1];
+                int32_t euv = -1, evu = -1;
+                for (int32_t i = row_ptr[u]; i < row_ptr[u + 1]; ++i) if (col_idx[i] == v) euv = i;
+                for (int32_t i = row_ptr[v]; i < row_ptr[v + 1]; ++i) if (col_idx[i] == u) evu = i;
+                sc_out[j] = o.g[euv] + o.g[evu];
+            }
+        }
+    }
+    free(want);
+    free(srcw);
+    if (own) {
+        free(tau); free(ttau); free(nreq); free(D); free(MC); free(vis0); free(vis1); free(gout);
+    }
+    return rc;
+}
+
+/* Exported for the tests: the c constant and the NWalks count as the oracle
+ * evaluates them. */
+double orc_cconst_export(double eps, double delta, int64_t m) { return orc_cconst(eps, delta, m); }
+int64_t orc_nwalks_export(int32_t L, double hmax, int32_t ds, double c) { return orc_nwalks(L, hmax, ds, c); }
+int32_t orc_tau_export(int32_t ds, int32_t dt, double lambda, double eps, int32_t tau_cap)
+{
+    return orc_tau(ds, dt, lambda, eps, tau_cap);
+}

@@ -1,0 +1,111 @@
+"""Pins for the oracle's hash, neighbour choice and walk keys (Sec. 3.1, Eq. (5), Sec. 3.3).
+
+No published MurmurHash2 test vectors are available offline, so the hash is
+pinned by properties its definition fixes: the empty message with seed 0
+hashes to 0, every step of the mixing is invertible (so for a fixed prefix the
+last 32-bit word maps bijectively to the output), strict avalanche and
+uniformity.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+
+
+def test_empty_message_seed_zero(orc):
+    # h = seed ^ len = 0, and the final avalanche maps 0 to 0
+    assert orc.murmur2(b"", 0) == 0
+
+
+def test_byte_form_equals_word_form(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        w = rng.integers(0, 2**32, size=4, dtype=np.uint64).astype(np.uint32)
+        seed = int(rng.integers(0, 2**32))
+        assert orc.hash_words(w, seed) == orc.murmur2(w.astype("<u4").tobytes(), seed)
+
+
+def test_last_word_bijective(orc):
+    # for a fixed first word and seed, the 2^20 distinct second words give 2^20 distinct
+    # hashes; a random function would collide ~128 times
+    b = np.arange(1 << 20, dtype=np.uint32) * np.uint32(2654435761)
+    a = np.full(b.size, 12345, dtype=np.uint32)
+    h = orc.hash2_batch(a, b, 0xDEADBEEF)
+    assert np.unique(h).size == b.size
+
+
+def test_strict_avalanche(orc):
+    rng = np.random.default_rng(2)
+    N = 8000
+    a = rng.integers(0, 2**32, size=N, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, size=N, dtype=np.uint64).astype(np.uint32)
+    seed = 977
+    h0 = orc.hash2_batch(a, b, seed)
+    for word in range(2):
+        for bit in range(32):
+            a1, b1 = a.copy(), b.copy()
+            if word == 0:
+                a1 ^= np.uint32(1 << bit)
+            else:
+                b1 ^= np.uint32(1 << bit)
+            diff = orc.hash2_batch(a1, b1, seed) ^ h0
+            frac = np.unpackbits(diff.view(np.uint8)).reshape(N, 32).mean(axis=0)
+            assert np.all(np.abs(frac - 0.5) < 0.05), (word, bit, frac.min(), frac.max())
+
+
+def test_uniform_top_bits(orc):
+    v = np.arange(1 << 18, dtype=np.uint32)
+    h = orc.hash2_batch(v, np.full(v.size, 7, dtype=np.uint32), 42)
+    counts = np.bincount(h >> 24, minlength=256)
+    exp = v.size / 256
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < 400  # 255 dof: mean 255, sd ~22.6
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 7, 10, 1000, 64606, (1 << 31) + 1, (1 << 32) - 1])
+def test_choice_exact_partition(orc, d):
+    # k(u) = floor(u d / 2^32) is non-decreasing, k(0) = 0, k(2^32-1) = d-1, and the first
+    # u with k(u) >= j is ceil(j 2^32 / d); together these fix the exact count of u per k:
+    # ceil((j+1) 2^32/d) - ceil(j 2^32/d).
+    assert orc.choice(0, d) == 0
+    assert orc.choice((1 << 32) - 1, d) == d - 1
+    js = range(1, d) if d < 2000 else np.random.default_rng(d % 1000).integers(1, d, 300)
+    for j in js:
+        j = int(j)
+        first = (j * (1 << 32) + d - 1) // d
+        assert orc.choice(first, d) == j
+        assert orc.choice(first - 1, d) == j - 1
+    rng = np.random.default_rng(3)
+    us = np.sort(rng.integers(0, 1 << 32, size=400, dtype=np.uint64))
+    ks = [orc.choice(int(u), d) for u in us]
+    assert all(0 <= k < d for k in ks)
+    assert all(x <= y for x, y in zip(ks, ks[1:]))
+
+
+def test_walk_key_schedule(orc):
+    # G = 1: key_lo = 0 and each walk index has its own key_hi
+    his = {orc.walk_key(1, 5, 0, 0, k, 1, 0)[0] for k in range(1000)}
+    assert len(his) == 1000
+    assert all(orc.walk_key(1, 5, 0, 0, k, 1, 0)[1] == 0 for k in range(10))
+    # G = 64, S = 20: members of a group share key_hi, key_lo = r << S
+    for k in range(200):
+        hi, lo = orc.walk_key(9, 3, 4, 1, k, 64, 20)
+        hi0, _ = orc.walk_key(9, 3, 4, 1, (k // 64) * 64, 64, 20)
+        assert hi == hi0 and lo == (k % 64) << 20
+    # address words and the seed all enter the key
+    base = orc.walk_key(1, 3, 4, 0, 0)[0]
+    assert base != orc.walk_key(1, 3, 4, 1, 0)[0]
+    assert base != orc.walk_key(1, 4, 3, 0, 0)[0]
+    assert base != orc.walk_key(2, 3, 4, 0, 0)[0]
+
+
+def test_walk_paths_follow_edges(orc):
+    g = graphgen.largest_component(graphgen.er_gnm(200, 700, 4))
+    adj = [set(g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]].tolist()) for x in range(g.n)]
+    for k in range(300):
+        hi, lo = orc.walk_key(3, k % g.n, 0, 0, k)
+        p = orc.walk_path(g, k % g.n, 20, hi, lo)
+        assert p[0] == k % g.n
+        for a, b in zip(p[:-1], p[1:]):
+            assert b in adj[a]
+        assert np.array_equal(p, orc.walk_path(g, k % g.n, 20, hi, lo))
