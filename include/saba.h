@@ -1,0 +1,186 @@
+/*
+ * saba.h -- C-ABI of the MI355X random-bouquet walk and spanning-centrality
+ * library (libsaba.so, HIP for gfx950).
+ *
+ * The library implements, on one GPU:
+ *   - random-walk generation on an undirected int32 CSR graph with the
+ *     hash-based neighbour choice of Eq. (5) and the grouping of walks into
+ *     bouquets (Sec. 3.2-3.3, Alg. 2 and Alg. 3);
+ *   - the TGT+ all-edges spanning-centrality estimator (Alg. 1) fed by those
+ *     walks, for all edges or for a query edge set.
+ *
+ * Conventions shared by every call:
+ *   - Return value: SABA_OK (0) or a negative SABA_E_* code.  No exception or
+ *     abort crosses the ABI.  saba_last_error() then holds a message for the
+ *     calling thread.
+ *   - Pointers named d_* are device pointers (HIP device memory of the current
+ *     device) owned by the caller.  Every other pointer is a host pointer.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it.  Calls that must read device results on the host
+ *     (the estimator's level loop, statistics) synchronise that stream.
+ *   - A graph handle may be used by one stream at a time.
+ *   - Results depend only on (graph, parameters): bouquet width, launch shape
+ *     and batching never change them.
+ */
+#ifndef SABA_H
+#define SABA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SABA_ABI_VERSION 1
+
+/* status codes */
+#define SABA_OK 0
+#define SABA_E_INVALID (-1)      /* an argument is out of range or NULL where required */
+#define SABA_E_NOMEM (-2)        /* host or device allocation failed */
+#define SABA_E_HIP (-3)          /* a HIP runtime call failed */
+#define SABA_E_GRAPH (-4)        /* the CSR arrays are not a canonical undirected graph */
+#define SABA_E_DISCONNECTED (-5) /* the estimator needs a connected graph */
+#define SABA_E_BIPARTITE (-6)    /* the estimator needs a non-bipartite graph (lambda < 1) */
+#define SABA_E_NOT_EDGE (-7)     /* a query pair is not an edge of the graph */
+#define SABA_E_OVERFLOW (-8)     /* a walk count exceeds the 64-bit range */
+#define SABA_E_NODEVICE (-9)     /* no usable gfx950 device */
+
+/* saba_graph_create flags */
+#define SABA_DEVICE_PTRS 1u /* row_ptr / col_idx are device pointers */
+#define SABA_TRUSTED 2u     /* skip CSR validation */
+
+/* walk execution modes (results are identical in both) */
+#define SABA_WALK_NAIVE 0   /* one lane per walk, walks in the order the sources are given */
+#define SABA_WALK_BOUQUET 1 /* walks of one start vertex run side by side in a wavefront */
+
+typedef struct saba_graph saba_graph;
+
+typedef struct {
+    int32_t n;          /* vertices */
+    int64_t nnz;        /* directed entries = 2m */
+    int64_t m;          /* undirected edges */
+    int32_t d_max;      /* maximum degree */
+    int32_t n_isolated; /* vertices of degree 0 */
+    int32_t connected;  /* 1 / 0 */
+    int32_t bipartite;  /* 1 / 0 */
+} saba_graph_info_t;
+
+typedef struct {
+    int64_t walks;            /* walks generated */
+    int64_t walk_steps;       /* steps taken by those walks */
+    int64_t push_edge_visits; /* adjacency entries read by the estimator's deterministic levels */
+    int64_t sources;          /* sources processed by the estimator */
+    int64_t batches;          /* source batches */
+    int32_t max_tau;          /* largest truncation length */
+    int32_t max_ttau;         /* largest deterministic level count */
+    int32_t warnings;         /* bit 0: some tau was capped at tau_cap */
+    int32_t reserved;
+    double kernel_ms;         /* time of the dominant kernel (walk kernel), when timing was asked */
+    double total_ms;          /* time of the whole call on its stream, when timing was asked */
+} saba_stats;
+
+typedef struct {
+    int64_t n_walks;         /* number of walks */
+    int32_t length;          /* steps per walk L >= 0 (positions 1..L are counted) */
+    uint32_t seed;           /* walk seed */
+    uint32_t group;          /* G >= 1: walks per key group (1 = independent walks) */
+    uint32_t spread;         /* S: bit offset of the lane index inside key_lo; G << S <= 2^32 */
+    int32_t mode;            /* SABA_WALK_NAIVE or SABA_WALK_BOUQUET */
+    int32_t time_kernels;    /* nonzero: fill saba_stats kernel_ms / total_ms (synchronises) */
+    const int32_t *d_sources; /* [n_walks] start vertex of each walk (device) */
+} saba_walk_params;
+
+typedef struct {
+    double eps;            /* absolute error target (0 < eps) */
+    double delta;          /* failure probability (0 < delta < 1) */
+    double lambda;         /* max(|lambda_2|, |lambda_n|) of D^-1/2 A D^-1/2, 0 < lambda < 1 */
+    uint32_t seed;         /* walk seed */
+    uint32_t group;        /* G >= 1 walk key grouping (1 = independent walks) */
+    uint32_t spread;       /* S, as in saba_walk_params */
+    int32_t tau_cap;       /* upper bound on tau (<= 0: 4096) */
+    int32_t tilde_tau_max; /* upper bound on deterministic levels (-1: none; 0: walks only) */
+    int32_t push_all;      /* nonzero: deterministic levels up to tau, no walks */
+    int32_t batch_sources; /* sources per batch (0: chosen from mem_budget); no effect on results */
+    int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
+    int64_t mem_budget;    /* bytes of per-batch scratch (0: 8 GiB or 40% of free memory) */
+} saba_aesc_params;
+
+/* ABI version (SABA_ABI_VERSION). */
+int saba_version(void);
+
+/* Message of the last failing call on this thread ("" if none). Valid until the next call. */
+const char *saba_last_error(void);
+
+/*
+ * Upload a graph (Sec. 2 notation: Gamma(v) is row v of the CSR, d(v) its length).
+ *   row_ptr[n+1], col_idx[nnz]: int32 CSR, host arrays unless SABA_DEVICE_PTRS.
+ *   The graph must be canonical: row_ptr[0] = 0, row_ptr[n] = nnz, rows strictly
+ *   ascending (no duplicates), no self-loops, symmetric.  Checked unless
+ *   SABA_TRUSTED (SABA_E_GRAPH on failure).
+ * The library copies the arrays into device memory it owns; the caller may free its
+ * arrays when the call returns.  *out receives the handle (NULL on failure).
+ */
+int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz,
+                      uint32_t flags, void *stream, saba_graph **out);
+
+/* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
+int saba_graph_destroy(saba_graph *g);
+
+/* Fill *out with the graph's sizes and properties. */
+int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
+
+/*
+ * Random-walk generation (Alg. 2 / Alg. 3, neighbour choice of Eq. (5), bouquet
+ * arrangement of Sec. 3.3), the synthetic benchmark of Sec. 5.4.
+ *   Walk j starts at d_sources[j] (which must not be isolated).  The walks that
+ *   start at a vertex s are numbered r = 0, 1, ... and walk r of s draws its
+ *   choices from the key of address (s, 0, 0) and index r under (seed, G, S), so
+ *   the result depends only on the multiset of sources.
+ *   d_endpoint[n] (int64): walks ending at each vertex after L steps.
+ *   d_visits[n] (int64): visits at positions 1..L.
+ *   Both outputs are overwritten (the library clears them on `stream`).
+ *   stats may be NULL.
+ */
+int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, int64_t *d_visits,
+               saba_stats *stats, void *stream);
+
+/*
+ * All-edges spanning centrality (Alg. 1, TGT+), SC(e) as defined in Sec. 2.1,
+ * estimated to within eps with probability 1 - delta when group == 1.
+ *   d_sc[m] (double): estimate of the i-th undirected edge in canonical order
+ *   (u < v, lexicographic).  Errors: SABA_E_DISCONNECTED, SABA_E_BIPARTITE,
+ *   SABA_E_INVALID (parameters), SABA_E_OVERFLOW (walk counts).
+ */
+int saba_aesc(saba_graph *g, const saba_aesc_params *p, double *d_sc, saba_stats *stats,
+              void *stream);
+
+/*
+ * Spanning centrality of a query edge set (Alg. 1 restricted to the sources
+ * and directed edges the queries need).
+ *   d_edges[2q] (int32, device): pairs (u, v) in either orientation; each must be
+ *   an edge (SABA_E_NOT_EDGE).  d_sc[q] (double): the estimate of each pair,
+ *   identical to saba_aesc's entry for the same edge and parameters.
+ */
+int saba_aesc_query(saba_graph *g, const saba_aesc_params *p, const int32_t *d_edges, int64_t q,
+                    double *d_sc, saba_stats *stats, void *stream);
+
+/*
+ * Per-directed-edge internals of saba_aesc (for parity checks), indexed by CSR
+ * position e (the edge s -> col_idx[e] of row s).  Any output may be NULL.
+ *   d_tau[nnz] int32: truncation length; d_ttau[nnz] int32: deterministic levels of s;
+ *   d_nreq[nnz] int64: walk pairs; d_D[nnz] double: deterministic part
+ *   sum_{l <= min(ttau, tau)} (h_l(s) - h_l(t)); d_MC[nnz] double: sum over pairs of the
+ *   walk statistic; d_vis0 / d_vis1[nnz] int64: walk positions of the walks from s / t
+ *   that land where h_ttau is nonzero; d_g[nnz] double: directed estimate g(s, t).
+ *   d_sc[m] as in saba_aesc (may be NULL).
+ */
+int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc, int32_t *d_tau,
+                         int32_t *d_ttau, int64_t *d_nreq, double *d_D, double *d_MC,
+                         int64_t *d_vis0, int64_t *d_vis1, double *d_g, saba_stats *stats,
+                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SABA_H */

@@ -146,7 +146,8 @@ int32_t orc_walk_path(const int32_t *row_ptr, const int32_t *col_idx, int32_t st
 }
 
 /* Synthetic random-walk benchmark (Sec. 5.4): walks from the given start
- * vertices, counting vertex visits at positions 1..L and endpoints at L.
+ * vertices, counting vertex visits at positions 1..L and endpoints at
+ * position L (the start itself when L = 0).
  * Walk j starting at s is the r-th walk of s in list order (r counts the
  * earlier list entries with the same start); its key is that of address
  * (s, 0, 0) and index r. */
@@ -188,12 +189,10 @@ int32_t orc_walks_histogram(const int32_t *row_ptr, const int32_t *col_idx, int3
 #endif
             visits[cur] += 1;
         }
-        if (L > 0) {
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
-            endpoint[cur] += 1;
-        }
+        endpoint[cur] += 1;
     }
     free(rank);
     free(seen);

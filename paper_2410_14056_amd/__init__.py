@@ -1,0 +1,18 @@
+"""MI355X (gfx950) random-bouquet walks and TGT+ spanning-centrality estimation.
+
+The computation lives in libsaba.so (HIP kernels behind the C-ABI declared in
+include/saba.h); this package is its Python binding.
+"""
+from ._binding import (  # noqa: F401
+    EXPORTS,
+    SABA_WALK_BOUQUET,
+    SABA_WALK_NAIVE,
+    SabaError,
+    SabaGraph,
+    WalkResult,
+    aesc,
+    aesc_edge_stats,
+    aesc_query,
+    load,
+    walks,
+)

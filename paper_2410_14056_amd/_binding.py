@@ -1,0 +1,236 @@
+"""ctypes binding of libsaba.so: argument marshalling only.
+
+Every computation happens in the HIP library; torch provides device memory and
+streams.  Importing this module fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsaba.so")
+
+SABA_OK = 0
+SABA_DEVICE_PTRS = 1
+SABA_TRUSTED = 2
+SABA_WALK_NAIVE = 0
+SABA_WALK_BOUQUET = 1
+
+_ERRORS = {
+    -1: "SABA_E_INVALID", -2: "SABA_E_NOMEM", -3: "SABA_E_HIP", -4: "SABA_E_GRAPH",
+    -5: "SABA_E_DISCONNECTED", -6: "SABA_E_BIPARTITE", -7: "SABA_E_NOT_EDGE",
+    -8: "SABA_E_OVERFLOW", -9: "SABA_E_NODEVICE",
+}
+
+
+class SabaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = _ERRORS.get(code, str(code))
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("d_max", ctypes.c_int32), ("n_isolated", ctypes.c_int32),
+                ("connected", ctypes.c_int32), ("bipartite", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("walks", ctypes.c_int64), ("walk_steps", ctypes.c_int64),
+                ("push_edge_visits", ctypes.c_int64), ("sources", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("max_tau", ctypes.c_int32),
+                ("max_ttau", ctypes.c_int32), ("warnings", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class WalkParams(ctypes.Structure):
+    _fields_ = [("n_walks", ctypes.c_int64), ("length", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("group", ctypes.c_uint32), ("spread", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32), ("d_sources", ctypes.c_void_p)]
+
+
+class AescParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("delta", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("seed", ctypes.c_uint32), ("group", ctypes.c_uint32), ("spread", ctypes.c_uint32),
+                ("tau_cap", ctypes.c_int32), ("tilde_tau_max", ctypes.c_int32),
+                ("push_all", ctypes.c_int32), ("batch_sources", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32), ("mem_budget", ctypes.c_int64)]
+
+
+# every symbol the header declares
+EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_destroy",
+           "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query", "saba_aesc_edge_stats"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsaba.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.saba_version.restype = ctypes.c_int
+    L.saba_last_error.restype = ctypes.c_char_p
+    L.saba_graph_create.argtypes = [P, P, i32, i64, u32, P, ctypes.POINTER(P)]
+    L.saba_graph_destroy.argtypes = [P]
+    L.saba_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
+    L.saba_walks.argtypes = [P, ctypes.POINTER(WalkParams), P, P, ctypes.POINTER(Stats), P]
+    L.saba_aesc.argtypes = [P, ctypes.POINTER(AescParams), P, ctypes.POINTER(Stats), P]
+    L.saba_aesc_query.argtypes = [P, ctypes.POINTER(AescParams), P, i64, P, ctypes.POINTER(Stats), P]
+    L.saba_aesc_edge_stats.argtypes = [P, ctypes.POINTER(AescParams), P, P, P, P, P, P, P, P, P,
+                                       ctypes.POINTER(Stats), P]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SABA_OK:
+        msg = load().saba_last_error().decode(errors="replace")
+        raise SabaError(rc, msg)
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class SabaGraph:
+    """A graph resident in device memory (saba_graph_create / saba_graph_destroy)."""
+
+    def __init__(self, row_ptr, col_idx, trusted: bool = False, stream=None):
+        lib = load()
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        n = rp.size - 1
+        h = ctypes.c_void_p()
+        flags = SABA_TRUSTED if trusted else 0
+        _check(lib.saba_graph_create(rp.ctypes.data_as(ctypes.c_void_p),
+                                     ci.ctypes.data_as(ctypes.c_void_p), n, ci.size, flags,
+                                     _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.nnz = ci.size
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        return cls(g.row_ptr, g.col_idx, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = GraphInfo()
+        _check(load().saba_graph_info(self._h, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in GraphInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().saba_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class WalkResult:
+    endpoint: torch.Tensor
+    visits: torch.Tensor
+    stats: dict
+
+
+def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group: int = 1,
+          spread: int = 0, mode: int = SABA_WALK_BOUQUET, time_kernels: bool = False,
+          endpoint: torch.Tensor | None = None, visits: torch.Tensor | None = None,
+          stream=None) -> WalkResult:
+    """saba_walks: endpoint / visit histograms of the walks started at `sources` (int32, device)."""
+    assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
+    dev = sources.device
+    if endpoint is None:
+        endpoint = torch.empty(graph.n, dtype=torch.int64, device=dev)
+    if visits is None:
+        visits = torch.empty(graph.n, dtype=torch.int64, device=dev)
+    p = WalkParams(sources.numel(), int(length), seed & 0xFFFFFFFF, int(group), int(spread),
+                   int(mode), int(bool(time_kernels)), sources.data_ptr())
+    st = Stats()
+    _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
+                             ctypes.byref(st), _stream_ptr(stream)))
+    return WalkResult(endpoint, visits, st.as_dict())
+
+
+def _aesc_params(eps, lam, seed, delta=0.01, group=1, spread=0, tau_cap=0, tilde_tau_max=-1,
+                 push_all=False, batch_sources=0, time_kernels=False, mem_budget=0):
+    return AescParams(float(eps), float(delta), float(lam), seed & 0xFFFFFFFF, int(group),
+                      int(spread), int(tau_cap), int(tilde_tau_max), int(bool(push_all)),
+                      int(batch_sources), int(bool(time_kernels)), int(mem_budget))
+
+
+def aesc(graph: SabaGraph, eps: float, lam: float, seed: int, device="cuda", stream=None, **kw):
+    """saba_aesc: spanning-centrality estimates of all edges in canonical order (double, device)."""
+    p = _aesc_params(eps, lam, seed, **kw)
+    sc = torch.empty(graph.nnz // 2, dtype=torch.float64, device=device)
+    st = Stats()
+    _check(load().saba_aesc(graph.handle, ctypes.byref(p), _ptr(sc), ctypes.byref(st),
+                            _stream_ptr(stream)))
+    return sc, st.as_dict()
+
+
+def aesc_query(graph: SabaGraph, edges: torch.Tensor, eps: float, lam: float, seed: int,
+               stream=None, **kw):
+    """saba_aesc_query: estimates of the query edges (int32 [q, 2], device)."""
+    assert edges.is_cuda and edges.dtype == torch.int32 and edges.is_contiguous()
+    q = edges.numel() // 2
+    p = _aesc_params(eps, lam, seed, **kw)
+    sc = torch.empty(q, dtype=torch.float64, device=edges.device)
+    st = Stats()
+    _check(load().saba_aesc_query(graph.handle, ctypes.byref(p), _ptr(edges), q, _ptr(sc),
+                                  ctypes.byref(st), _stream_ptr(stream)))
+    return sc, st.as_dict()
+
+
+def aesc_edge_stats(graph: SabaGraph, eps: float, lam: float, seed: int, device="cuda",
+                    stream=None, **kw):
+    """saba_aesc_edge_stats: per-directed-edge internals plus the all-edges estimates."""
+    p = _aesc_params(eps, lam, seed, **kw)
+    nnz = graph.nnz
+    out = {
+        "sc": torch.empty(nnz // 2, dtype=torch.float64, device=device),
+        "tau": torch.empty(nnz, dtype=torch.int32, device=device),
+        "ttau": torch.empty(nnz, dtype=torch.int32, device=device),
+        "nreq": torch.empty(nnz, dtype=torch.int64, device=device),
+        "D": torch.empty(nnz, dtype=torch.float64, device=device),
+        "MC": torch.empty(nnz, dtype=torch.float64, device=device),
+        "vis0": torch.empty(nnz, dtype=torch.int64, device=device),
+        "vis1": torch.empty(nnz, dtype=torch.int64, device=device),
+        "g": torch.empty(nnz, dtype=torch.float64, device=device),
+    }
+    st = Stats()
+    _check(load().saba_aesc_edge_stats(
+        graph.handle, ctypes.byref(p), _ptr(out["sc"]), _ptr(out["tau"]), _ptr(out["ttau"]),
+        _ptr(out["nreq"]), _ptr(out["D"]), _ptr(out["MC"]), _ptr(out["vis0"]), _ptr(out["vis1"]),
+        _ptr(out["g"]), ctypes.byref(st), _stream_ptr(stream)))
+    return out, st.as_dict()

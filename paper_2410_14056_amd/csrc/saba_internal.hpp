@@ -1,0 +1,147 @@
+// Internal declarations of libsaba: the graph handle, device scratch buffers,
+// error reporting and the device functions of the walk sampler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "saba.h"
+
+namespace saba {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+void clear_error();
+
+#define SABA_HIP_TRY(expr)                                                                   \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess) {                                                              \
+            ::saba::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));            \
+            return SABA_E_HIP;                                                               \
+        }                                                                                    \
+    } while (0)
+
+#define SABA_TRY(expr)                 \
+    do {                               \
+        int _rc = (expr);              \
+        if (_rc != SABA_OK) return _rc; \
+    } while (0)
+
+// Grow-only device buffer owned by a graph handle.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t want);
+    void release();
+    template <class T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Device-resident graph.  vrec[v] = (row start, degree) so one 8-byte gather gives
+// both; rev[e] is the CSR position of the reverse entry of e; canon[i] is the CSR
+// position of the i-th undirected edge in canonical (u < v, lexicographic) order.
+struct Graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t d_max = 0;
+    int32_t n_isolated = 0;
+    int32_t connected = 0;
+    int32_t bipartite = 0;
+    std::vector<int32_t> h_row_ptr, h_col_idx;
+    int32_t *row_ptr = nullptr;
+    int32_t *col_idx = nullptr;
+    int2 *vrec = nullptr;
+    int32_t *rev = nullptr;
+    int32_t *canon = nullptr;
+    int32_t *row_of = nullptr;  // source vertex of each CSR entry
+    uint32_t stamp = 0;         // visit-mark generation for the estimator's level expansion
+    // reusable scratch
+    DevBuf walk_scratch[4];
+    DevBuf est[32];
+};
+
+int check_graph(const saba_graph *g);
+inline Graph *G(saba_graph *g) { return reinterpret_cast<Graph *>(g); }
+inline const Graph *G(const saba_graph *g) { return reinterpret_cast<const Graph *>(g); }
+
+// Exclusive prefix sum of int64 values on the device: out[0] = 0, out[i] = sum in[0..i).
+// out has n + 1 entries (out[n] = total).  tmp must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+int scan_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s);
+
+// ----------------------------------------------------------- device sampler
+// MurmurHash2 (32-bit) over little-endian 32-bit words: multiplier 0x5bd1e995,
+// rotation-free mixing with shift 24, seed XOR byte length, final avalanche
+// (>>13, *m, >>15).  Only whole 32-bit words occur here.
+constexpr uint32_t kMurmurM = 0x5bd1e995u;
+
+__device__ __forceinline__ uint32_t mm2_block(uint32_t h, uint32_t k) {
+    k *= kMurmurM;
+    k ^= k >> 24;
+    k *= kMurmurM;
+    h *= kMurmurM;
+    return h ^ k;
+}
+
+__device__ __forceinline__ uint32_t mm2_final(uint32_t h) {
+    h ^= h >> 13;
+    h *= kMurmurM;
+    h ^= h >> 15;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t hash_w2(uint32_t a, uint32_t b, uint32_t seed) {
+    uint32_t h = seed ^ 8u;
+    h = mm2_block(h, a);
+    h = mm2_block(h, b);
+    return mm2_final(h);
+}
+
+__device__ __forceinline__ uint32_t hash_w4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                            uint32_t seed) {
+    uint32_t h = seed ^ 16u;
+    h = mm2_block(h, a);
+    h = mm2_block(h, b);
+    h = mm2_block(h, c);
+    h = mm2_block(h, d);
+    return mm2_final(h);
+}
+
+// Key of walk index k of address (a0, a1, a2) under grouping (G, S): the walks of a
+// group share key_hi, and lane r = k mod G is written at bit S of key_lo.
+struct WalkKey {
+    uint32_t hi, lo;
+};
+
+__device__ __forceinline__ WalkKey walk_key(uint32_t seed, uint32_t a0, uint32_t a1, uint32_t a2,
+                                            uint64_t k, uint32_t G, uint32_t S) {
+    WalkKey key;
+    if (G == 1) {
+        key.hi = hash_w4(a0, a1, a2, (uint32_t)k, seed);
+        key.lo = 0u;
+    } else {
+        uint64_t grp = k / G;
+        uint32_t r = (uint32_t)(k - grp * G);
+        key.hi = hash_w4(a0, a1, a2, (uint32_t)grp, seed);
+        key.lo = r << S;
+    }
+    return key;
+}
+
+// One step (Eq. (5)): choose entry floor(u * d / 2^32) of the row of `cur`, where
+// u = Murmur2(cur | l, key_hi) XOR key_lo and l is the position being filled.
+__device__ __forceinline__ int32_t walk_step(const int2 *__restrict__ vrec,
+                                             const int32_t *__restrict__ col, int32_t cur,
+                                             uint32_t l, WalkKey key) {
+    int2 r = vrec[cur];
+    uint32_t u = hash_w2((uint32_t)cur, l, key.hi) ^ key.lo;
+    uint32_t k = (uint32_t)(((uint64_t)u * (uint32_t)r.y) >> 32);
+    return col[r.x + (int32_t)k];
+}
+
+}  // namespace saba
