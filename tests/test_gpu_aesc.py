@@ -1,0 +1,152 @@
+"""GPU parity of the TGT+ estimator (Alg. 1) against the oracle.
+
+Integer quantities (tau, deterministic level count, walk pairs, in-support visit counts)
+and the deterministic part D must be bit-identical; the directed estimates g, the final
+SC values and the per-edge Monte-Carlo sums agree to 1e-12 relative (the GPU sums the walk
+statistics in a fixed tree order, the oracle left to right).
+"""
+import numpy as np
+import pytest
+
+import graphgen
+from oracle import exact_sc
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def saba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_14056_amd as saba
+    saba.load()
+    return saba
+
+
+def _graph(n, m, seed):
+    g = graphgen.largest_component(graphgen.er_gnm(n, m, seed))
+    return g, graphgen.spectral_lambda(g)
+
+
+def _compare(o_gpu, o_orc, sc_gpu, sc_orc, want=None):
+    gpu = {k: v.cpu().numpy() for k, v in o_gpu.items()}
+    sel = np.ones(o_orc["tau"].size, bool) if want is None else want
+    for k in ("tau", "ttau", "nreq", "vis0", "vis1"):
+        assert np.array_equal(gpu[k][sel], o_orc[k][sel]), k
+    assert np.array_equal(gpu["D"][sel], o_orc["D"][sel]), "D"
+    np.testing.assert_allclose(gpu["g"][sel], o_orc["g"][sel], rtol=RTOL, atol=1e-15)
+    # MC sums can cancel; compare against the scale of the summed terms
+    L = np.maximum(o_orc["tau"] - o_orc["ttau"], 0)
+    scale = np.maximum(1.0, o_orc["nreq"] * L)[sel]
+    assert np.all(np.abs(gpu["MC"][sel] - o_orc["MC"][sel]) <= 1e-12 * scale)
+    np.testing.assert_allclose(sc_gpu, sc_orc, rtol=RTOL, atol=1e-15)
+
+
+CASES = [
+    # (n, m, seed, eps, kwargs)
+    (120, 500, 6, 0.15, {}),
+    (120, 500, 6, 0.15, {"group": 64, "spread": 20}),
+    (80, 260, 4, 0.3, {"tilde_tau_max": 0}),
+    (80, 260, 4, 0.2, {"push_all": True}),
+    (300, 1200, 3, 0.1, {}),
+    (60, 200, 9, 0.5, {"tilde_tau_max": 1, "group": 8, "spread": 27}),
+]
+
+
+@pytest.mark.parametrize("n,m,seed,eps,kw", CASES)
+def test_aesc_matches_oracle(saba, orc, n, m, seed, eps, kw):
+    g, lam = _graph(n, m, seed)
+    print(f"aesc parity n={g.n} m={g.m} eps={eps} {kw}", flush=True)
+    sg = saba.SabaGraph.from_graph(g)
+    o_gpu, st = saba.aesc_edge_stats(sg, eps, lam, seed=5, **kw)
+    okw = dict(kw)
+    if "group" in okw:
+        okw["G"], okw["S"] = okw.pop("group"), okw.pop("spread")
+    sc_o, o_orc = orc.aesc(g, eps, lam, seed=5, **okw)
+    _compare(o_gpu, o_orc, o_gpu["sc"].cpu().numpy(), sc_o)
+    assert st["walk_steps"] == int(np.sum(2 * o_orc["nreq"] * np.maximum(o_orc["tau"] - o_orc["ttau"], 0)))
+    sc2, _ = saba.aesc(sg, eps, lam, 5, **kw)
+    assert np.array_equal(sc2.cpu().numpy(), o_gpu["sc"].cpu().numpy())
+
+
+def test_batching_and_repeat_invariance(saba):
+    g, lam = _graph(200, 800, 12)
+    sg = saba.SabaGraph.from_graph(g)
+    ref, _ = saba.aesc(sg, 0.2, lam, 3)
+    for bsz in (1, 7, 64):
+        sc, st = saba.aesc(sg, 0.2, lam, 3, batch_sources=bsz)
+        assert np.array_equal(sc.cpu().numpy(), ref.cpu().numpy()), bsz
+        assert st["batches"] == -(-g.n // bsz)
+    again, _ = saba.aesc(sg, 0.2, lam, 3)
+    assert np.array_equal(again.cpu().numpy(), ref.cpu().numpy())
+
+
+def test_query_matches_all_edges_and_oracle(saba, orc):
+    import torch
+    g, lam = _graph(150, 600, 2)
+    sg = saba.SabaGraph.from_graph(g)
+    sc_all, _ = saba.aesc(sg, 0.12, lam, 8)
+    ce = graphgen.canonical_edges(g)
+    pick = np.random.default_rng(1).choice(g.m, 40, replace=False)
+    q = np.ascontiguousarray(ce[pick])
+    q[::2] = q[::2, ::-1]  # either orientation
+    sq, st = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.12, lam, 8)
+    assert np.array_equal(sq.cpu().numpy(), sc_all.cpu().numpy()[pick])
+    so, _ = orc.aesc(g, 0.12, lam, seed=8, query=q)
+    np.testing.assert_allclose(sq.cpu().numpy(), so, rtol=RTOL)
+    # empty query
+    e, _ = saba.aesc_query(sg, torch.zeros((0, 2), dtype=torch.int32, device="cuda"), 0.12, lam, 8)
+    assert e.numel() == 0
+
+
+def test_errors(saba):
+    import torch
+    # disconnected
+    g = graphgen.from_edges([(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)], 6)
+    with pytest.raises(saba.SabaError) as ei:
+        saba.aesc(saba.SabaGraph.from_graph(g), 0.1, 0.5, 1)
+    assert ei.value.name == "SABA_E_DISCONNECTED"
+    # bipartite (even cycle)
+    g = graphgen.from_edges([(i, (i + 1) % 8) for i in range(8)], 8)
+    with pytest.raises(saba.SabaError) as ei:
+        saba.aesc(saba.SabaGraph.from_graph(g), 0.1, 0.9, 1)
+    assert ei.value.name == "SABA_E_BIPARTITE"
+    # non-edge query, then the handle still works
+    g, lam = _graph(50, 150, 3)
+    sg = saba.SabaGraph.from_graph(g)
+    with pytest.raises(saba.SabaError) as ei:
+        saba.aesc_query(sg, torch.tensor([[0, 0]], dtype=torch.int32, device="cuda"), 0.2, lam, 1)
+    assert ei.value.name == "SABA_E_NOT_EDGE"
+    with pytest.raises(saba.SabaError):
+        saba.aesc(sg, -0.1, lam, 1)
+    a, _ = saba.aesc(sg, 0.2, lam, 1)
+    b, _ = saba.aesc(sg, 0.2, lam, 1)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_toy_graph(saba, orc):
+    g = graphgen.toy_graph()
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    sc, _ = saba.aesc(sg, 0.05, lam, 1)
+    so, _ = orc.aesc(g, 0.05, lam, seed=1)
+    np.testing.assert_allclose(sc.cpu().numpy(), so, rtol=RTOL)
+    assert np.max(np.abs(sc.cpu().numpy() - np.array([0.625, 0.625, 0.5, 0.625, 0.625]))) <= 0.05
+
+
+def test_config1_parity_and_eps(saba, orc):
+    # ER n=2000, m=8000, seed 1, largest component, eps=0.3, plain (G = 1) walks
+    g = graphgen.largest_component(graphgen.er_gnm(2000, 8000, 1))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    o_gpu, st = saba.aesc_edge_stats(sg, 0.3, lam, 1)
+    sc_o, o_orc = orc.aesc(g, 0.3, lam, seed=1)
+    _compare(o_gpu, o_orc, o_gpu["sc"].cpu().numpy(), sc_o)
+    ex = exact_sc.sc_pinv(g.row_ptr, g.col_idx, g.n)
+    err = np.abs(o_gpu["sc"].cpu().numpy() - ex)
+    print(f"config1: max err {err.max():.4g} mean {err.mean():.4g} sum {o_gpu['sc'].sum().item():.2f}"
+          f" (n-1={g.n - 1}) steps {st['walk_steps']}", flush=True)
+    assert err.max() <= 0.3
