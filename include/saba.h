@@ -77,6 +77,7 @@ typedef struct {
     int32_t reserved;
     double kernel_ms;         /* time of the dominant kernel (walk kernel), when timing was asked */
     double total_ms;          /* time of the whole call on its stream, when timing was asked */
+    double count_ms;          /* time of the histogram passes after the walk kernel, if timed */
 } saba_stats;
 
 typedef struct {

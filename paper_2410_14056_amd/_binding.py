@@ -47,7 +47,7 @@ class Stats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("max_tau", ctypes.c_int32),
                 ("max_ttau", ctypes.c_int32), ("warnings", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("count_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -1,6 +1,15 @@
 // Random-walk generation: Alg. 2 (one lane per walk) and Alg. 3 (bouquets: the
 // walks of one start vertex advance side by side in a wavefront), with the
 // neighbour choice of Eq. (5) and the keyed seed arrangement of Sec. 3.3.
+//
+// Counting.  Per-step global atomics on the visit histogram serialise on hub
+// vertices.  The bouquet path therefore counts without global atomics in the
+// hot loop: the walk kernel writes each visited vertex to a step-major visit log
+// (coalesced) and counts per block how many visits fall in each bucket of
+// 2^bsh consecutive vertex ids (LDS); a scatter pass groups the log by bucket,
+// and a histogram pass counts each bucket slice in LDS and adds the bins to the
+// int64 outputs.  All counts are integers, so the result does not depend on the
+// order of any of these steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,6 +19,11 @@
 namespace saba {
 
 constexpr int kWalkBlock = 256;
+constexpr int kMaxBucketShift = 14;      // LDS histogram of up to 16384 bins (64 KiB)
+constexpr int kMaxBuckets = 2048;        // LDS bucket counters in the walk and scatter kernels
+constexpr int64_t kLogCap = 1ll << 29;   // visit-log entries per chunk of walks
+constexpr int64_t kHistSlice = 1 << 18;  // log entries per histogram block
+constexpr int kPersistBlocks = 2048;
 
 // Counts of equal keys held by adjacent active lanes are merged, so one wavefront
 // issues one atomic per run of equal vertices instead of one per lane.
@@ -62,10 +76,10 @@ __global__ __launch_bounds__(kWalkBlock) void source_fill_kernel(const int64_t *
     }
 }
 
-// Alg. 2: one lane per walk, walks in the order the sources are given.  The rank of
-// a walk among the walks of its source is taken from a per-source counter; the set
-// of (source, rank) pairs, and so the histograms, does not depend on which walk
-// receives which rank.
+// Alg. 2: one lane per walk, walks in the order the sources are given, one global
+// atomic per visit.  The rank of a walk among the walks of its source is taken from a
+// per-source counter; the set of (source, rank) pairs, and so the histograms, does
+// not depend on which walk receives which rank.
 __global__ __launch_bounds__(kWalkBlock) void walk_naive_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int32_t *__restrict__ src,
     int64_t W, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int32_t n,
@@ -88,11 +102,9 @@ __global__ __launch_bounds__(kWalkBlock) void walk_naive_kernel(
     atomicAdd(endpoint + cur, 1ull);
 }
 
-// Alg. 3: bouquets.  Walks are taken in bucket order, so the lanes of a wavefront
-// hold consecutive walks of the same start vertex: their first gathers hit the
-// same row, lanes standing on the same vertex share one request, and equal visits
-// of adjacent lanes are merged before the atomics.
-__global__ __launch_bounds__(kWalkBlock) void walk_bouquet_kernel(
+// Alg. 3 for graphs too large for the bucketed count: bouquet order with equal visits
+// of adjacent lanes merged before the global atomics.
+__global__ __launch_bounds__(kWalkBlock) void walk_bouquet_atomic_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
     const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int32_t L,
     uint32_t seed, uint32_t G, uint32_t S, unsigned long long *__restrict__ endpoint,
@@ -115,30 +127,229 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_kernel(
     wave_merged_add(endpoint, cur, active);
 }
 
+// Alg. 3 with the bucketed count: walks w0 .. w0 + wc of the bucket order.  Walk
+// w0 + i writes its position l to vlog[(l - 1) * wc + i] and its end vertex to
+// elog[i]; the block counts its visits and ends per vertex bucket and writes the
+// counts bucket-major: cnt[b * gridDim.x + blockIdx.x].
+__global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int64_t w0,
+    int64_t wc, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int bsh, int32_t nbk,
+    int32_t *__restrict__ vlog, int32_t *__restrict__ elog, long long *__restrict__ cnt_v,
+    long long *__restrict__ cnt_e) {
+    extern __shared__ uint32_t lds_cnt[];
+    uint32_t *cv = lds_cnt, *ce = lds_cnt + nbk;
+    for (int i = threadIdx.x; i < 2 * nbk; i += kWalkBlock) lds_cnt[i] = 0;
+    __syncthreads();
+    const int64_t valid = min(wc, offs[n] - w0);
+    for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid; tile += gridDim.x) {
+        const int64_t i = tile * kWalkBlock + threadIdx.x;
+        if (i < valid) {
+            const int64_t w = w0 + i;
+            const int32_t s = bsrc[w];
+            const WalkKey key = walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S);
+            int32_t cur = s;
+            for (int32_t l = 1; l <= L; ++l) {
+                cur = walk_step(vrec, col, cur, (uint32_t)l, key);
+                __builtin_nontemporal_store(cur, vlog + (int64_t)(l - 1) * wc + i);
+                atomicAdd(cv + (cur >> bsh), 1u);
+            }
+            __builtin_nontemporal_store(cur, elog + i);
+            atomicAdd(ce + (cur >> bsh), 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += kWalkBlock) {
+        cnt_v[(int64_t)b * gridDim.x + blockIdx.x] = cv[b];
+        cnt_e[(int64_t)b * gridDim.x + blockIdx.x] = ce[b];
+    }
+}
+
+// Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order:
+// block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].
+// Block-wide exclusive scan of one value per thread (blockDim.x == kWalkBlock).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_tot) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wave_tot[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    __syncthreads();
+    return before + inc - v;
+}
+
+constexpr int kSortRows = 16;  // log rows per local sort: 16 x 256 entries
+
+// Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order.
+// Block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].  Each
+// group of 16 rows x 256 walks is first sorted by bucket in LDS, so every bucket leaves
+// the block as one contiguous run.  The walks with a valid start are
+// w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.
+__global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
+    const int32_t *__restrict__ vlog, int32_t rows, int64_t wc, const int64_t *__restrict__ offs,
+    int32_t n, int64_t w0, int bsh, int32_t nbk, const int64_t *__restrict__ pos,
+    int32_t *__restrict__ part) {
+    extern __shared__ unsigned char lds_raw[];
+    int64_t *gpos = reinterpret_cast<int64_t *>(lds_raw);           // [nbk] global cursor
+    uint32_t *lcnt = reinterpret_cast<uint32_t *>(gpos + nbk);       // [nbk] counts / cursors
+    uint32_t *loff = lcnt + nbk;                                     // [nbk + 1] local offsets
+    int32_t *keys = reinterpret_cast<int32_t *>(loff + nbk + 1);     // [kSortRows * kWalkBlock]
+    uint32_t *wave_tot = reinterpret_cast<uint32_t *>(keys + kSortRows * kWalkBlock);  // [4]
+    const int per = (nbk + kWalkBlock - 1) / kWalkBlock;  // buckets per thread in the scan
+    for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] = pos[(int64_t)b * gridDim.x + blockIdx.x];
+    const int64_t valid = min(wc, offs[n] - w0);
+    for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid; tile += gridDim.x) {
+        const int64_t i = tile * kWalkBlock + threadIdx.x;
+        const bool live = i < valid;
+        for (int32_t r0 = 0; r0 < rows; r0 += kSortRows) {
+            const int nr = min(kSortRows, rows - r0);
+            int32_t v[kSortRows];
+            for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lcnt[b] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSortRows; ++k) {
+                v[k] = -1;
+                if (live && k < nr) {
+                    v[k] = __builtin_nontemporal_load(vlog + (int64_t)(r0 + k) * wc + i);
+                    atomicAdd(lcnt + (v[k] >> bsh), 1u);
+                }
+            }
+            __syncthreads();
+            // local offsets: exclusive scan of lcnt, `per` buckets per thread
+            uint32_t mine = 0;
+            for (int q = 0; q < per; ++q) {
+                const int b = threadIdx.x * per + q;
+                if (b < nbk) mine += lcnt[b];
+            }
+            uint32_t run = block_exclusive_scan(mine, wave_tot);
+            for (int q = 0; q < per; ++q) {
+                const int b = threadIdx.x * per + q;
+                if (b < nbk) {
+                    loff[b] = run;
+                    run += lcnt[b];
+                }
+            }
+            if (threadIdx.x == kWalkBlock - 1) loff[nbk] = run;
+            __syncthreads();
+            for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lcnt[b] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSortRows; ++k) {
+                if (v[k] >= 0) {
+                    const int32_t b = v[k] >> bsh;
+                    keys[loff[b] + atomicAdd(lcnt + b, 1u)] = v[k];
+                }
+            }
+            __syncthreads();
+            const uint32_t total = loff[nbk];
+            for (uint32_t j = threadIdx.x; j < total; j += kWalkBlock) {
+                const int32_t x = keys[j];
+                const int32_t b = x >> bsh;
+                part[gpos[b] + (j - loff[b])] = x;
+            }
+            __syncthreads();
+            for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] += loff[b + 1] - loff[b];
+            __syncthreads();
+        }
+    }
+}
+
+static size_t scatter_lds_bytes(int32_t nbk) {
+    return sizeof(int64_t) * nbk + sizeof(uint32_t) * (2 * (size_t)nbk + 1) +
+           sizeof(int32_t) * kSortRows * kWalkBlock + sizeof(uint32_t) * 4 + 16;
+}
+
+// Histogram of the bucket-ordered entries: block j counts part[j*slice, (j+1)*slice) bucket
+// by bucket in LDS and adds the nonzero bins to out.  Bucket b starts at pos[b * nblk].
+__global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ pos, int nblk, int bsh,
+    int32_t nbk, int64_t slice, int32_t n, unsigned long long *__restrict__ out) {
+    extern __shared__ uint32_t lds_h[];
+    const int32_t bins = 1 << bsh;
+    const int64_t total = pos[(int64_t)nbk * nblk];
+    const int64_t s0 = (int64_t)blockIdx.x * slice;
+    const int64_t s1 = min(total, s0 + slice);
+    if (s0 >= s1) return;
+    int32_t lo = 0, hi = nbk;  // largest bucket b with start(b) <= s0
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (pos[(int64_t)mid * nblk] <= s0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    for (int32_t b = lo; b < nbk; ++b) {
+        const int64_t bs = pos[(int64_t)b * nblk];
+        const int64_t be = pos[(int64_t)(b + 1) * nblk];
+        if (bs >= s1) break;
+        const int64_t a = max(s0, bs), z = min(s1, be);
+        if (a >= z) continue;
+        for (int i = threadIdx.x; i < bins; i += kWalkBlock) lds_h[i] = 0;
+        __syncthreads();
+        for (int64_t i = a + threadIdx.x; i < z; i += kWalkBlock)
+            atomicAdd(lds_h + (part[i] & (bins - 1)), 1u);
+        __syncthreads();
+        const int64_t base = (int64_t)b << bsh;
+        for (int i = threadIdx.x; i < bins; i += kWalkBlock) {
+            const uint32_t c = lds_h[i];
+            if (c && base + i < n) atomicAdd(out + base + i, (unsigned long long)c);
+        }
+        __syncthreads();
+    }
+}
+
+struct EventSet {
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    ~EventSet() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// Bucketed count of one log (rows x wc entries, `valid` walks per row) into out.
+static int bucket_count(int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
+                        int64_t w0, int nblk, int bsh, int32_t nbk, int64_t *cnt, int64_t *pos,
+                        void *scan_tmp, int32_t *part, int32_t n, unsigned long long *out,
+                        hipStream_t s) {
+    const int64_t ncnt = (int64_t)nbk * nblk;
+    SABA_TRY(scan_i64(cnt, pos, ncnt, scan_tmp, s));
+    bucket_scatter_kernel<<<nblk, kWalkBlock, scatter_lds_bytes(nbk), s>>>(vlog, rows, wc, offs, n,
+                                                                          w0, bsh, nbk, pos, part);
+    SABA_HIP_TRY(hipGetLastError());
+    const int64_t bound = (int64_t)rows * wc;  // at least the number of entries counted
+    const unsigned hblocks = (unsigned)std::max<int64_t>(1, (bound + kHistSlice - 1) / kHistSlice);
+    bucket_hist_kernel<<<hblocks, kWalkBlock, sizeof(uint32_t) << bsh, s>>>(
+        part, pos, nblk, bsh, nbk, kHistSlice, n, out);
+    SABA_HIP_TRY(hipGetLastError());
+    return SABA_OK;
+}
+
 static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                       int64_t *d_visits, saba_stats *st, hipStream_t s) {
     const int64_t W = p->n_walks;
     const int32_t n = g->n;
-    if (W < 0 || p->length < 0 || p->group < 1 || p->spread > 31 ||
+    const int32_t L = p->length;
+    if (W < 0 || L < 0 || p->group < 1 || p->spread > 31 ||
         (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) ||
         (W > 0 && !p->d_sources) || !d_endpoint || !d_visits ||
         (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET)) {
         set_error("invalid walk parameters");
         return SABA_E_INVALID;
     }
-    if ((__int128)W * (p->length > 0 ? p->length : 1) >= ((__int128)1 << 62)) {
+    if ((__int128)W * (L > 0 ? L : 1) >= ((__int128)1 << 62)) {
         set_error("walk count too large");
         return SABA_E_OVERFLOW;
     }
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    EventSet ev;
     const bool timing = st && p->time_kernels;
     if (timing)
-        for (auto &e : ev) SABA_HIP_TRY(hipEventCreate(&e));
-    auto cleanup = [&]() {
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-    };
-    if (timing) SABA_HIP_TRY(hipEventRecord(ev[0], s));
+        for (auto &e : ev.e) SABA_HIP_TRY(hipEventCreate(&e));
+    if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[0], s));
 
     SABA_TRY(g->walk_scratch[3].ensure(sizeof(int32_t)));
     int32_t *err = g->walk_scratch[3].as<int32_t>();
@@ -147,19 +358,21 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     SABA_HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * (size_t)n, s));
     auto *ep = reinterpret_cast<unsigned long long *>(d_endpoint);
     auto *vi = reinterpret_cast<unsigned long long *>(d_visits);
+    bool counted_separately = false;
 
     if (W > 0 && p->mode == SABA_WALK_NAIVE) {
         SABA_TRY(g->walk_scratch[0].ensure(sizeof(uint32_t) * (size_t)n));
         uint32_t *cursor = g->walk_scratch[0].as<uint32_t>();
         SABA_HIP_TRY(hipMemsetAsync(cursor, 0, sizeof(uint32_t) * (size_t)n, s));
-        if (timing) SABA_HIP_TRY(hipEventRecord(ev[1], s));
+        if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
         unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
-        walk_naive_kernel<<<blocks, kWalkBlock, 0, s>>>(g->vrec, g->col_idx, p->d_sources, W,
-                                                        p->length, p->seed, p->group, p->spread,
-                                                        n, cursor, ep, vi, err);
+        walk_naive_kernel<<<blocks, kWalkBlock, 0, s>>>(g->vrec, g->col_idx, p->d_sources, W, L,
+                                                        p->seed, p->group, p->spread, n, cursor,
+                                                        ep, vi, err);
         SABA_HIP_TRY(hipGetLastError());
-        if (timing) SABA_HIP_TRY(hipEventRecord(ev[2], s));
+        if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
     } else if (W > 0) {
+        // bucket order of the walks
         SABA_TRY(g->walk_scratch[0].ensure(sizeof(int64_t) * (size_t)n));
         SABA_TRY(g->walk_scratch[1].ensure(sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n)));
         SABA_TRY(g->walk_scratch[2].ensure(sizeof(int32_t) * (size_t)W));
@@ -174,36 +387,89 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
         source_fill_kernel<<<cblocks, kWalkBlock, 0, s>>>(offs, n, bsrc);
         SABA_HIP_TRY(hipGetLastError());
-        if (timing) SABA_HIP_TRY(hipEventRecord(ev[1], s));
-        unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
-        walk_bouquet_kernel<<<blocks, kWalkBlock, 0, s>>>(g->vrec, g->col_idx, bsrc, offs, n,
-                                                          p->length, p->seed, p->group, p->spread,
-                                                          ep, vi);
-        SABA_HIP_TRY(hipGetLastError());
-        if (timing) SABA_HIP_TRY(hipEventRecord(ev[2], s));
+
+        int bsh = 12;
+        while (bsh < kMaxBucketShift && (((int64_t)n + (1 << bsh) - 1) >> bsh) > kMaxBuckets) ++bsh;
+        const int32_t nbk = (int32_t)(((int64_t)n + (1 << bsh) - 1) >> bsh);
+        if (nbk > kMaxBuckets) {
+            if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
+            unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
+            walk_bouquet_atomic_kernel<<<blocks, kWalkBlock, 0, s>>>(
+                g->vrec, g->col_idx, bsrc, offs, n, L, p->seed, p->group, p->spread, ep, vi);
+            SABA_HIP_TRY(hipGetLastError());
+            if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
+        } else {
+            counted_separately = true;
+            // chunks of walks whose visit log fits kLogCap entries
+            int64_t wc = std::max<int64_t>(kWalkBlock, kLogCap / std::max<int32_t>(L, 1));
+            wc = std::min<int64_t>(W, wc / kWalkBlock * kWalkBlock);
+            const int nblk = (int)std::min<int64_t>(kPersistBlocks, (wc + kWalkBlock - 1) / kWalkBlock);
+            const int64_t ncnt = (int64_t)nbk * nblk;
+            const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
+            SABA_TRY(g->walk_scratch[4].ensure(sizeof(int32_t) * (size_t)(logn + wc)));
+            SABA_TRY(g->walk_scratch[5].ensure(sizeof(int32_t) * (size_t)(std::max<int32_t>(L, 1) * wc)));
+            SABA_TRY(g->walk_scratch[6].ensure(sizeof(int64_t) * (size_t)(4 * ncnt + 2) +
+                                               scan_tmp_bytes(ncnt)));
+            int32_t *vlog = g->walk_scratch[4].as<int32_t>();
+            int32_t *elog = vlog + logn;
+            int32_t *part = g->walk_scratch[5].as<int32_t>();
+            int64_t *cnt_v = g->walk_scratch[6].as<int64_t>();
+            int64_t *cnt_e = cnt_v + ncnt;
+            int64_t *pos = cnt_e + ncnt;  // ncnt + 1 entries
+            void *ctmp = pos + ncnt + 2;
+            float walk_ms = 0.f, count_ms = 0.f;
+            for (int64_t w0 = 0; w0 < W; w0 += wc) {
+                const int64_t this_wc = std::min<int64_t>(wc, W - w0);
+                if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
+                walk_bouquet_log_kernel<<<nblk, kWalkBlock, sizeof(uint32_t) * 2 * nbk, s>>>(
+                    g->vrec, g->col_idx, bsrc, offs, n, w0, this_wc, L, p->seed, p->group,
+                    p->spread, bsh, nbk, vlog, elog, reinterpret_cast<long long *>(cnt_v),
+                    reinterpret_cast<long long *>(cnt_e));
+                SABA_HIP_TRY(hipGetLastError());
+                if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
+                if (L > 0)
+                    SABA_TRY(bucket_count(vlog, L, this_wc, offs, w0, nblk, bsh, nbk, cnt_v, pos,
+                                          ctmp, part, n, vi, s));
+                SABA_TRY(bucket_count(elog, 1, this_wc, offs, w0, nblk, bsh, nbk, cnt_e, pos, ctmp,
+                                      part, n, ep, s));
+                if (timing) {
+                    SABA_HIP_TRY(hipEventRecord(ev.e[3], s));
+                    SABA_HIP_TRY(hipEventSynchronize(ev.e[3]));
+                    float a = 0.f, b = 0.f;
+                    SABA_HIP_TRY(hipEventElapsedTime(&a, ev.e[1], ev.e[2]));
+                    SABA_HIP_TRY(hipEventElapsedTime(&b, ev.e[2], ev.e[3]));
+                    walk_ms += a;
+                    count_ms += b;
+                }
+            }
+            if (st && timing) {
+                st->kernel_ms = walk_ms;
+                st->count_ms = count_ms;
+            }
+        }
     }
-    if (timing) SABA_HIP_TRY(hipEventRecord(ev[3], s));
+    if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[4], s));
     int32_t h_err = 0;
     SABA_HIP_TRY(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     SABA_HIP_TRY(hipStreamSynchronize(s));
     if (h_err) {
-        cleanup();
         set_error("a walk source is out of range or an isolated vertex");
         return SABA_E_INVALID;
     }
     if (st) {
+        const double kms = st->kernel_ms, cms = st->count_ms;
         *st = saba_stats{};
         st->walks = W;
-        st->walk_steps = W * (int64_t)p->length;
+        st->walk_steps = W * (int64_t)L;
         if (timing) {
             float a = 0.f, b = 0.f;
-            if (W > 0) SABA_HIP_TRY(hipEventElapsedTime(&a, ev[1], ev[2]));
-            SABA_HIP_TRY(hipEventElapsedTime(&b, ev[0], ev[3]));
-            st->kernel_ms = a;
+            if (W > 0 && !counted_separately) SABA_HIP_TRY(hipEventElapsedTime(&a, ev.e[1], ev.e[2]));
+            SABA_HIP_TRY(hipEventElapsedTime(&b, ev.e[0], ev.e[4]));
+            st->kernel_ms = counted_separately ? kms : a;
+            st->count_ms = counted_separately ? cms : 0.0;
             st->total_ms = b;
         }
     }
-    cleanup();
     return SABA_OK;
 }
 

@@ -58,5 +58,5 @@ def test_structs_match_header_layout():
     assert ctypes.sizeof(b.WalkParams) == 40
     # saba_aesc_params: 3 doubles, 3 uint32, 5 int32, int64 -> 64 bytes
     assert ctypes.sizeof(b.AescParams) == 64
-    assert ctypes.sizeof(b.Stats) == 72
+    assert ctypes.sizeof(b.Stats) == 80
     assert ctypes.sizeof(b.GraphInfo) == 40
