@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark of the random-bouquet walk generator on one MI355X.
+"""Benchmark of the random-bouquet walk generator and the TGT+ estimator on one MI355X.
 
-Workload: R-MAT scale 20, edge factor 16, (a, b, c) = (0.57, 0.19, 0.19), seed 1,
-symmetrised and deduplicated, int32 CSR; 2^24 walks of 64 steps from uniform
-non-isolated sources (seed 1), hash-keyed neighbour choice, bouquet execution.
-A step is one saba_walks call: source bucketing, key set-up, the walks and the
-int64 endpoint / visit histograms (Sec. 5.4's synthetic benchmark).
+Headline (`value`): walk-steps/s.  Workload: R-MAT scale 20, edge factor 16,
+(a, b, c) = (0.57, 0.19, 0.19), seed 1, symmetrised and deduplicated, int32 CSR;
+2^24 walks of 64 steps from uniform non-isolated sources (seed 1), hash-keyed
+neighbour choice, bouquet execution, G = 1.  A step is one saba_walks call:
+source bucketing, key set-up, the walks and the int64 endpoint / visit
+histograms (the synthetic benchmark of Sec. 5.4).
 
-Prints one JSON line.  `roofline` prices the walk kernel at 3 random 64-byte
-sectors per walk step (vertex record, adjacency entry, visit counter) against
-the 8 TB/s HBM peak; `cpu_baseline` times the CPU oracle on a bounded slice of
-the same workload.
+Secondary (`aesc`): edges/s of the TGT+ estimator at eps = 0.1 on the Chung-Lu
+graph n = 10^6, average degree 10, exponent 2.5, seed 1, largest component,
+over a seeded 1% sample of its edges (saba_aesc_query; the paper estimates its
+largest graph the same way, from a fixed 5% of the edges).
+
+`roofline` prices the dominant kernel with its algorithmic bytes; `cpu_baseline`
+times the CPU oracle on a bounded slice of the same workload.
 """
 from __future__ import annotations
 
@@ -25,9 +29,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and AESC edges/s at ε=0.1 (1 GPU); p50/p99 query latency"
-BYTES_PER_STEP = 192  # 3 random 64 B sectors: vertex record, adjacency entry, visit counter
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_rmat20_counters.json")
+# walk kernel: two random 64 B sectors per step (vertex record, adjacency entry) plus the
+# 4 B coalesced visit-log store
+WALK_KERNEL_BYTES_PER_STEP = 132
+# whole walk call, counted as the survey's unit: vertex record, adjacency entry and a random
+# visit-counter update per step
+WALK_STEP_BYTES = 192
+# estimator walk kernel: vertex record, adjacency entry, support-map lookup per step
+AESC_STEP_BYTES = 192
+COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
 
 def kernel_source_sha() -> str:
@@ -38,25 +49,23 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(mode: str, walks: int, steps: int):
-    """HBM bytes per launch of the walk kernel from committed rocprofv3 counters, if they
-    were taken on the current kernel source; else None."""
+def measured_traffic(walks: int, steps: int, chunks: int):
+    """HBM bytes per launch of the walk kernel from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source with this workload; else None."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except OSError:
         return None
-    rec = c.get(mode)
-    if not rec or c.get("kernel_source_sha") != kernel_source_sha():
+    if c.get("kernel_source_sha") != kernel_source_sha():
         return None
-    if rec.get("walks") != walks or rec.get("length") != steps:
+    if c.get("walks") != walks or c.get("length") != steps or c.get("chunks") != chunks:
         return None
-    return float(rec["hbm_bytes_per_dispatch"])
+    return float(c["hbm_bytes_per_dispatch"])
 
 
-def cpu_baseline(g, L, seed, target_s=12.0):
+def walks_cpu_baseline(g, L, seed, target_s=12.0):
     """The oracle as it stands, on all host cores, on a slice of the walks."""
-    import numpy as np
     import graphgen
     import oracle
     cores = os.cpu_count() or 1
@@ -76,39 +85,11 @@ def cpu_baseline(g, L, seed, target_s=12.0):
                       f"({dt:.1f} s wall, OpenMP over walks)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
-    ap.add_argument("--group", type=int, default=1)
-    ap.add_argument("--spread", type=int, default=0)
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--walks-log2", type=int, default=24)
-    ap.add_argument("--length", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the walk path shards by splitting the walk range, see the design notes)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
+def bench_walks(args, saba, torch, np):
     import graphgen
-    import paper_2410_14056_amd as saba
-
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    saba.load()
-    t_gen = time.perf_counter()
     g = graphgen.rmat(args.scale, 16, 0.57, 0.19, 0.19, 1)
     W, L, seed = 1 << args.walks_log2, args.length, 1
     src_np = graphgen.uniform_sources(g, W, 1)
-    t_gen = time.perf_counter() - t_gen
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     src = torch.from_numpy(src_np).cuda()
     mode = saba.SABA_WALK_BOUQUET if args.mode == "bouquet" else saba.SABA_WALK_NAIVE
@@ -122,38 +103,33 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    kms = []
+    kms, cms, tms = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = step()
         kms.append(r.stats["kernel_ms"])
+        cms.append(r.stats["count_ms"])
+        tms.append(r.stats["total_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert int(vi.sum().item()) == W * L and int(ep.sum().item()) == W
-
-    steps_total = W * L * args.steps
-    value = steps_total / dt
     k_ms = float(np.mean(kms))
-    achieved = BYTES_PER_STEP * W * L / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.mode, W, L)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "walk-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    call_ms = float(np.mean(tms))
+    log_cap = 1 << 29  # visit-log entries per chunk (library constant)
+    chunks = -(-W * L // log_cap) if mode == saba.SABA_WALK_BOUQUET else 1
+    per_launch_steps = W * L // chunks
+    bouquet = mode == saba.SABA_WALK_BOUQUET
+    kbytes = WALK_KERNEL_BYTES_PER_STEP if bouquet else WALK_STEP_BYTES
+    achieved = kbytes * per_launch_steps / (k_ms / chunks * 1e-3) / 1e9
+    return g, {
+        "value": W * L * args.steps / dt,
         "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
         "config": {
             "workload": f"rmat{args.scale}_ef16_walks_2^{args.walks_log2}x{L}",
             "graph": f"R-MAT scale {args.scale}, edge factor 16, a=0.57 b=0.19 c=0.19, seed 1, "
                      "symmetrised, deduplicated, int32 CSR",
-            "n": g.n, "nnz": g.nnz, "walks": W, "length": L, "sources": "uniform non-isolated, seed 1",
+            "n": g.n, "nnz": g.nnz, "walks": W, "length": L,
+            "sources": "uniform non-isolated, seed 1",
             "mode": args.mode, "group": args.group, "spread": args.spread,
         },
         "roofline": {
@@ -162,14 +138,129 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "walk_bouquet_kernel" if mode == saba.SABA_WALK_BOUQUET else "walk_naive_kernel",
-            "kernel_ms": k_ms,
-            "bytes_per_step": BYTES_PER_STEP,
+            "traffic": measured_traffic(W, L, chunks) if bouquet else None,
+            "kernel": "walk_bouquet_log_kernel" if bouquet else "walk_naive_kernel",
+            "kernel_ms_per_launch": k_ms / chunks,
+            "launches_per_step": chunks,
+            "bytes_per_step": kbytes,
+            "steps_per_launch": per_launch_steps,
+            "call": {"ms": call_ms, "count_ms": float(np.mean(cms)),
+                     "achieved_at_192B_per_step": WALK_STEP_BYTES * W * L / (call_ms * 1e-3) / 1e9},
         },
     }
+
+
+def bench_aesc(args, saba, torch, np):
+    import graphgen
+    t0 = time.perf_counter()
+    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+    lam = graphgen.spectral_lambda(g)
+    prep_s = time.perf_counter() - t0
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    ce = graphgen.canonical_edges(g)
+    perm = np.random.default_rng(7).permutation(g.m)
+    k = max(1, int(round(args.aesc_frac * g.m)))
+    q = np.ascontiguousarray(ce[np.sort(perm[:k])])
+    qt = torch.from_numpy(q).cuda()
+    warm = torch.from_numpy(np.ascontiguousarray(ce[np.sort(perm[k:k + 64])])).cuda()
+    saba.aesc_query(sg, warm, args.aesc_eps, lam, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc, st = saba.aesc_query(sg, qt, args.aesc_eps, lam, 1, time_kernels=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert bool(torch.isfinite(sc).all().item())
+    walk_s = st["kernel_ms"] * 1e-3
+    achieved = AESC_STEP_BYTES * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
+    out = {
+        "value": k / dt,
+        "unit": "edges/s",
+        "seconds": dt,
+        "edges": k,
+        "eps": args.aesc_eps,
+        "workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_query_1pct"
+        if abs(args.aesc_frac - 0.01) < 1e-12 else f"chung_lu_n1e6_k10_b2.5_lcc_query_{args.aesc_frac}",
+        "graph": {"n": g.n, "m": g.m, "lambda": lam, "prep_s": prep_s},
+        "walk_steps": st["walk_steps"],
+        "walk_steps_per_s": st["walk_steps"] / dt,
+        "push_edge_visits": st["push_edge_visits"],
+        "sources": st["sources"],
+        "max_tau": st["max_tau"], "max_ttau": st["max_ttau"],
+        "roofline": {"bound": "hbm", "kernel": "mc_walk_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "kernel_ms": st["kernel_ms"],
+                     "bytes_per_step": AESC_STEP_BYTES},
+    }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, L, seed)
+        import oracle
+        cores = os.cpu_count() or 1
+        nq = 32
+        t1 = time.perf_counter()
+        oracle.aesc(g, args.aesc_eps, lam, 1, query=q[:nq], nthreads=cores)
+        dq = time.perf_counter() - t1
+        if dq < 8.0:
+            nq = int(min(k, nq * max(1.0, 12.0 / max(dq, 1e-3))))
+            t1 = time.perf_counter()
+            oracle.aesc(g, args.aesc_eps, lam, 1, query=q[:nq], nthreads=cores)
+            dq = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": nq / dq, "unit": "edges/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"first {nq} edges of the same 1% sample ({dq:.1f} s wall, "
+                                         "OpenMP over sources)"}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["all", "walks", "aesc"], default="all")
+    ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
+    ap.add_argument("--group", type=int, default=1)
+    ap.add_argument("--spread", type=int, default=0)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--walks-log2", type=int, default=24)
+    ap.add_argument("--length", type=int, default=64)
+    ap.add_argument("--aesc-frac", type=float, default=0.01)
+    ap.add_argument("--aesc-eps", type=float, default=0.1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the walk range would be split across GPUs and the histograms summed; "
+              "see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2410_14056_amd as saba
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    saba.load()
+    out = {"metric": METRIC, "value": None, "unit": "walk-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic"}
+    if args.workload in ("all", "walks"):
+        g, w = bench_walks(args, saba, torch, np)
+        out.update({"value": w["value"], "ms_per_step": w["ms_per_step"], "config": w["config"],
+                    "roofline": w["roofline"]})
+        print(json.dumps({"progress": "walks done", "value": w["value"]}), file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = walks_cpu_baseline(g, args.length, 1)
+        del g
+    if args.workload in ("all", "aesc"):
+        a = bench_aesc(args, saba, torch, np)
+        out["aesc"] = a
+        if args.workload == "aesc":
+            out.update({"value": a["value"], "unit": "edges/s", "dtype": "f64",
+                        "ms_per_step": a["seconds"] * 1e3,
+                        "config": {"workload": a["workload"]}, "roofline": a["roofline"]})
+            if "cpu_baseline" in a:
+                out["cpu_baseline"] = a["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 

@@ -13,9 +13,13 @@
 // and g(s,t) = (D_st + MC_st / n_st) / d_s, SC(u,v) = g(u,v) + g(v,u).
 //
 // Work layout: sources are processed in batches that fit a memory budget.  Each source of a
-// batch owns dense FP64 h vectors (two levels), frontier lists and a visit-stamp array; the
-// dense vectors are cleared sparsely through the frontier lists, so they are zeroed only once.
-// The deterministic levels run level-synchronously over the whole batch.  The walk pairs of
+// batch owns dense FP64 h vectors (two levels), frontier lists and support bitmaps (two
+// levels); they are cleared sparsely through the frontier lists, so they are zeroed only
+// once.  The deterministic levels run level-synchronously over the whole batch.  A wavefront
+// walks the concatenated rows of 64 frontier vertices in chunks of 64 entries, so hub rows are
+// split across lanes; the pull folds only the terms whose vertex is in the support bitmap (a
+// zero term leaves a sum of non-negative numbers unchanged), in row order, so every h value is
+// bit-identical to the sequential left fold over the whole row.  The walk pairs of
 // all directed edges of the batch are cut into chunks of 64 walks; one wavefront walks one
 // chunk and reduces it in a fixed butterfly order, and each edge sums its chunks in chunk
 // order, so results do not depend on the launch shape.
@@ -32,22 +36,23 @@ namespace saba {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kChunk = 64;  // walks per wavefront chunk
-constexpr int kBigRow = 32; // rows longer than this are processed by a whole wavefront
 
 enum : int32_t { kErrOverflow = 1, kErrNotEdge = 2 };
 
 // scratch slots in Graph::est
 enum {
     B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G, B_TTAU_SRC, B_MAXTAU_SRC, B_WANT, B_SRCMARK,
-    B_SRCPOS, B_LIST, B_HA, B_HB, B_FA, B_FB, B_MARK, B_BSRC, B_BSTATE, B_EBASE, B_CHUNKS,
+    B_SRCPOS, B_LIST, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_BSRC, B_BSTATE, B_EBASE, B_CHUNKS,
     B_COFF, B_PART, B_SCAN, B_FLAGS, B_QE, B_DEG64, B_COUNT
 };
 
-struct BatchState {  // one per source of a batch
+struct BatchState {  // one per source of a batch; [2] entries are indexed by level parity
     int32_t active;
     int32_t finalbuf;
-    int32_t fsz[2];
-    double hmax;
+    int32_t fsz[2];                 // frontier (support) sizes
+    unsigned long long vol[2];      // support volume sum of d(x)
+    unsigned long long hmaxbits[2]; // max of h over the support, as IEEE bits (h > 0)
+    double hmax;                    // max of h_ttau once the source has stopped
 };
 
 struct Flags {
@@ -191,13 +196,14 @@ __global__ void compact_kernel(const long long *__restrict__ mark, const int64_t
         if (mark[s]) list[pos[s]] = (int32_t)s;
 }
 
-// Level 0 of every source of the batch: h_0 = e_s, frontier {s}; per-edge accumulators reset.
+// Level 0 of every source of the batch: h_0 = e_s, support {s}; per-edge accumulators reset.
 __global__ __launch_bounds__(kBlock) void batch_init_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ list, int64_t i0, int32_t nb,
-    int32_t n, int32_t *__restrict__ bsrc, BatchState *__restrict__ bs, double *__restrict__ hA,
-    int32_t *__restrict__ FA, double *__restrict__ D, long long *__restrict__ nreq,
-    double *__restrict__ MC, unsigned long long *__restrict__ vis0,
-    unsigned long long *__restrict__ vis1, long long *__restrict__ deg64) {
+    int32_t n, int64_t nw, int32_t *__restrict__ bsrc, BatchState *__restrict__ bs,
+    double *__restrict__ hA, int32_t *__restrict__ FA, uint32_t *__restrict__ bmA,
+    double *__restrict__ D, long long *__restrict__ nreq, double *__restrict__ MC,
+    unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
+    long long *__restrict__ deg64) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb) return;
@@ -205,13 +211,20 @@ __global__ __launch_bounds__(kBlock) void batch_init_kernel(
     const int2 r = vrec[s];
     if (lane == 0) {
         bsrc[b] = s;
-        bs[b].active = 1;
-        bs[b].finalbuf = 0;
-        bs[b].fsz[0] = 1;
-        bs[b].fsz[1] = 0;
-        bs[b].hmax = 0.0;
+        BatchState st;
+        st.active = 1;
+        st.finalbuf = 0;
+        st.fsz[0] = 1;
+        st.fsz[1] = 0;
+        st.vol[0] = (unsigned long long)r.y;
+        st.vol[1] = 0;
+        st.hmaxbits[0] = (unsigned long long)__double_as_longlong(1.0);
+        st.hmaxbits[1] = 0;
+        st.hmax = 0.0;
+        bs[b] = st;
         hA[b * n + s] = 1.0;
         FA[b * n] = s;
+        bmA[b * nw + (s >> 5)] = 1u << (s & 31);
         deg64[b] = r.y;
     }
     for (int32_t i = lane; i < r.y; i += 64) {
@@ -223,32 +236,23 @@ __global__ __launch_bounds__(kBlock) void batch_init_kernel(
     }
 }
 
-// Alg. 1 loop test at level l for each active source: support volume and maximum of h_l,
-// the deterministic terms of level l, and the walk pairs still needed.
-__global__ __launch_bounds__(kBlock) void level_stats_kernel(
+// Alg. 1 loop test at level l for each active source: with the support volume and maximum of
+// h_l (accumulated when h_l was built), add the deterministic terms of level l and compare the
+// volume with the walk pairs that would still be needed.
+__global__ __launch_bounds__(kBlock) void level_decide_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
     const int32_t *__restrict__ bsrc, BatchState *__restrict__ bs, int32_t nb, int32_t n,
-    int32_t level, const double *__restrict__ hcur_all, const int32_t *__restrict__ Fcur_all,
-    const int32_t *__restrict__ tau, const int32_t *__restrict__ maxtau, double *__restrict__ D,
-    int32_t *__restrict__ ttau_src, double c, int32_t push_all, int32_t tilde_tau_max,
-    Flags *__restrict__ fl) {
+    int32_t level, const double *__restrict__ hcur_all, const int32_t *__restrict__ tau,
+    const int32_t *__restrict__ maxtau, double *__restrict__ D, int32_t *__restrict__ ttau_src,
+    double c, int32_t push_all, int32_t tilde_tau_max, Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb || !bs[b].active) return;
-    const int cur = level & 1;
+    const int cur = level & 1, nxt = cur ^ 1;
     const int32_t s = bsrc[b];
     const double *h = hcur_all + b * n;
-    const int32_t *F = Fcur_all + b * n;
-    const int32_t fsz = bs[b].fsz[cur];
-    long long vol = 0;
-    double hmax = 0.0;
-    for (int32_t i = lane; i < fsz; i += 64) {
-        const int32_t x = F[i];
-        vol += vrec[x].y;
-        hmax = fmax(hmax, h[x]);
-    }
-    vol = wave_sum_ll(vol);
-    hmax = wave_max_d(hmax);
+    const long long vol = (long long)bs[b].vol[cur];
+    const double hmax = __longlong_as_double((long long)bs[b].hmaxbits[cur]);
     const int2 r = vrec[s];
     const double hs = h[s];
     long long need = 0;
@@ -279,49 +283,98 @@ __global__ __launch_bounds__(kBlock) void level_stats_kernel(
             ttau_src[s] = level;
             atomicMax(&fl->max_ttau, level);
         } else {
+            // level l + 1 is built into the buffers of parity nxt (cleared after level l - 1)
+            bs[b].fsz[nxt] = 0;
+            bs[b].vol[nxt] = 0;
+            bs[b].hmaxbits[nxt] = 0;
             fl->any_active = 1;
         }
     }
 }
 
-// Next frontier: the neighbours of the current frontier, each appended once (visit stamps).
+// Rows of the 64 frontier entries [base, base + 64) of one source, as seen by each lane:
+// its own row and the exclusive prefix of the row lengths over the wavefront.
+struct WaveRows {
+    int32_t start, len, pre, total;
+};
+
+__device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
+                                              const int32_t *__restrict__ F, int64_t base,
+                                              int32_t fsz) {
+    const int lane = __lane_id();
+    WaveRows w;
+    w.start = 0;
+    w.len = 0;
+    if (base + lane < fsz) {
+        const int2 r = vrec[F[base + lane]];
+        w.start = r.x;
+        w.len = r.y;
+    }
+    int32_t inc = w.len;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    w.total = __shfl(inc, 63);
+    w.pre = inc - w.len;
+    if (w.len == 0) w.pre = w.total;  // lanes past the frontier own no entries
+    return w;
+}
+
+// Owner lane of flattened entry j (0 <= j < total): the largest lane whose prefix is <= j.
+__device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
+    int lo = 0, hi = 64;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (__shfl(pre, mid) <= j)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Next frontier: the neighbours of the current support, each appended once (support bitmap
+// of the next level), with one append counter update per wavefront chunk.
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, BatchState *__restrict__ bs,
-    int32_t n, int32_t level, const int32_t *__restrict__ Fcur_all, int32_t *__restrict__ Fnext_all,
-    uint32_t *__restrict__ mark_all, uint32_t stamp, Flags *__restrict__ fl) {
+    int32_t n, int64_t nw, int32_t level, const int32_t *__restrict__ Fcur_all,
+    int32_t *__restrict__ Fnext_all, uint32_t *__restrict__ bmnext_all, Flags *__restrict__ fl) {
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
     const int cur = level & 1, nxt = cur ^ 1;
     const int32_t *F = Fcur_all + b * n;
     int32_t *Fn = Fnext_all + b * n;
-    uint32_t *mark = mark_all + b * n;
+    uint32_t *bm = bmnext_all + b * nw;
     int32_t *nsz = &bs[b].fsz[nxt];
     const int32_t fsz = bs[b].fsz[cur];
     const int lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane;  // wave base
+    const int64_t wstride = (int64_t)gridDim.x * kBlock;
     unsigned long long visits = 0;
-    for (int64_t base = first; base < fsz; base += stride) {
-        const int64_t i = base + lane;
-        int2 r = make_int2(0, 0);
-        if (i < fsz) r = vrec[F[i]];
-        visits += r.y;
-        const bool big = r.y > kBigRow;
-        if (!big) {
-            for (int32_t k = 0; k < r.y; ++k) {
-                const int32_t x = col[r.x + k];
-                if (atomicExch(mark + x, stamp) != stamp) Fn[atomicAdd(nsz, 1)] = x;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
+         base += wstride) {
+        const WaveRows w = wave_rows(vrec, F, base, fsz);
+        if (lane == 0) visits += w.total;
+        for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
+            // cross-lane reads happen with every lane active; only memory accesses are masked
+            const int32_t j = j0 + lane;
+            const bool inr = j < w.total;
+            const int32_t jc = inr ? j : w.total - 1;
+            const int o = wave_owner(w.pre, jc);
+            const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
+            bool fresh = false;
+            int32_t x = 0;
+            if (inr) {
+                x = col[ost + (jc - opre)];
+                const uint32_t bit = 1u << (x & 31);
+                fresh = !(atomicOr(bm + (x >> 5), bit) & bit);
             }
-        }
-        unsigned long long bigm = __ballot(big);
-        while (bigm) {
-            const int src_lane = __builtin_ctzll(bigm);
-            bigm &= bigm - 1;
-            const int32_t rx = __shfl(r.x, src_lane);
-            const int32_t ry = __shfl(r.y, src_lane);
-            for (int32_t k = lane; k < ry; k += 64) {
-                const int32_t x = col[rx + k];
-                if (atomicExch(mark + x, stamp) != stamp) Fn[atomicAdd(nsz, 1)] = x;
+            const unsigned long long m = __ballot(fresh);
+            if (m) {
+                int32_t basepos = 0;
+                if (lane == 0) basepos = atomicAdd(nsz, (int32_t)__popcll(m));
+                basepos = __shfl(basepos, 0);
+                if (fresh) Fn[basepos + __popcll(m & ((1ull << lane) - 1))] = x;
             }
         }
     }
@@ -329,76 +382,99 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
-// h_{l+1}(x) = (sum over Gamma(x) of h_l, folded left to right in CSR order) / d(x).
+// h_{l+1}(x) = (left fold over Gamma(x) in CSR order of h_l) / d(x) for x in the next support;
+// the fold takes only the terms in the support of h_l, in row order.  Also accumulates the
+// support volume and maximum of h_{l+1}.
 __global__ __launch_bounds__(kBlock) void pull_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, BatchState *__restrict__ bs,
-    int32_t n, int32_t level, const double *__restrict__ hcur_all, double *__restrict__ hnext_all,
+    int32_t n, int64_t nw, int32_t level, const double *__restrict__ hcur_all,
+    const uint32_t *__restrict__ bmcur_all, double *__restrict__ hnext_all,
     const int32_t *__restrict__ Fnext_all, Flags *__restrict__ fl) {
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
     const int nxt = (level & 1) ^ 1;
     const double *h = hcur_all + b * n;
+    const uint32_t *bm = bmcur_all + b * nw;
     double *hn = hnext_all + b * n;
     const int32_t *F = Fnext_all + b * n;
     const int32_t fsz = bs[b].fsz[nxt];
     const int lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane;
-    unsigned long long visits = 0;
-    for (int64_t base = first; base < fsz; base += stride) {
-        const int64_t i = base + lane;
-        int32_t x = 0;
-        int2 r = make_int2(0, 0);
-        if (i < fsz) {
-            x = F[i];
-            r = vrec[x];
-        }
-        visits += r.y;
-        const bool big = r.y > kBigRow;
-        if (i < fsz && !big) {
-            double acc = 0.0;
-            for (int32_t k = 0; k < r.y; ++k) acc += h[col[r.x + k]];
-            hn[x] = acc / (double)r.y;
-        }
-        unsigned long long bigm = __ballot(big);
-        while (bigm) {
-            const int src_lane = __builtin_ctzll(bigm);
-            bigm &= bigm - 1;
-            const int32_t bx = __shfl(x, src_lane);
-            const int32_t rx = __shfl(r.x, src_lane);
-            const int32_t ry = __shfl(r.y, src_lane);
-            double acc = 0.0;
-            for (int32_t k0 = 0; k0 < ry; k0 += 64) {
-                const double v = (k0 + lane < ry) ? h[col[rx + k0 + lane]] : 0.0;
-                const int32_t cnt = min(64, ry - k0);
-                for (int32_t j = 0; j < cnt; ++j) acc += __shfl(v, j);
+    const int64_t wstride = (int64_t)gridDim.x * kBlock;
+    unsigned long long visits = 0, vol = 0;
+    double hmax = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
+         base += wstride) {
+        const WaveRows w = wave_rows(vrec, F, base, fsz);
+        if (lane == 0) visits += w.total;
+        double acc = 0.0;  // the fold of this lane's own row
+        for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
+            const int32_t j = j0 + lane;
+            const bool inr = j < w.total;
+            const int32_t jc = inr ? j : w.total - 1;
+            const int o = wave_owner(w.pre, jc);
+            const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
+            double v = 0.0;
+            bool nz = false;
+            if (inr) {
+                const int32_t y = col[ost + (jc - opre)];
+                if (bm[y >> 5] & (1u << (y & 31))) {
+                    v = h[y];
+                    nz = true;
+                }
             }
-            if (lane == 0) hn[bx] = acc / (double)ry;
+            unsigned long long m = __ballot(nz);
+            while (m) {  // ascending lanes = ascending row positions
+                const int src = __builtin_ctzll(m);
+                m &= m - 1;
+                const double t = __shfl(v, src);
+                const int owner = __shfl(o, src);
+                if (lane == owner) acc += t;
+            }
+        }
+        if (base + lane < fsz) {
+            const double hv = acc / (double)w.len;
+            hn[F[base + lane]] = hv;
+            vol += (unsigned long long)w.len;
+            hmax = fmax(hmax, hv);
         }
     }
     visits = wave_sum_ll((long long)visits);
-    if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
+    vol = wave_sum_ll((long long)vol);
+    hmax = wave_max_d(hmax);
+    if (lane == 0) {
+        if (visits) atomicAdd(&fl->push_visits, visits);
+        if (vol) {
+            atomicAdd(&bs[b].vol[nxt], vol);
+            atomicMax(&bs[b].hmaxbits[nxt], (unsigned long long)__double_as_longlong(hmax));
+        }
+    }
 }
 
-// After a level: zero h_l over its frontier so the dense vector is clean for level l + 2.
-__global__ __launch_bounds__(kBlock) void clear_level_kernel(BatchState *__restrict__ bs,
-                                                             int32_t n, int32_t level,
-                                                             double *__restrict__ hcur_all,
-                                                             const int32_t *__restrict__ Fcur_all) {
+// After a level: zero h_l and its support bitmap over the support, so both are clean when the
+// buffers are reused for level l + 2.  (Every set bit of a touched bitmap word belongs to the
+// support, so the whole word is cleared.)
+__global__ __launch_bounds__(kBlock) void clear_level_kernel(const BatchState *__restrict__ bs,
+                                                             int32_t n, int64_t nw, int parity,
+                                                             bool only_active,
+                                                             double *__restrict__ hA,
+                                                             double *__restrict__ hB,
+                                                             uint32_t *__restrict__ bmA,
+                                                             uint32_t *__restrict__ bmB,
+                                                             const int32_t *__restrict__ FA,
+                                                             const int32_t *__restrict__ FB) {
     const int64_t b = blockIdx.y;
-    if (!bs[b].active) return;
-    const int cur = level & 1;
-    double *h = hcur_all + b * n;
-    const int32_t *F = Fcur_all + b * n;
-    const int32_t fsz = bs[b].fsz[cur];
+    if (only_active && !bs[b].active) return;
+    const int pb = parity < 0 ? bs[b].finalbuf : parity;
+    double *h = (pb ? hB : hA) + b * (int64_t)n;
+    uint32_t *bm = (pb ? bmB : bmA) + b * nw;
+    const int32_t *F = (pb ? FB : FA) + b * (int64_t)n;
+    const int32_t fsz = bs[b].fsz[pb];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fsz;
-         i += (int64_t)gridDim.x * blockDim.x)
-        h[F[i]] = 0.0;
-}
-
-__global__ void reset_fsz_kernel(BatchState *__restrict__ bs, int32_t nb, int32_t level) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nb && bs[b].active) bs[b].fsz[level & 1] = 0;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = F[i];
+        h[x] = 0.0;
+        bm[x >> 5] = 0u;
+    }
 }
 
 // Walk pairs per wanted directed edge and the number of 64-walk chunks they need.
@@ -466,7 +542,8 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const int64_t *__restrict__ ebase, const int64_t *__restrict__ coff, int64_t nle,
     const int32_t *__restrict__ tau, const int32_t *__restrict__ ttau_src,
     const long long *__restrict__ nreq, const double *__restrict__ hA,
-    const double *__restrict__ hB, uint32_t seed, uint32_t G, uint32_t S,
+    const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
+    const uint32_t *__restrict__ bmB, int64_t nw, uint32_t seed, uint32_t G, uint32_t S,
     double *__restrict__ partial, unsigned long long *__restrict__ vis0,
     unsigned long long *__restrict__ vis1) {
     const int lane = __lane_id();
@@ -482,7 +559,9 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
         const int32_t t = col[e];
         const long long nr = nreq[e];
         const int32_t L = tau[e] - ttau_src[s];
-        const double *h = (bs[b].finalbuf ? hB : hA) + b * (int64_t)n;
+        const int fb = bs[b].finalbuf;
+        const double *h = (fb ? hB : hA) + b * (int64_t)n;
+        const uint32_t *bm = (fb ? bmB : bmA) + b * nw;
         const long long j = (c - coff[le]) * kChunk + lane;
         const bool active = j < 2 * nr;
         const int side = j >= nr ? 1 : 0;
@@ -495,9 +574,10 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
             int32_t cur = side ? t : s;
             for (int32_t l = 1; l <= L; ++l) {
                 cur = walk_step(vrec, col, cur, (uint32_t)l, key);
-                const double hv = h[cur];
-                acc += hv;
-                hits += hv != 0.0;
+                if (bm[cur >> 5] & (1u << (cur & 31))) {  // h_ttau is zero off its support
+                    acc += h[cur];
+                    hits += 1;
+                }
             }
         }
         const double sum = wave_sum_d(active ? (side ? -acc : acc) : 0.0);
@@ -532,22 +612,6 @@ __global__ void edge_reduce_kernel(const int2 *__restrict__ vrec, const int32_t 
         MC[e] = mc;
         g[e] = nr > 0 ? (D[e] + mc / (double)nr) / (double)rs.y : D[e] / (double)rs.y;
     }
-}
-
-// Leave the batch's dense vectors zero: clear h_ttau over its final frontier.
-__global__ __launch_bounds__(kBlock) void batch_clear_kernel(const BatchState *__restrict__ bs,
-                                                             int32_t n, double *__restrict__ hA,
-                                                             double *__restrict__ hB,
-                                                             const int32_t *__restrict__ FA,
-                                                             const int32_t *__restrict__ FB) {
-    const int64_t b = blockIdx.y;
-    const int fb = bs[b].finalbuf;
-    double *h = (fb ? hB : hA) + b * (int64_t)n;
-    const int32_t *F = (fb ? FB : FA) + b * (int64_t)n;
-    const int32_t fsz = bs[b].fsz[fb];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fsz;
-         i += (int64_t)gridDim.x * blockDim.x)
-        h[F[i]] = 0.0;
 }
 
 __global__ void finalize_all_kernel(const int32_t *__restrict__ canon,
@@ -689,21 +753,24 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         }
     }
 
-    // batch size from the memory budget: two dense FP64 levels, two frontiers, stamps
+    // batch size from the memory budget: two dense FP64 levels, two frontiers, two bitmaps
     size_t freeb = 0, totalb = 0;
     SABA_HIP_TRY(hipMemGetInfo(&freeb, &totalb));
     int64_t budget = p->mem_budget > 0 ? p->mem_budget
                                        : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
-    const int64_t per_src = (int64_t)n * (2 * 8 + 2 * 4 + 4);
+    const int64_t nw = ((int64_t)n + 31) / 32;
+    const int64_t per_src = (int64_t)n * (2 * 8 + 2 * 4) + 2 * 4 * nw;
     int64_t B = p->batch_sources > 0 ? p->batch_sources : std::max<int64_t>(1, budget / per_src);
     B = std::min<int64_t>({B, std::max<int64_t>(ns, 1), 65535});
 
-    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)(B * n);
+    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)(B * n) ||
+                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)(B * nw);
     SABA_TRY(E[B_HA].ensure(sizeof(double) * B * n));
     SABA_TRY(E[B_HB].ensure(sizeof(double) * B * n));
     SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * B * n));
     SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * B * n));
-    SABA_TRY(E[B_MARK].ensure(sizeof(uint32_t) * B * n));
+    SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * B * nw));
+    SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * B * nw));
     SABA_TRY(E[B_BSRC].ensure(sizeof(int32_t) * B));
     SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * B));
     SABA_TRY(E[B_EBASE].ensure(sizeof(int64_t) * (B + 1)));
@@ -711,18 +778,19 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
     SABA_TRY(E[B_SCAN].ensure(std::max(scan_tmp_bytes(B), scan_tmp_bytes(nnz))));
     double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
     int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
-    uint32_t *mark = E[B_MARK].as<uint32_t>();
+    uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
     int32_t *bsrc = E[B_BSRC].as<int32_t>();
     BatchState *bs = E[B_BSTATE].as<BatchState>();
     int64_t *ebase = E[B_EBASE].as<int64_t>();
     long long *deg64 = E[B_DEG64].as<long long>();
-    if (grow || g->stamp == 0 || g->stamp > 0xFFFFFF00u) {
-        // dense vectors start at zero and are kept clean by the sparse clears below
-        SABA_HIP_TRY(hipMemsetAsync(hA, 0, sizeof(double) * B * n, s));
-        SABA_HIP_TRY(hipMemsetAsync(hB, 0, sizeof(double) * B * n, s));
-        SABA_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * B * n, s));
-        g->stamp = 1;
+    if (grow || !g->est_clean) {
+        // dense vectors and bitmaps start at zero and are kept clean by the sparse clears
+        SABA_HIP_TRY(hipMemsetAsync(hA, 0, E[B_HA].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(hB, 0, E[B_HB].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(bmA, 0, E[B_BMA].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(bmB, 0, E[B_BMB].bytes, s));
     }
+    g->est_clean = false;  // until this call has cleared everything it touched
 
     const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
     int64_t batches = 0;
@@ -730,29 +798,30 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         const int32_t nb = (int32_t)std::min<int64_t>(B, ns - i0);
         ++batches;
         batch_init_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-            g->vrec, list, i0, nb, n, bsrc, bs, hA, FA, D, nreq, MC, vis0, vis1, deg64);
+            g->vrec, list, i0, nb, n, nw, bsrc, bs, hA, FA, bmA, D, nreq, MC, vis0, vis1, deg64);
         SABA_HIP_TRY(hipGetLastError());
+        const dim3 grid(ysplit, (unsigned)nb);
         for (int32_t level = 0;; ++level) {
-            double *hcur = (level & 1) ? hB : hA, *hnext = (level & 1) ? hA : hB;
-            int32_t *Fcur = (level & 1) ? FB : FA, *Fnext = (level & 1) ? FA : FB;
+            const int cur = level & 1;
+            double *hcur = cur ? hB : hA, *hnext = cur ? hA : hB;
+            int32_t *Fcur = cur ? FB : FA, *Fnext = cur ? FA : FB;
+            uint32_t *bmcur = cur ? bmB : bmA, *bmnext = cur ? bmA : bmB;
             SABA_HIP_TRY(hipMemsetAsync(&fl->any_active, 0, sizeof(int32_t), s));
-            level_stats_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-                g->vrec, g->col_idx, bsrc, bs, nb, n, level, hcur, Fcur, tau, maxtau, D,
-                ttau_src, c, p->push_all, p->tilde_tau_max, fl);
+            level_decide_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
+                g->vrec, g->col_idx, bsrc, bs, nb, n, level, hcur, tau, maxtau, D, ttau_src, c,
+                p->push_all, p->tilde_tau_max, fl);
             SABA_HIP_TRY(hipGetLastError());
             int32_t any = 0;
             SABA_HIP_TRY(hipMemcpyAsync(&any, &fl->any_active, sizeof(int32_t),
                                         hipMemcpyDeviceToHost, s));
             SABA_HIP_TRY(hipStreamSynchronize(s));
             if (!any) break;
-            const uint32_t stamp = ++g->stamp;
-            dim3 grid(ysplit, (unsigned)nb);
-            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, level, Fcur, Fnext,
-                                                  mark, stamp, fl);
-            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, level, hcur, hnext,
-                                                Fnext, fl);
-            clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, level, hcur, Fcur);
-            reset_fsz_kernel<<<grid_for(nb, 256), 256, 0, s>>>(bs, nb, level);
+            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, level, Fcur,
+                                                  Fnext, bmnext, fl);
+            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, level, hcur,
+                                                bmcur, hnext, Fnext, fl);
+            clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, nw, cur, true, hA, hB, bmA, bmB, FA,
+                                                       FB);
             SABA_HIP_TRY(hipGetLastError());
         }
         // walk pairs of the batch's edges
@@ -774,9 +843,8 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         SABA_HIP_TRY(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
         SABA_HIP_TRY(hipStreamSynchronize(s));
         if (hf.err & kErrOverflow) {
-            g->stamp = 0;  // dense vectors may be dirty: re-zero on the next call
             set_error("walk count overflows the 64-bit range (eps too small?)");
-            return SABA_E_OVERFLOW;
+            return SABA_E_OVERFLOW;  // scratch stays marked dirty: re-zeroed on the next call
         }
         SABA_TRY(E[B_PART].ensure(sizeof(double) * std::max<int64_t>(T, 1)));
         double *partial = E[B_PART].as<double>();
@@ -784,7 +852,7 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
             if (timing) SABA_HIP_TRY(hipEventRecord(ev[1], s));
             mc_walk_kernel<<<grid_for(T, kWavesPerBlock, 2048), kBlock, 0, s>>>(
                 g->vrec, g->col_idx, bsrc, bs, nb, n, ebase, coff, nle, tau, ttau_src, nreq, hA,
-                hB, p->seed, p->group, p->spread, partial, vis0, vis1);
+                hB, bmA, bmB, nw, p->seed, p->group, p->spread, partial, vis0, vis1);
             SABA_HIP_TRY(hipGetLastError());
             if (timing) {
                 SABA_HIP_TRY(hipEventRecord(ev[2], s));
@@ -796,9 +864,11 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         }
         edge_reduce_kernel<<<grid_for(nle, 256, 1 << 16), 256, 0, s>>>(
             g->vrec, bsrc, nb, ebase, coff, nle, want, nreq, D, partial, MC, gd);
-        batch_clear_kernel<<<dim3(ysplit, (unsigned)nb), kBlock, 0, s>>>(bs, n, hA, hB, FA, FB);
+        // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
+        clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, nw, -1, false, hA, hB, bmA, bmB, FA, FB);
         SABA_HIP_TRY(hipGetLastError());
     }
+    g->est_clean = true;
 
     if (o.sc) {
         if (o.q < 0) {

@@ -59,7 +59,7 @@ struct Graph {
     int32_t *rev = nullptr;
     int32_t *canon = nullptr;
     int32_t *row_of = nullptr;  // source vertex of each CSR entry
-    uint32_t stamp = 0;         // visit-mark generation for the estimator's level expansion
+    bool est_clean = false;     // estimator scratch vectors are all zero
     // reusable scratch
     DevBuf walk_scratch[4];
     DevBuf est[32];
