@@ -42,7 +42,7 @@ enum : int32_t { kErrOverflow = 1, kErrNotEdge = 2 };
 // scratch slots in Graph::est
 enum {
     B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G, B_TTAU_SRC, B_MAXTAU_SRC, B_WANT, B_SRCMARK,
-    B_SRCPOS, B_LIST, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_BSRC, B_BSTATE, B_EBASE, B_CHUNKS,
+    B_SRCPOS, B_LIST, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_BSRC, B_BSTATE, B_EBASE, B_CHUNKS,
     B_COFF, B_PART, B_SCAN, B_FLAGS, B_QE, B_DEG64, B_COUNT
 };
 
@@ -293,22 +293,25 @@ __global__ __launch_bounds__(kBlock) void level_decide_kernel(
 }
 
 // Rows of the 64 frontier entries [base, base + 64) of one source, as seen by each lane:
-// its own row and the exclusive prefix of the row lengths over the wavefront.
+// its own row and the exclusive prefix of the row lengths over the wavefront.  Hub rows
+// count as empty when `skip_hubs` is set (they are handled separately).
 struct WaveRows {
-    int32_t start, len, pre, total;
+    int32_t x, start, len, pre, total;
 };
 
 __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
                                               const int32_t *__restrict__ F, int64_t base,
-                                              int32_t fsz) {
+                                              int32_t fsz, bool skip_hubs) {
     const int lane = __lane_id();
     WaveRows w;
+    w.x = -1;
     w.start = 0;
     w.len = 0;
     if (base + lane < fsz) {
-        const int2 r = vrec[F[base + lane]];
+        w.x = F[base + lane];
+        const int2 r = vrec[w.x];
         w.start = r.x;
-        w.len = r.y;
+        w.len = (skip_hubs && r.y > kHubRow) ? 0 : r.y;
     }
     int32_t inc = w.len;
     for (int o = 1; o < 64; o <<= 1) {
@@ -317,11 +320,11 @@ __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
     }
     w.total = __shfl(inc, 63);
     w.pre = inc - w.len;
-    if (w.len == 0) w.pre = w.total;  // lanes past the frontier own no entries
     return w;
 }
 
-// Owner lane of flattened entry j (0 <= j < total): the largest lane whose prefix is <= j.
+// Owner lane of flattened entry j (0 <= j < total): the largest lane whose prefix is <= j,
+// which is always a lane whose row contains entry j.
 __device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
     int lo = 0, hi = 64;
     while (hi - lo > 1) {
@@ -334,26 +337,28 @@ __device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
     return lo;
 }
 
-// Next frontier: the neighbours of the current support, each appended once (support bitmap
-// of the next level), with one append counter update per wavefront chunk.
+// Push the current support one hop: set the bit of every neighbour in the next level's
+// support bitmap and, for neighbours with hub rows, the bit of the reverse CSR position in
+// the hub-slot bitmap.  Fire-and-forget atomics; the next frontier list is built from the
+// bitmap afterwards, in ascending vertex order.
 __global__ __launch_bounds__(kBlock) void expand_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, BatchState *__restrict__ bs,
-    int32_t n, int64_t nw, int32_t level, const int32_t *__restrict__ Fcur_all,
-    int32_t *__restrict__ Fnext_all, uint32_t *__restrict__ bmnext_all, Flags *__restrict__ fl) {
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ slotv, BatchState *__restrict__ bs, int32_t n, int64_t nw,
+    int64_t nsw, int32_t level, const int32_t *__restrict__ Fcur_all,
+    uint32_t *__restrict__ bmnext_all, uint32_t *__restrict__ slotbm_all, Flags *__restrict__ fl) {
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
-    const int cur = level & 1, nxt = cur ^ 1;
+    const int cur = level & 1;
     const int32_t *F = Fcur_all + b * n;
-    int32_t *Fn = Fnext_all + b * n;
     uint32_t *bm = bmnext_all + b * nw;
-    int32_t *nsz = &bs[b].fsz[nxt];
+    uint32_t *sbm = slotbm_all + b * nsw;
     const int32_t fsz = bs[b].fsz[cur];
     const int lane = __lane_id();
     const int64_t wstride = (int64_t)gridDim.x * kBlock;
     unsigned long long visits = 0;
     for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
          base += wstride) {
-        const WaveRows w = wave_rows(vrec, F, base, fsz);
+        const WaveRows w = wave_rows(vrec, F, base, fsz, false);
         if (lane == 0) visits += w.total;
         for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
             // cross-lane reads happen with every lane active; only memory accesses are masked
@@ -362,19 +367,12 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
             const int32_t jc = inr ? j : w.total - 1;
             const int o = wave_owner(w.pre, jc);
             const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
-            bool fresh = false;
-            int32_t x = 0;
             if (inr) {
-                x = col[ost + (jc - opre)];
-                const uint32_t bit = 1u << (x & 31);
-                fresh = !(atomicOr(bm + (x >> 5), bit) & bit);
-            }
-            const unsigned long long m = __ballot(fresh);
-            if (m) {
-                int32_t basepos = 0;
-                if (lane == 0) basepos = atomicAdd(nsz, (int32_t)__popcll(m));
-                basepos = __shfl(basepos, 0);
-                if (fresh) Fn[basepos + __popcll(m & ((1ull << lane) - 1))] = x;
+                const int32_t e = ost + (jc - opre);
+                const int32_t x = col[e];
+                atomicOr(bm + (x >> 5), 1u << (x & 31));
+                const int32_t slot = slotv[e];
+                if (slot >= 0) atomicOr(sbm + (slot >> 5), 1u << (slot & 31));
             }
         }
     }
@@ -382,31 +380,86 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
-// h_{l+1}(x) = (left fold over Gamma(x) in CSR order of h_l) / d(x) for x in the next support;
-// the fold takes only the terms in the support of h_l, in row order.  Also accumulates the
-// support volume and maximum of h_{l+1}.
+// Next frontier list of each active source: the set bits of its next-level support bitmap,
+// in ascending vertex order (one block per source).
+__global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
+    BatchState *__restrict__ bs, int32_t n, int64_t nw, int32_t level,
+    const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all) {
+    __shared__ uint32_t wave_tot[kWavesPerBlock];
+    __shared__ int32_t carry;
+    const int64_t b = blockIdx.x;
+    if (!bs[b].active) return;
+    const int nxt = (level & 1) ^ 1;
+    const uint32_t *bm = bmnext_all + b * nw;
+    int32_t *Fn = Fnext_all + b * n;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t w0 = 0; w0 < nw; w0 += kBlock) {
+        const int64_t wi = w0 + threadIdx.x;
+        const uint32_t word = wi < nw ? bm[wi] : 0u;
+        const uint32_t cnt = __popc(word);
+        uint32_t inc = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) wave_tot[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) {
+            if (k < wave) before += wave_tot[k];
+            all += wave_tot[k];
+        }
+        int32_t pos = carry + (int32_t)(before + inc - cnt);
+        uint32_t rest = word;
+        while (rest) {
+            const int bit = __builtin_ctz(rest);
+            rest &= rest - 1;
+            Fn[pos++] = (int32_t)(wi * 32 + bit);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += (int32_t)all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bs[b].fsz[nxt] = carry;
+}
+
+constexpr int kFoldWindow = 256;  // LDS values per wavefront in the hub-row fold
+
+// h_{l+1}(x) = (left fold over Gamma(x) in CSR order of h_l) / d(x) for x in the next support.
+// Only terms in the support of h_l are folded (the others are zero), in row order:
+//  - ordinary rows: the wavefront walks the concatenated rows of its 64 vertices and checks
+//    each neighbour in the current support bitmap;
+//  - hub rows: the set bits of the hub-slot bitmap over the row mark exactly the occupied
+//    positions; their values are staged in LDS in row order and folded by one lane.
+// Also accumulates the support volume and maximum of h_{l+1}, and clears the hub-slot bits.
 __global__ __launch_bounds__(kBlock) void pull_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, BatchState *__restrict__ bs,
-    int32_t n, int64_t nw, int32_t level, const double *__restrict__ hcur_all,
-    const uint32_t *__restrict__ bmcur_all, double *__restrict__ hnext_all,
-    const int32_t *__restrict__ Fnext_all, Flags *__restrict__ fl) {
+    int32_t n, int64_t nw, int64_t nsw, int32_t level, const double *__restrict__ hcur_all,
+    const uint32_t *__restrict__ bmcur_all, uint32_t *__restrict__ slotbm_all,
+    double *__restrict__ hnext_all, const int32_t *__restrict__ Fnext_all,
+    Flags *__restrict__ fl) {
+    __shared__ double stage[kWavesPerBlock][kFoldWindow];
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
     const int nxt = (level & 1) ^ 1;
     const double *h = hcur_all + b * n;
     const uint32_t *bm = bmcur_all + b * nw;
+    uint32_t *sbm = slotbm_all + b * nsw;
     double *hn = hnext_all + b * n;
     const int32_t *F = Fnext_all + b * n;
     const int32_t fsz = bs[b].fsz[nxt];
     const int lane = __lane_id();
+    double *lds = stage[threadIdx.x >> 6];
     const int64_t wstride = (int64_t)gridDim.x * kBlock;
     unsigned long long visits = 0, vol = 0;
     double hmax = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
          base += wstride) {
-        const WaveRows w = wave_rows(vrec, F, base, fsz);
+        const WaveRows w = wave_rows(vrec, F, base, fsz, true);
         if (lane == 0) visits += w.total;
-        double acc = 0.0;  // the fold of this lane's own row
+        double acc = 0.0;  // the fold of this lane's own (ordinary) row
         for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
             const int32_t j = j0 + lane;
             const bool inr = j < w.total;
@@ -431,10 +484,75 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
                 if (lane == owner) acc += t;
             }
         }
-        if (base + lane < fsz) {
-            const double hv = acc / (double)w.len;
-            hn[F[base + lane]] = hv;
-            vol += (unsigned long long)w.len;
+        // hub rows of this group, one at a time
+        const int2 rr = (w.x >= 0) ? vrec[w.x] : make_int2(0, 0);
+        unsigned long long hubs = __ballot(rr.y > kHubRow);
+        while (hubs) {
+            const int hl = __builtin_ctzll(hubs);
+            hubs &= hubs - 1;
+            const int32_t a = __shfl(rr.x, hl), d = __shfl(rr.y, hl);
+            const int32_t e1 = a + d;  // row positions [a, e1)
+            const int64_t wfirst = a >> 5, wlast = (e1 - 1) >> 5;
+            double hacc = 0.0;
+            for (int64_t wc = wfirst; wc <= wlast; wc += 64) {
+                const int64_t wi = wc + lane;
+                uint32_t word = 0;
+                if (wi <= wlast) {
+                    word = sbm[wi];
+                    if (wi == wfirst) word &= ~0u << (a & 31);
+                    if (wi == wlast && (e1 & 31)) word &= (1u << (e1 & 31)) - 1u;
+                }
+                const int32_t cnt = __popc(word);
+                int32_t inc = cnt;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int32_t t = __shfl_up(inc, o);
+                    if (lane >= o) inc += t;
+                }
+                const int32_t T = __shfl(inc, 63);
+                const int32_t pos0 = inc - cnt;
+                for (int32_t r0 = 0; r0 < T; r0 += kFoldWindow) {
+                    uint32_t rest = word;
+                    int32_t p = pos0;
+                    while (rest) {
+                        const int bit = __builtin_ctz(rest);
+                        rest &= rest - 1;
+                        if (p >= r0 && p < r0 + kFoldWindow) {
+                            const int32_t y = col[wi * 32 + bit];
+                            lds[p - r0] = h[y];
+                        }
+                        ++p;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (lane == 0) {
+                        const int32_t cntw = min(kFoldWindow, T - r0);
+                        for (int32_t i = 0; i < cntw; ++i) hacc += lds[i];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                // this row's bits are consumed: clear them (boundary words are shared)
+                if (wi <= wlast) {
+                    const bool edge = (wi == wfirst && (a & 31)) || (wi == wlast && (e1 & 31));
+                    if (edge) {
+                        uint32_t mask = ~0u;
+                        if (wi == wfirst) mask &= ~0u << (a & 31);
+                        if (wi == wlast && (e1 & 31)) mask &= (1u << (e1 & 31)) - 1u;
+                        atomicAnd(sbm + wi, ~mask);
+                    } else {
+                        sbm[wi] = 0u;
+                    }
+                }
+            }
+            hacc = __shfl(hacc, 0);
+            if (lane == hl) acc = hacc;
+        }
+        if (w.x >= 0) {
+            const double hv = acc / (double)rr.y;
+            hn[w.x] = hv;
+            vol += (unsigned long long)rr.y;
             hmax = fmax(hmax, hv);
         }
     }
@@ -759,18 +877,21 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
     int64_t budget = p->mem_budget > 0 ? p->mem_budget
                                        : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
     const int64_t nw = ((int64_t)n + 31) / 32;
-    const int64_t per_src = (int64_t)n * (2 * 8 + 2 * 4) + 2 * 4 * nw;
+    const int64_t nsw = (nnz + 31) / 32;
+    const int64_t per_src = (int64_t)n * (2 * 8 + 2 * 4) + 2 * 4 * nw + 4 * nsw;
     int64_t B = p->batch_sources > 0 ? p->batch_sources : std::max<int64_t>(1, budget / per_src);
     B = std::min<int64_t>({B, std::max<int64_t>(ns, 1), 65535});
 
     const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)(B * n) ||
-                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)(B * nw);
+                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)(B * nw) ||
+                      E[B_SLOTBM].bytes < sizeof(uint32_t) * (size_t)(B * nsw);
     SABA_TRY(E[B_HA].ensure(sizeof(double) * B * n));
     SABA_TRY(E[B_HB].ensure(sizeof(double) * B * n));
     SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * B * n));
     SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * B * n));
     SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * B * nw));
     SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * B * nw));
+    SABA_TRY(E[B_SLOTBM].ensure(sizeof(uint32_t) * B * nsw));
     SABA_TRY(E[B_BSRC].ensure(sizeof(int32_t) * B));
     SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * B));
     SABA_TRY(E[B_EBASE].ensure(sizeof(int64_t) * (B + 1)));
@@ -779,6 +900,7 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
     double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
     int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
     uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
+    uint32_t *slotbm = E[B_SLOTBM].as<uint32_t>();
     int32_t *bsrc = E[B_BSRC].as<int32_t>();
     BatchState *bs = E[B_BSTATE].as<BatchState>();
     int64_t *ebase = E[B_EBASE].as<int64_t>();
@@ -789,6 +911,7 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         SABA_HIP_TRY(hipMemsetAsync(hB, 0, E[B_HB].bytes, s));
         SABA_HIP_TRY(hipMemsetAsync(bmA, 0, E[B_BMA].bytes, s));
         SABA_HIP_TRY(hipMemsetAsync(bmB, 0, E[B_BMB].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(slotbm, 0, E[B_SLOTBM].bytes, s));
     }
     g->est_clean = false;  // until this call has cleared everything it touched
 
@@ -816,10 +939,12 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
                                         hipMemcpyDeviceToHost, s));
             SABA_HIP_TRY(hipStreamSynchronize(s));
             if (!any) break;
-            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, level, Fcur,
-                                                  Fnext, bmnext, fl);
-            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, level, hcur,
-                                                bmcur, hnext, Fnext, fl);
+            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, bs, n, nw, nsw,
+                                                  level, Fcur, bmnext, slotbm, fl);
+            compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(bs, n, nw, level, bmnext,
+                                                                    Fnext);
+            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, nsw, level, hcur,
+                                                bmcur, slotbm, hnext, Fnext, fl);
             clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, nw, cur, true, hA, hB, bmA, bmB, FA,
                                                        FB);
             SABA_HIP_TRY(hipGetLastError());

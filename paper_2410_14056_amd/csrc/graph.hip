@@ -149,6 +149,14 @@ __global__ void build_rev_kernel(const int32_t *__restrict__ row_ptr,
     }
 }
 
+__global__ void build_slotv_kernel(const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+                                   const int32_t *__restrict__ rev, int64_t nnz,
+                                   int32_t *__restrict__ slotv) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        slotv[e] = vrec[col[e]].y > kHubRow ? rev[e] : -1;
+}
+
 static int validate_host(const int32_t *rp, const int32_t *ci, int32_t n, int64_t nnz) {
     if (rp[0] != 0 || (int64_t)rp[n] != nnz) {
         set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
@@ -229,6 +237,7 @@ static void destroy_graph(Graph *g) {
     if (g->rev) (void)hipFree(g->rev);
     if (g->canon) (void)hipFree(g->canon);
     if (g->row_of) (void)hipFree(g->row_of);
+    if (g->slotv) (void)hipFree(g->slotv);
     for (auto &b : g->walk_scratch) b.release();
     for (auto &b : g->est) b.release();
     delete g;
@@ -319,6 +328,7 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
         hipMalloc(&g->col_idx, nb) != hipSuccess ||
         hipMalloc(&g->vrec, sizeof(int2) * std::max<int32_t>(n, 1)) != hipSuccess ||
         hipMalloc(&g->rev, nb) != hipSuccess || hipMalloc(&g->row_of, nb) != hipSuccess ||
+        hipMalloc(&g->slotv, nb) != hipSuccess ||
         hipMalloc(&g->canon, sizeof(int32_t) * std::max<size_t>(canon.size(), 1)) != hipSuccess) {
         (void)hipGetLastError();
         set_error("device allocation for the graph failed");
@@ -341,6 +351,7 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
     if (nnz > 0) {
         unsigned blocks = (unsigned)std::min<int64_t>((nnz + 255) / 256, 1 << 20);
         build_rev_kernel<<<blocks, 256, 0, s>>>(g->row_ptr, g->col_idx, g->row_of, nnz, g->rev);
+        build_slotv_kernel<<<blocks, 256, 0, s>>>(g->vrec, g->col_idx, g->rev, nnz, g->slotv);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("graph set-up kernels failed");

@@ -59,11 +59,16 @@ struct Graph {
     int32_t *rev = nullptr;
     int32_t *canon = nullptr;
     int32_t *row_of = nullptr;  // source vertex of each CSR entry
+    int32_t *slotv = nullptr;   // rev[e] if the row of col[e] is longer than kHubRow, else -1
     bool est_clean = false;     // estimator scratch vectors are all zero
     // reusable scratch
     DevBuf walk_scratch[4];
     DevBuf est[32];
 };
+
+// Rows longer than this are "hub rows": the estimator finds their terms through a bitmap
+// over CSR positions instead of scanning them.
+constexpr int32_t kHubRow = 256;
 
 int check_graph(const saba_graph *g);
 inline Graph *G(saba_graph *g) { return reinterpret_cast<Graph *>(g); }

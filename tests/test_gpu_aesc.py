@@ -150,3 +150,47 @@ def test_config1_parity_and_eps(saba, orc):
     print(f"config1: max err {err.max():.4g} mean {err.mean():.4g} sum {o_gpu['sc'].sum().item():.2f}"
           f" (n-1={g.n - 1}) steps {st['walk_steps']}", flush=True)
     assert err.max() <= 0.3
+
+
+def _hub_graph(seed=5):
+    # Erdos-Renyi core plus three hubs of degree 300 / 500 / 900, so that rows longer than the
+    # hub threshold (256) occur in every level of the push
+    rng = np.random.default_rng(seed)
+    base = graphgen.er_gnm(1500, 4500, seed)
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    u, v = [rows], [base.col_idx.astype(np.int64)]
+    for hub, deg in ((0, 300), (1, 500), (2, 900)):
+        nb = rng.choice(np.arange(3, base.n), size=deg, replace=False)
+        u.append(np.full(deg, hub))
+        v.append(nb)
+    g = graphgen.canonical_csr(np.concatenate(u), np.concatenate(v), base.n)
+    g = graphgen.largest_component(g)
+    return g, graphgen.spectral_lambda(g)
+
+
+@pytest.mark.parametrize("eps,kw", [(0.2, {}), (0.1, {"batch_sources": 97}), (0.3, {"push_all": True})])
+def test_hub_rows_match_oracle(saba, orc, eps, kw):
+    g, lam = _hub_graph()
+    assert np.diff(g.row_ptr).max() > 256
+    print(f"hub parity n={g.n} m={g.m} dmax={np.diff(g.row_ptr).max()} eps={eps} {kw}", flush=True)
+    sg = saba.SabaGraph.from_graph(g)
+    o_gpu, _ = saba.aesc_edge_stats(sg, eps, lam, seed=3, **kw)
+    okw = {k: v for k, v in kw.items() if k != "batch_sources"}
+    sc_o, o_orc = orc.aesc(g, eps, lam, seed=3, **okw)
+    _compare(o_gpu, o_orc, o_gpu["sc"].cpu().numpy(), sc_o)
+
+
+def test_chung_lu_query_matches_oracle(saba, orc):
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(30000, 10, 2.3, 4))
+    lam = graphgen.spectral_lambda(g)
+    deg = np.diff(g.row_ptr)
+    ce = graphgen.canonical_edges(g)
+    hub_edges = np.flatnonzero(np.maximum(deg[ce[:, 0]], deg[ce[:, 1]]) > 256)
+    pick = np.concatenate([hub_edges[:20], np.random.default_rng(2).choice(g.m, 20, replace=False)])
+    q = np.ascontiguousarray(ce[pick])
+    print(f"chung-lu query n={g.n} m={g.m} dmax={deg.max()} q={len(q)}", flush=True)
+    sg = saba.SabaGraph.from_graph(g)
+    sq, _ = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.2, lam, 11)
+    so, _ = orc.aesc(g, 0.2, lam, seed=11, query=q)
+    np.testing.assert_allclose(sq.cpu().numpy(), so, rtol=RTOL, atol=1e-15)
