@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["all", "walks", "aesc"], default="all")
+    ap.add_argument("--workload", choices=["all", "walks", "aesc", "copy"], default="all")
     ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--spread", type=int, default=0)
@@ -240,6 +240,18 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     saba.load()
+    if args.workload == "copy":
+        # counter calibration: one device-to-device copy of 1 GiB (reads and writes 1 GiB)
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"workload": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "seconds": dt}), flush=True)
+        return
     out = {"metric": METRIC, "value": None, "unit": "walk-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
