@@ -198,8 +198,8 @@ def bench_aesc(args, saba, torch, np):
         t1 = time.perf_counter()
         oracle.aesc(g, args.aesc_eps, lam, 1, query=q[:nq], nthreads=cores)
         dq = time.perf_counter() - t1
-        if dq < 8.0:
-            nq = int(min(k, nq * max(1.0, 12.0 / max(dq, 1e-3))))
+        if dq < 4.0:
+            nq = int(min(k, nq * max(1.0, 5.0 / max(dq, 1e-3))))
             t1 = time.perf_counter()
             oracle.aesc(g, args.aesc_eps, lam, 1, query=q[:nq], nthreads=cores)
             dq = time.perf_counter() - t1
@@ -210,12 +210,47 @@ def bench_aesc(args, saba, torch, np):
     return out
 
 
+def bench_c1(args, saba, torch, np):
+    """Config 1: all edges of ER n=2000, m=8000, seed 1 (largest component), eps=0.3, plain walks."""
+    import graphgen
+    g = graphgen.largest_component(graphgen.er_gnm(2000, 8000, 1))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    saba.aesc(sg, 0.3, lam, 1)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        sc, st = saba.aesc(sg, 0.3, lam, 1)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    out = {"workload": "er_n2000_m8000_s1_lcc_eps0.3_all_edges", "n": g.n, "m": g.m,
+           "latency_ms_median": med * 1e3, "latency_ms_min": min(times) * 1e3,
+           "edges_per_s": g.m / med, "walk_steps": st["walk_steps"],
+           "push_edge_visits": st["push_edge_visits"],
+           "sum_sc": float(sc.sum().item()), "n_minus_1": g.n - 1}
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        oracle.aesc(g, 0.3, lam, 1, nthreads=1)
+        d1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.aesc(g, 0.3, lam, 1, nthreads=cores)
+        dn = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": g.m / dn, "unit": "edges/s", "cores": cores,
+                               "kind": "oracle", "single_thread_edges_per_s": g.m / d1,
+                               "sample": "all edges of the same graph"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["all", "walks", "aesc", "copy"], default="all")
+    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "copy"], default="all")
     ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--spread", type=int, default=0)
@@ -264,6 +299,12 @@ def main():
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = walks_cpu_baseline(g, args.length, 1)
         del g
+    if args.workload in ("all", "c1"):
+        out["c1"] = bench_c1(args, saba, torch, np)
+        if args.workload == "c1":
+            out.update({"value": out["c1"]["edges_per_s"], "unit": "edges/s", "dtype": "f64",
+                        "ms_per_step": out["c1"]["latency_ms_median"],
+                        "config": {"workload": out["c1"]["workload"]}})
     if args.workload in ("all", "aesc"):
         a = bench_aesc(args, saba, torch, np)
         out["aesc"] = a

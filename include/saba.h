@@ -61,8 +61,9 @@ typedef struct {
     int64_t m;          /* undirected edges */
     int32_t d_max;      /* maximum degree */
     int32_t n_isolated; /* vertices of degree 0 */
-    int32_t connected;  /* 1 / 0 */
+    int32_t connected;  /* 1 / 0 (0 when the handle holds several graphs) */
     int32_t bipartite;  /* 1 / 0 */
+    int32_t ngraphs;    /* graphs held side by side (saba_graph_create_multi) */
 } saba_graph_info_t;
 
 typedef struct {
@@ -106,6 +107,24 @@ typedef struct {
     int64_t mem_budget;    /* bytes of per-batch scratch (0: 8 GiB or 40% of free memory) */
 } saba_aesc_params;
 
+/* One estimator request of saba_aesc_batch. */
+typedef struct {
+    int32_t graph;            /* index of the graph in the handle (0 for a single graph) */
+    int32_t reserved;
+    saba_aesc_params params;  /* eps, delta, lambda, seed, group, spread, tau_cap, tilde_tau_max,
+                                 push_all (the execution fields are taken from the options) */
+    const int32_t *d_edges;   /* [2q] query pairs in the graph's own vertex ids (device) */
+    int64_t q;                /* number of pairs, or -1 for all edges of the graph */
+    double *d_sc;             /* [q] results, or [m of the graph] in canonical order when q = -1 */
+} saba_aesc_request;
+
+/* Execution options of saba_aesc_batch; none of them changes a result. */
+typedef struct {
+    int64_t mem_budget;    /* bytes of per-batch scratch (0: 8 GiB or 40% of free memory) */
+    int32_t batch_sources; /* cap on instances per batch (0: from mem_budget) */
+    int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
+} saba_batch_options;
+
 /* ABI version (SABA_ABI_VERSION). */
 int saba_version(void);
 
@@ -123,6 +142,17 @@ const char *saba_last_error(void);
  */
 int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz,
                       uint32_t flags, void *stream, saba_graph **out);
+
+/*
+ * Upload several graphs at once, side by side (a block-diagonal CSR): graph k owns the
+ * vertices vertex_offsets[k] .. vertex_offsets[k+1]-1 (host array of ngraphs + 1 entries,
+ * from 0 to n) and no edge may leave its graph (SABA_E_GRAPH).  Otherwise as
+ * saba_graph_create.  Estimator requests name a graph by k and use its own vertex ids, and
+ * each result equals the one computed on a handle holding that graph alone.
+ */
+int saba_graph_create_multi(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                            int64_t nnz, int32_t ngraphs, const int32_t *vertex_offsets,
+                            uint32_t flags, void *stream, saba_graph **out);
 
 /* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
 int saba_graph_destroy(saba_graph *g);
@@ -179,6 +209,17 @@ int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc,
                          int32_t *d_ttau, int64_t *d_nreq, double *d_D, double *d_MC,
                          int64_t *d_vis0, int64_t *d_vis1, double *d_g, saba_stats *stats,
                          void *stream);
+
+/*
+ * Several estimator requests evaluated together (Alg. 1 for each): batched multi-graph
+ * estimation and the shared launches of the query server.  Requests with equal graph and
+ * parameters share their source instances; every instance of every request runs in the same
+ * batches and walk launches.  Each request's d_sc receives exactly what saba_aesc (q = -1) or
+ * saba_aesc_query (q >= 0) returns for that graph and parameters alone.  opt may be NULL.
+ * Errors as saba_aesc / saba_aesc_query; no output is written when a request is invalid.
+ */
+int saba_aesc_batch(saba_graph *g, const saba_aesc_request *reqs, int32_t nreq,
+                    const saba_batch_options *opt, saba_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,7 @@ from ._binding import (  # noqa: F401
     SabaGraph,
     WalkResult,
     aesc,
+    aesc_batch,
     aesc_edge_stats,
     aesc_query,
     load,

@@ -38,7 +38,8 @@ class SabaError(RuntimeError):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("m", ctypes.c_int64),
                 ("d_max", ctypes.c_int32), ("n_isolated", ctypes.c_int32),
-                ("connected", ctypes.c_int32), ("bipartite", ctypes.c_int32)]
+                ("connected", ctypes.c_int32), ("bipartite", ctypes.c_int32),
+                ("ngraphs", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,9 +68,20 @@ class AescParams(ctypes.Structure):
                 ("time_kernels", ctypes.c_int32), ("mem_budget", ctypes.c_int64)]
 
 
+class AescRequest(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("reserved", ctypes.c_int32), ("params", AescParams),
+                ("d_edges", ctypes.c_void_p), ("q", ctypes.c_int64), ("d_sc", ctypes.c_void_p)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("batch_sources", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32)]
+
+
 # every symbol the header declares
-EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_destroy",
-           "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query", "saba_aesc_edge_stats"]
+EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_create_multi",
+           "saba_graph_destroy", "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
+           "saba_aesc_edge_stats", "saba_aesc_batch"]
 
 _lib = None
 
@@ -86,6 +98,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_version.restype = ctypes.c_int
     L.saba_last_error.restype = ctypes.c_char_p
     L.saba_graph_create.argtypes = [P, P, i32, i64, u32, P, ctypes.POINTER(P)]
+    L.saba_graph_create_multi.argtypes = [P, P, i32, i64, i32, P, u32, P, ctypes.POINTER(P)]
     L.saba_graph_destroy.argtypes = [P]
     L.saba_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
     L.saba_walks.argtypes = [P, ctypes.POINTER(WalkParams), P, P, ctypes.POINTER(Stats), P]
@@ -93,6 +106,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_aesc_query.argtypes = [P, ctypes.POINTER(AescParams), P, i64, P, ctypes.POINTER(Stats), P]
     L.saba_aesc_edge_stats.argtypes = [P, ctypes.POINTER(AescParams), P, P, P, P, P, P, P, P, P,
                                        ctypes.POINTER(Stats), P]
+    L.saba_aesc_batch.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions), ctypes.POINTER(Stats), P]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
     _lib = L
@@ -134,6 +148,35 @@ class SabaGraph:
     @classmethod
     def from_graph(cls, g, **kw):
         return cls(g.row_ptr, g.col_idx, **kw)
+
+    @classmethod
+    def from_graphs(cls, graphs, trusted: bool = False, stream=None):
+        """Several graphs side by side in one handle (saba_graph_create_multi); graph k keeps
+        its own vertex ids in estimator requests."""
+        lib = load()
+        offs = [0]
+        rps, cis = [], []
+        nnz = 0
+        for g in graphs:
+            rps.append(np.asarray(g.row_ptr[:-1], dtype=np.int64) + nnz)
+            cis.append(np.asarray(g.col_idx, dtype=np.int64) + offs[-1])
+            nnz += int(g.col_idx.size)
+            offs.append(offs[-1] + int(g.row_ptr.size - 1))
+        rp = np.ascontiguousarray(np.concatenate(rps + [np.array([nnz])]), dtype=np.int32)
+        ci = np.ascontiguousarray(np.concatenate(cis) if cis else np.zeros(0), dtype=np.int32)
+        off = np.ascontiguousarray(offs, dtype=np.int32)
+        self = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        flags = SABA_TRUSTED if trusted else 0
+        _check(lib.saba_graph_create_multi(rp.ctypes.data_as(ctypes.c_void_p),
+                                           ci.ctypes.data_as(ctypes.c_void_p), offs[-1], nnz,
+                                           len(graphs), off.ctypes.data_as(ctypes.c_void_p), flags,
+                                           _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = offs[-1]
+        self.nnz = nnz
+        self.graph_m = [int(g.col_idx.size) // 2 for g in graphs]
+        return self
 
     @property
     def handle(self):
@@ -234,3 +277,40 @@ def aesc_edge_stats(graph: SabaGraph, eps: float, lam: float, seed: int, device=
         _ptr(out["nreq"]), _ptr(out["D"]), _ptr(out["MC"]), _ptr(out["vis0"]), _ptr(out["vis1"]),
         _ptr(out["g"]), ctypes.byref(st), _stream_ptr(stream)))
     return out, st.as_dict()
+
+
+def aesc_batch(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: int = 0,
+               time_kernels: bool = False, device="cuda", stream=None):
+    """saba_aesc_batch.  Each request is a dict with keys graph (index), eps, lam, seed and
+    optionally edges (int32 [q, 2] device tensor of the graph's own ids; omitted = all edges),
+    m (edge count of the graph, needed for all-edges requests) and the estimator keywords of
+    aesc().  Returns (list of result tensors, stats)."""
+    lib = load()
+    arr = (AescRequest * max(1, len(requests)))()
+    outs = []
+    keep = []
+    for i, r in enumerate(requests):
+        kw = {k: v for k, v in r.items() if k not in ("graph", "eps", "lam", "seed", "edges", "m")}
+        p = _aesc_params(r["eps"], r["lam"], r["seed"], **kw)
+        edges = r.get("edges")
+        if edges is None:
+            q = -1
+            out = torch.empty(int(r["m"]), dtype=torch.float64, device=device)
+            eptr = None
+        else:
+            assert edges.is_cuda and edges.dtype == torch.int32 and edges.is_contiguous()
+            q = edges.numel() // 2
+            out = torch.empty(q, dtype=torch.float64, device=edges.device)
+            eptr = edges.data_ptr()
+            keep.append(edges)
+        arr[i].graph = int(r.get("graph", 0))
+        arr[i].params = p
+        arr[i].d_edges = eptr
+        arr[i].q = q
+        arr[i].d_sc = out.data_ptr() if out.numel() else None
+        outs.append(out)
+    opt = BatchOptions(int(mem_budget), int(batch_sources), int(bool(time_kernels)))
+    st = Stats()
+    _check(lib.saba_aesc_batch(graph.handle, ctypes.cast(arr, ctypes.c_void_p), len(requests),
+                               ctypes.byref(opt), ctypes.byref(st), _stream_ptr(stream)))
+    return outs, st.as_dict()

@@ -12,22 +12,34 @@
 //   MC_st    sum over pairs k of X_k = sum_b h_ttau(W^s_k[b]) - sum_b h_ttau(W^t_k[b]), b = 1..L;
 // and g(s,t) = (D_st + MC_st / n_st) / d_s, SC(u,v) = g(u,v) + g(v,u).
 //
-// Work layout: sources are processed in batches that fit a memory budget.  Each source of a
-// batch owns dense FP64 h vectors (two levels), frontier lists and support bitmaps (two
-// levels); they are cleared sparsely through the frontier lists, so they are zeroed only
-// once.  The deterministic levels run level-synchronously over the whole batch.  A wavefront
-// walks the concatenated rows of 64 frontier vertices in chunks of 64 entries, so hub rows are
-// split across lanes; the pull folds only the terms whose vertex is in the support bitmap (a
-// zero term leaves a sum of non-negative numbers unchanged), in row order, so every h value is
-// bit-identical to the sequential left fold over the whole row.  The walk pairs of
-// all directed edges of the batch are cut into chunks of 64 walks; one wavefront walks one
-// chunk and reduces it in a fixed butterfly order, and each edge sums its chunks in chunk
+// Work items.  A call evaluates a set of requests; each request names a graph of the handle
+// and a parameter set (eps, delta, lambda, seed, grouping).  An *instance* is a (source vertex,
+// parameter set) pair that some request needs, and an *instance edge* is a directed edge out
+// of an instance's vertex.  Everything an instance computes depends only on its graph, its
+// parameters and the vertex, and keys and hashes use the graph's own vertex ids, so a result
+// is the same whether its request runs alone or batched with others, on a handle holding one
+// graph or many.
+//
+// Work layout.  Instances are processed in batches that fit a memory budget.  Each instance of
+// a batch owns a slot: dense FP64 h vectors (two levels), frontier lists and support bitmaps
+// (two levels) sized to its graph, and a bitmap over its graph's CSR positions for hub rows.
+// All of these are cleared sparsely through the frontier lists, so they are zeroed only once.
+// The deterministic levels run level-synchronously over the whole batch.  A wavefront walks
+// the concatenated rows of 64 frontier vertices in chunks of 64 entries, so long rows are split
+// across lanes; the pull folds only the terms whose vertex is in the support bitmap (a zero
+// term leaves a sum of non-negative numbers unchanged), in row order, so every h value is
+// bit-identical to the sequential left fold over the whole row.  The walk pairs of all instance
+// edges of the batch are cut into chunks of 64 walks; one persistent launch covers all of them,
+// a wavefront reduces a chunk in a fixed butterfly order, and each edge sums its chunks in chunk
 // order, so results do not depend on the launch shape.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
 
 #include "saba_internal.hpp"
 
@@ -36,23 +48,47 @@ namespace saba {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kChunk = 64;  // walks per wavefront chunk
+constexpr int kWalkGrid = 2048;
 
-enum : int32_t { kErrOverflow = 1, kErrNotEdge = 2 };
+enum : int32_t { kErrOverflow = 1 };
 
 // scratch slots in Graph::est
 enum {
-    B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G, B_TTAU_SRC, B_MAXTAU_SRC, B_WANT, B_SRCMARK,
-    B_SRCPOS, B_LIST, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_BSRC, B_BSTATE, B_EBASE, B_CHUNKS,
-    B_COFF, B_PART, B_SCAN, B_FLAGS, B_QE, B_DEG64, B_COUNT
+    B_PSET, B_SLOT, B_EB, B_BSTATE, B_WANT, B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G,
+    B_TTAU, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_CHUNKS, B_COFF, B_PART, B_SCAN,
+    B_FLAGS, B_PAIRS, B_COUNT
+};
+static_assert(B_COUNT <= 32, "Graph::est holds 32 buffers");
+
+struct PSet {  // one parameter set of a call
+    double lambda, eps, c;
+    uint32_t seed, G, S;
+    int32_t tau_cap, tilde_tau_max, push_all;
 };
 
-struct BatchState {  // one per source of a batch; [2] entries are indexed by level parity
+struct Slot {  // one instance of a batch
+    int64_t hoff;   // first element of its dense vectors and frontier lists
+    int64_t bmoff;  // first word of its vertex bitmaps
+    int64_t sboff;  // first word of its CSR-position bitmap
+    int64_t ie;     // first instance edge
+    int64_t inst;   // instance index
+    int32_t v;      // source vertex (handle ids)
+    int32_t p;      // parameter set
+    int32_t goff;   // first vertex of its graph
+    int32_t gn;     // vertices of its graph
+    int32_t gpos;   // first CSR position of its graph
+    int32_t pad;
+};
+
+struct BatchState {  // one per slot; [2] entries are indexed by level parity
     int32_t active;
     int32_t finalbuf;
     int32_t fsz[2];                 // frontier (support) sizes
     unsigned long long vol[2];      // support volume sum of d(x)
     unsigned long long hmaxbits[2]; // max of h over the support, as IEEE bits (h > 0)
     double hmax;                    // max of h_ttau once the source has stopped
+    int32_t maxtau;
+    int32_t ttau;
 };
 
 struct Flags {
@@ -110,107 +146,38 @@ __device__ __forceinline__ long long nwalks(int32_t L, double hmax, int32_t ds, 
 }
 
 // ------------------------------------------------------------ kernels
-// tau for every directed entry of the listed sources' rows (all vertices when list == NULL),
-// and the largest tau of each source.
-__global__ __launch_bounds__(kBlock) void tau_kernel(const int2 *__restrict__ vrec,
-                                                     const int32_t *__restrict__ col, int32_t n,
-                                                     double lambda, double eps, int32_t cap,
-                                                     int32_t *__restrict__ tau,
-                                                     int32_t *__restrict__ maxtau,
-                                                     Flags *__restrict__ fl) {
-    const int lane = __lane_id();
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t s = wid; s < n; s += nw) {
-        const int2 r = vrec[s];
-        int mx = 0, capped = 0;
-        for (int32_t i = lane; i < r.y; i += 64) {
-            const int32_t t = col[r.x + i];
-            const int32_t tv = tau_of(r.y, vrec[t].y, lambda, eps, cap);
-            tau[r.x + i] = tv;
-            mx = max(mx, tv);
-            capped |= (tv >= cap) ? 1 : 0;
-        }
-        mx = wave_max_i(mx);
-        capped = wave_max_i(capped);
-        if (lane == 0) {
-            maxtau[s] = mx;
-            atomicMax(&fl->max_tau, mx);
-            if (capped) atomicOr(&fl->warnings, 1);
-        }
-    }
-}
-
-__global__ void iota_kernel(int32_t *__restrict__ a, int32_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = (int32_t)i;
-}
-
-__device__ __forceinline__ int32_t find_entry(const int2 *__restrict__ vrec,
-                                              const int32_t *__restrict__ col, int32_t u,
-                                              int32_t v) {
-    const int2 r = vrec[u];
-    int32_t lo = r.x, hi = r.x + r.y;
-    while (lo < hi) {
-        const int32_t mid = lo + ((hi - lo) >> 1);
-        if (col[mid] < v)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return (lo < r.x + r.y && col[lo] == v) ? lo : -1;
-}
-
-// Query edges: locate both directed entries, mark them wanted and their endpoints as sources.
-__global__ void query_mark_kernel(const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
-                                  int32_t n, const int32_t *__restrict__ edges, int64_t q,
-                                  uint8_t *__restrict__ want, long long *__restrict__ srcmark,
-                                  int32_t *__restrict__ qe, Flags *__restrict__ fl) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = edges[2 * j], v = edges[2 * j + 1];
-        int32_t euv = -1, evu = -1;
-        if (u >= 0 && u < n && v >= 0 && v < n) {
-            euv = find_entry(vrec, col, u, v);
-            evu = find_entry(vrec, col, v, u);
-        }
-        if (euv < 0 || evu < 0) {
-            atomicOr(&fl->err, kErrNotEdge);
-            qe[2 * j] = qe[2 * j + 1] = 0;
-            continue;
-        }
-        want[euv] = 1;
-        want[evu] = 1;
-        srcmark[u] = 1;
-        srcmark[v] = 1;
-        qe[2 * j] = euv;
-        qe[2 * j + 1] = evu;
-    }
-}
-
-__global__ void compact_kernel(const long long *__restrict__ mark, const int64_t *__restrict__ pos,
-                               int32_t n, int32_t *__restrict__ list) {
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x)
-        if (mark[s]) list[pos[s]] = (int32_t)s;
-}
-
-// Level 0 of every source of the batch: h_0 = e_s, support {s}; per-edge accumulators reset.
+// Level 0 of every instance of the batch: h_0 = e_s, support {s}; tau of its edges, per-edge
+// accumulators reset.
 __global__ __launch_bounds__(kBlock) void batch_init_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ list, int64_t i0, int32_t nb,
-    int32_t n, int64_t nw, int32_t *__restrict__ bsrc, BatchState *__restrict__ bs,
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    const PSet *__restrict__ psets, int32_t nb, BatchState *__restrict__ bs,
     double *__restrict__ hA, int32_t *__restrict__ FA, uint32_t *__restrict__ bmA,
-    double *__restrict__ D, long long *__restrict__ nreq, double *__restrict__ MC,
-    unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
-    long long *__restrict__ deg64) {
+    int32_t *__restrict__ tau, double *__restrict__ D, long long *__restrict__ nreq,
+    double *__restrict__ MC, unsigned long long *__restrict__ vis0,
+    unsigned long long *__restrict__ vis1, Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb) return;
-    const int32_t s = list[i0 + b];
-    const int2 r = vrec[s];
+    const Slot sl = slots[b];
+    const PSet ps = psets[sl.p];
+    const int2 r = vrec[sl.v];
+    int mx = 0, capped = 0;
+    for (int32_t i = lane; i < r.y; i += 64) {
+        const int64_t ie = sl.ie + i;
+        const int32_t tv = tau_of(r.y, vrec[col[r.x + i]].y, ps.lambda, ps.eps, ps.tau_cap);
+        tau[ie] = tv;
+        mx = max(mx, tv);
+        capped |= tv >= ps.tau_cap ? 1 : 0;
+        D[ie] = 0.0;
+        nreq[ie] = 0;
+        MC[ie] = 0.0;
+        vis0[ie] = 0;
+        vis1[ie] = 0;
+    }
+    mx = wave_max_i(mx);
+    capped = wave_max_i(capped);
     if (lane == 0) {
-        bsrc[b] = s;
+        const int32_t sl_local = sl.v - sl.goff;
         BatchState st;
         st.active = 1;
         st.finalbuf = 0;
@@ -221,48 +188,44 @@ __global__ __launch_bounds__(kBlock) void batch_init_kernel(
         st.hmaxbits[0] = (unsigned long long)__double_as_longlong(1.0);
         st.hmaxbits[1] = 0;
         st.hmax = 0.0;
+        st.maxtau = mx;
+        st.ttau = 0;
         bs[b] = st;
-        hA[b * n + s] = 1.0;
-        FA[b * n] = s;
-        bmA[b * nw + (s >> 5)] = 1u << (s & 31);
-        deg64[b] = r.y;
-    }
-    for (int32_t i = lane; i < r.y; i += 64) {
-        D[r.x + i] = 0.0;
-        nreq[r.x + i] = 0;
-        MC[r.x + i] = 0.0;
-        vis0[r.x + i] = 0;
-        vis1[r.x + i] = 0;
+        hA[sl.hoff + sl_local] = 1.0;
+        FA[sl.hoff] = sl.v;
+        bmA[sl.bmoff + (sl_local >> 5)] = 1u << (sl_local & 31);
+        atomicMax(&fl->max_tau, mx);
+        if (capped) atomicOr(&fl->warnings, 1);
     }
 }
 
-// Alg. 1 loop test at level l for each active source: with the support volume and maximum of
-// h_l (accumulated when h_l was built), add the deterministic terms of level l and compare the
-// volume with the walk pairs that would still be needed.
+// Alg. 1 loop test at level l for each active instance: with the support volume and maximum
+// of h_l (accumulated when h_l was built), add the deterministic terms of level l and compare
+// the volume with the walk pairs that would still be needed.
 __global__ __launch_bounds__(kBlock) void level_decide_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ bsrc, BatchState *__restrict__ bs, int32_t nb, int32_t n,
-    int32_t level, const double *__restrict__ hcur_all, const int32_t *__restrict__ tau,
-    const int32_t *__restrict__ maxtau, double *__restrict__ D, int32_t *__restrict__ ttau_src,
-    double c, int32_t push_all, int32_t tilde_tau_max, Flags *__restrict__ fl) {
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    const PSet *__restrict__ psets, BatchState *__restrict__ bs, int32_t nb, int32_t level,
+    const double *__restrict__ hcur_all, const int32_t *__restrict__ tau, double *__restrict__ D,
+    int32_t *__restrict__ ttau_inst, Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb || !bs[b].active) return;
     const int cur = level & 1, nxt = cur ^ 1;
-    const int32_t s = bsrc[b];
-    const double *h = hcur_all + b * n;
+    const Slot sl = slots[b];
+    const PSet ps = psets[sl.p];
+    const double *h = hcur_all + sl.hoff;  // indexed by graph-local vertex ids
     const long long vol = (long long)bs[b].vol[cur];
     const double hmax = __longlong_as_double((long long)bs[b].hmaxbits[cur]);
-    const int2 r = vrec[s];
-    const double hs = h[s];
+    const int2 r = vrec[sl.v];
+    const double hs = h[sl.v - sl.goff];
     long long need = 0;
     int ovf = 0;
     for (int32_t i = lane; i < r.y; i += 64) {
-        const int32_t e = r.x + i;
-        const int32_t te = tau[e];
-        if (level <= te) D[e] += hs - h[col[e]];
+        const int64_t ie = sl.ie + i;
+        const int32_t te = tau[ie];
+        if (level <= te) D[ie] += hs - h[col[r.x + i] - sl.goff];
         if (te > level) {
-            const long long w = nwalks(te - level, hmax, r.y, c);
+            const long long w = nwalks(te - level, hmax, r.y, ps.c);
             if (w < 0)
                 ovf = 1;
             else
@@ -273,14 +236,15 @@ __global__ __launch_bounds__(kBlock) void level_decide_kernel(
     ovf = wave_max_i(ovf);
     if (lane == 0) {
         if (ovf) atomicOr(&fl->err, kErrOverflow);
-        bool stop = push_all ? (level >= maxtau[s]) : !(vol < need);
-        if (tilde_tau_max >= 0 && level >= tilde_tau_max) stop = true;
+        bool stop = ps.push_all ? (level >= bs[b].maxtau) : !(vol < need);
+        if (ps.tilde_tau_max >= 0 && level >= ps.tilde_tau_max) stop = true;
         if (ovf) stop = true;
         if (stop) {
             bs[b].active = 0;
             bs[b].finalbuf = cur;
             bs[b].hmax = hmax;
-            ttau_src[s] = level;
+            bs[b].ttau = level;
+            ttau_inst[sl.inst] = level;
             atomicMax(&fl->max_ttau, level);
         } else {
             // level l + 1 is built into the buffers of parity nxt (cleared after level l - 1)
@@ -292,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void level_decide_kernel(
     }
 }
 
-// Rows of the 64 frontier entries [base, base + 64) of one source, as seen by each lane:
+// Rows of the 64 frontier entries [base, base + 64) of one instance, as seen by each lane:
 // its own row and the exclusive prefix of the row lengths over the wavefront.  Hub rows
 // count as empty when `skip_hubs` is set (they are handled separately).
 struct WaveRows {
@@ -318,7 +282,9 @@ __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
         const int32_t t = __shfl_up(inc, o);
         if (lane >= o) inc += t;
     }
-    w.total = __shfl(inc, 63);
+    // readfirstlane makes the loop bounds derived from the total provably wave-uniform, so the
+    // compiler keeps the wavefront converged around the cross-lane operations in those loops
+    w.total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63));
     w.pre = inc - w.len;
     return w;
 }
@@ -327,7 +293,7 @@ __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
 // which is always a lane whose row contains entry j.
 __device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
     int lo = 0, hi = 64;
-    while (hi - lo > 1) {
+    for (int it = 0; it < 6; ++it) {  // 64 -> 1 candidates: a fixed, uniform trip count
         const int mid = (lo + hi) >> 1;
         if (__shfl(pre, mid) <= j)
             lo = mid;
@@ -339,19 +305,20 @@ __device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
 
 // Push the current support one hop: set the bit of every neighbour in the next level's
 // support bitmap and, for neighbours with hub rows, the bit of the reverse CSR position in
-// the hub-slot bitmap.  Fire-and-forget atomics; the next frontier list is built from the
-// bitmap afterwards, in ascending vertex order.
+// the slot's CSR-position bitmap.  Fire-and-forget atomics; the next frontier list is built
+// from the bitmap afterwards, in ascending vertex order.
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ slotv, BatchState *__restrict__ bs, int32_t n, int64_t nw,
-    int64_t nsw, int32_t level, const int32_t *__restrict__ Fcur_all,
-    uint32_t *__restrict__ bmnext_all, uint32_t *__restrict__ slotbm_all, Flags *__restrict__ fl) {
+    const int32_t *__restrict__ slotv, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
+    int32_t level, const int32_t *__restrict__ Fcur_all, uint32_t *__restrict__ bmnext_all,
+    uint32_t *__restrict__ slotbm_all, Flags *__restrict__ fl) {
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
     const int cur = level & 1;
-    const int32_t *F = Fcur_all + b * n;
-    uint32_t *bm = bmnext_all + b * nw;
-    uint32_t *sbm = slotbm_all + b * nsw;
+    const Slot sl = slots[b];
+    const int32_t *F = Fcur_all + sl.hoff;
+    uint32_t *bm = bmnext_all + sl.bmoff;
+    uint32_t *sbm = slotbm_all + sl.sboff;
     const int32_t fsz = bs[b].fsz[cur];
     const int lane = __lane_id();
     const int64_t wstride = (int64_t)gridDim.x * kBlock;
@@ -369,10 +336,13 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
             const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
             if (inr) {
                 const int32_t e = ost + (jc - opre);
-                const int32_t x = col[e];
+                const int32_t x = col[e] - sl.goff;
                 atomicOr(bm + (x >> 5), 1u << (x & 31));
                 const int32_t slot = slotv[e];
-                if (slot >= 0) atomicOr(sbm + (slot >> 5), 1u << (slot & 31));
+                if (slot >= 0) {
+                    const int32_t ls = slot - sl.gpos;
+                    atomicOr(sbm + (ls >> 5), 1u << (ls & 31));
+                }
             }
         }
     }
@@ -380,18 +350,20 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
-// Next frontier list of each active source: the set bits of its next-level support bitmap,
-// in ascending vertex order (one block per source).
+// Next frontier list of each active instance: the set bits of its next-level support bitmap,
+// in ascending vertex order (one block per instance).
 __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
-    BatchState *__restrict__ bs, int32_t n, int64_t nw, int32_t level,
+    const Slot *__restrict__ slots, BatchState *__restrict__ bs, int32_t level,
     const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all) {
     __shared__ uint32_t wave_tot[kWavesPerBlock];
     __shared__ int32_t carry;
     const int64_t b = blockIdx.x;
     if (!bs[b].active) return;
     const int nxt = (level & 1) ^ 1;
-    const uint32_t *bm = bmnext_all + b * nw;
-    int32_t *Fn = Fnext_all + b * n;
+    const Slot sl = slots[b];
+    const uint32_t *bm = bmnext_all + sl.bmoff;
+    int32_t *Fn = Fnext_all + sl.hoff;
+    const int64_t nw = ((int64_t)sl.gn + 31) / 32;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -416,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
         while (rest) {
             const int bit = __builtin_ctz(rest);
             rest &= rest - 1;
-            Fn[pos++] = (int32_t)(wi * 32 + bit);
+            Fn[pos++] = sl.goff + (int32_t)(wi * 32 + bit);
         }
         __syncthreads();
         if (threadIdx.x == 0) carry += (int32_t)all;
@@ -431,12 +403,12 @@ constexpr int kFoldWindow = 256;  // LDS values per wavefront in the hub-row fol
 // Only terms in the support of h_l are folded (the others are zero), in row order:
 //  - ordinary rows: the wavefront walks the concatenated rows of its 64 vertices and checks
 //    each neighbour in the current support bitmap;
-//  - hub rows: the set bits of the hub-slot bitmap over the row mark exactly the occupied
+//  - hub rows: the set bits of the CSR-position bitmap over the row mark exactly the occupied
 //    positions; their values are staged in LDS in row order and folded by one lane.
-// Also accumulates the support volume and maximum of h_{l+1}, and clears the hub-slot bits.
+// Also accumulates the support volume and maximum of h_{l+1}, and clears the hub-row bits.
 __global__ __launch_bounds__(kBlock) void pull_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, BatchState *__restrict__ bs,
-    int32_t n, int64_t nw, int64_t nsw, int32_t level, const double *__restrict__ hcur_all,
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    BatchState *__restrict__ bs, int32_t level, const double *__restrict__ hcur_all,
     const uint32_t *__restrict__ bmcur_all, uint32_t *__restrict__ slotbm_all,
     double *__restrict__ hnext_all, const int32_t *__restrict__ Fnext_all,
     Flags *__restrict__ fl) {
@@ -444,11 +416,12 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
     const int64_t b = blockIdx.y;
     if (!bs[b].active) return;
     const int nxt = (level & 1) ^ 1;
-    const double *h = hcur_all + b * n;
-    const uint32_t *bm = bmcur_all + b * nw;
-    uint32_t *sbm = slotbm_all + b * nsw;
-    double *hn = hnext_all + b * n;
-    const int32_t *F = Fnext_all + b * n;
+    const Slot sl = slots[b];
+    const double *h = hcur_all + sl.hoff;  // indexed by graph-local vertex ids
+    const uint32_t *bm = bmcur_all + sl.bmoff;
+    uint32_t *sbm = slotbm_all + sl.sboff;
+    double *hn = hnext_all + sl.hoff;
+    const int32_t *F = Fnext_all + sl.hoff;
     const int32_t fsz = bs[b].fsz[nxt];
     const int lane = __lane_id();
     double *lds = stage[threadIdx.x >> 6];
@@ -470,8 +443,9 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
             bool nz = false;
             if (inr) {
                 const int32_t y = col[ost + (jc - opre)];
-                if (bm[y >> 5] & (1u << (y & 31))) {
-                    v = h[y];
+                const int32_t yl = y - sl.goff;
+                if (bm[yl >> 5] & (1u << (yl & 31))) {
+                    v = h[yl];
                     nz = true;
                 }
             }
@@ -490,8 +464,8 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
         while (hubs) {
             const int hl = __builtin_ctzll(hubs);
             hubs &= hubs - 1;
-            const int32_t a = __shfl(rr.x, hl), d = __shfl(rr.y, hl);
-            const int32_t e1 = a + d;  // row positions [a, e1)
+            const int32_t a = __shfl(rr.x, hl) - sl.gpos, d = __shfl(rr.y, hl);
+            const int32_t e1 = a + d;  // local row positions [a, e1)
             const int64_t wfirst = a >> 5, wlast = (e1 - 1) >> 5;
             double hacc = 0.0;
             for (int64_t wc = wfirst; wc <= wlast; wc += 64) {
@@ -508,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
                     const int32_t t = __shfl_up(inc, o);
                     if (lane >= o) inc += t;
                 }
-                const int32_t T = __shfl(inc, 63);
+                const int32_t T = __builtin_amdgcn_readfirstlane(__shfl(inc, 63));
                 const int32_t pos0 = inc - cnt;
                 for (int32_t r0 = 0; r0 < T; r0 += kFoldWindow) {
                     uint32_t rest = word;
@@ -517,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
                         const int bit = __builtin_ctz(rest);
                         rest &= rest - 1;
                         if (p >= r0 && p < r0 + kFoldWindow) {
-                            const int32_t y = col[wi * 32 + bit];
-                            lds[p - r0] = h[y];
+                            const int32_t y = col[sl.gpos + wi * 32 + bit];
+                            lds[p - r0] = h[y - sl.goff];
                         }
                         ++p;
                     }
@@ -551,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
         }
         if (w.x >= 0) {
             const double hv = acc / (double)rr.y;
-            hn[w.x] = hv;
+            hn[w.x - sl.goff] = hv;
             vol += (unsigned long long)rr.y;
             hmax = fmax(hmax, hv);
         }
@@ -570,60 +544,56 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
 
 // After a level: zero h_l and its support bitmap over the support, so both are clean when the
 // buffers are reused for level l + 2.  (Every set bit of a touched bitmap word belongs to the
-// support, so the whole word is cleared.)
-__global__ __launch_bounds__(kBlock) void clear_level_kernel(const BatchState *__restrict__ bs,
-                                                             int32_t n, int64_t nw, int parity,
-                                                             bool only_active,
-                                                             double *__restrict__ hA,
-                                                             double *__restrict__ hB,
-                                                             uint32_t *__restrict__ bmA,
-                                                             uint32_t *__restrict__ bmB,
-                                                             const int32_t *__restrict__ FA,
-                                                             const int32_t *__restrict__ FB) {
+// support, so the whole word is cleared.)  parity < 0 clears each slot's final level.
+__global__ __launch_bounds__(kBlock) void clear_level_kernel(
+    const Slot *__restrict__ slots, const BatchState *__restrict__ bs, int parity,
+    bool only_active, double *__restrict__ hA, double *__restrict__ hB, uint32_t *__restrict__ bmA,
+    uint32_t *__restrict__ bmB, const int32_t *__restrict__ FA, const int32_t *__restrict__ FB) {
     const int64_t b = blockIdx.y;
     if (only_active && !bs[b].active) return;
+    const Slot sl = slots[b];
     const int pb = parity < 0 ? bs[b].finalbuf : parity;
-    double *h = (pb ? hB : hA) + b * (int64_t)n;
-    uint32_t *bm = (pb ? bmB : bmA) + b * nw;
-    const int32_t *F = (pb ? FB : FA) + b * (int64_t)n;
+    double *h = (pb ? hB : hA) + sl.hoff;
+    uint32_t *bm = (pb ? bmB : bmA) + sl.bmoff;
+    const int32_t *F = (pb ? FB : FA) + sl.hoff;
     const int32_t fsz = bs[b].fsz[pb];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fsz;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t x = F[i];
+        const int32_t x = F[i] - sl.goff;
         h[x] = 0.0;
         bm[x >> 5] = 0u;
     }
 }
 
-// Walk pairs per wanted directed edge and the number of 64-walk chunks they need.
+// Walk pairs per wanted instance edge and the number of 64-walk chunks they need.
 __global__ __launch_bounds__(kBlock) void nreq_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ bsrc,
-    const BatchState *__restrict__ bs, int32_t nb, const int64_t *__restrict__ ebase,
-    const int32_t *__restrict__ tau, const int32_t *__restrict__ ttau_src,
-    const uint8_t *__restrict__ want, double c, long long *__restrict__ nreq,
-    long long *__restrict__ chunks, Flags *__restrict__ fl) {
+    const int2 *__restrict__ vrec, const Slot *__restrict__ slots, const PSet *__restrict__ psets,
+    const BatchState *__restrict__ bs, int32_t nb, int64_t ie0, const int32_t *__restrict__ tau,
+    const uint8_t *__restrict__ want, long long *__restrict__ nreq, long long *__restrict__ chunks,
+    Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb) return;
-    const int32_t s = bsrc[b];
-    const int2 r = vrec[s];
-    const int32_t tt = ttau_src[s];
+    const Slot sl = slots[b];
+    const double c = psets[sl.p].c;
+    const int2 r = vrec[sl.v];
+    const int32_t tt = bs[b].ttau;
     const double hmax = bs[b].hmax;
     long long steps = 0, walks = 0;
     int ovf = 0;
     for (int32_t i = lane; i < r.y; i += 64) {
-        const int32_t e = r.x + i;
+        const int64_t ie = sl.ie + i;
         long long nr = 0;
-        const int32_t L = tau[e] - tt;
-        if (want[e] && L > 0) {
+        const int32_t L = tau[ie] - tt;
+        if (want[ie] && L > 0) {
             nr = nwalks(L, hmax, r.y, c);
             if (nr < 0) {
                 ovf = 1;
                 nr = 0;
             }
         }
-        nreq[e] = nr;
-        chunks[ebase[b] + i] = (2 * nr + kChunk - 1) / kChunk;
+        nreq[ie] = nr;
+        chunks[ie - ie0] = (2 * nr + kChunk - 1) / kChunk;
         steps += 2 * nr * (long long)(L > 0 ? L : 0);
         walks += 2 * nr;
     }
@@ -651,35 +621,39 @@ __device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, in
     return lo;
 }
 
-// The walk pairs (Alg. 1 inner loop): chunk c of local edge le holds walks
+// The walk pairs (Alg. 1 inner loop).  Chunk c of local edge le holds walks
 // j = 64 (c - coff[le]) + lane; j < n walk from s (side 0, index j), n <= j < 2n walk from t
-// (side 1, index j - n).  Each walk sums h_ttau over its positions 1..L.
+// (side 1, index j - n).  Each walk sums h_ttau over its positions 1..L.  The persistent grid
+// covers the flat chunk space of the whole batch (every instance edge of every request) in a
+// fixed wavefront-strided order; the loop control depends only on the wavefront index, so the
+// wavefront stays converged around its reductions.
 __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ bsrc, const BatchState *__restrict__ bs, int32_t nb, int32_t n,
-    const int64_t *__restrict__ ebase, const int64_t *__restrict__ coff, int64_t nle,
-    const int32_t *__restrict__ tau, const int32_t *__restrict__ ttau_src,
-    const long long *__restrict__ nreq, const double *__restrict__ hA,
-    const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
-    const uint32_t *__restrict__ bmB, int64_t nw, uint32_t seed, uint32_t G, uint32_t S,
-    double *__restrict__ partial, unsigned long long *__restrict__ vis0,
-    unsigned long long *__restrict__ vis1) {
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    const PSet *__restrict__ psets, const BatchState *__restrict__ bs, int32_t nb,
+    const int64_t *__restrict__ eb, int64_t ie0, const int64_t *__restrict__ coff, int64_t nle,
+    const int32_t *__restrict__ tau, const long long *__restrict__ nreq,
+    const double *__restrict__ hA, const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
+    const uint32_t *__restrict__ bmB, double *__restrict__ partial,
+    unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
+    Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t T = coff[nle];
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); c < T;
          c += nwaves) {
         const int64_t le = upper_index(coff, nle + 1, c);
-        const int64_t b = upper_index(ebase, nb + 1, le);
-        const int32_t s = bsrc[b];
-        const int2 rs = vrec[s];
-        const int32_t e = rs.x + (int32_t)(le - ebase[b]);
-        const int32_t t = col[e];
-        const long long nr = nreq[e];
-        const int32_t L = tau[e] - ttau_src[s];
+        const int64_t b = upper_index(eb, nb + 1, le);
+        const Slot sl = slots[b];
+        const PSet ps = psets[sl.p];
+        const int2 rs = vrec[sl.v];
+        const int32_t i = (int32_t)(le - eb[b]);
+        const int64_t ie = ie0 + le;
+        const int32_t t = col[rs.x + i];
+        const long long nr = nreq[ie];
+        const int32_t L = tau[ie] - bs[b].ttau;
         const int fb = bs[b].finalbuf;
-        const double *h = (fb ? hB : hA) + b * (int64_t)n;
-        const uint32_t *bm = (fb ? bmB : bmA) + b * nw;
+        const double *h = (fb ? hB : hA) + sl.hoff;
+        const uint32_t *bm = (fb ? bmB : bmA) + sl.bmoff;
         const long long j = (c - coff[le]) * kChunk + lane;
         const bool active = j < 2 * nr;
         const int side = j >= nr ? 1 : 0;
@@ -687,13 +661,15 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
         double acc = 0.0;
         long long hits = 0;
         if (active) {
-            const WalkKey key = walk_key(seed, (uint32_t)s, (uint32_t)t, (uint32_t)side,
-                                         (uint64_t)k, G, S);
-            int32_t cur = side ? t : s;
+            const int32_t sloc = sl.v - sl.goff, tloc = t - sl.goff;
+            const WalkKey key = walk_key(ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side,
+                                         (uint64_t)k, ps.G, ps.S);
+            int32_t cur = side ? t : sl.v;
             for (int32_t l = 1; l <= L; ++l) {
-                cur = walk_step(vrec, col, cur, (uint32_t)l, key);
-                if (bm[cur >> 5] & (1u << (cur & 31))) {  // h_ttau is zero off its support
-                    acc += h[cur];
+                cur = walk_step_local(vrec, col, cur, (uint32_t)l, key, sl.goff);
+                const int32_t xl = cur - sl.goff;
+                if (bm[xl >> 5] & (1u << (xl & 31))) {  // h_ttau is zero off its support
+                    acc += h[xl];
                     hits += 1;
                 }
             }
@@ -703,15 +679,15 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
         const long long h1 = wave_sum_ll(active && side ? hits : 0);
         if (lane == 0) {
             partial[c] = sum;
-            if (h0) atomicAdd(vis0 + e, (unsigned long long)h0);
-            if (h1) atomicAdd(vis1 + e, (unsigned long long)h1);
+            if (h0) atomicAdd(vis0 + ie, (unsigned long long)h0);
+            if (h1) atomicAdd(vis1 + ie, (unsigned long long)h1);
         }
     }
 }
 
-// Per directed edge: MC = its chunk sums in chunk order; g(s,t) = (D + MC / n) / d_s.
-__global__ void edge_reduce_kernel(const int2 *__restrict__ vrec, const int32_t *__restrict__ bsrc,
-                                   int32_t nb, const int64_t *__restrict__ ebase,
+// Per instance edge: MC = its chunk sums in chunk order; g(s,t) = (D + MC / n) / d_s.
+__global__ void edge_reduce_kernel(const int2 *__restrict__ vrec, const Slot *__restrict__ slots,
+                                   int32_t nb, const int64_t *__restrict__ eb, int64_t ie0,
                                    const int64_t *__restrict__ coff, int64_t nle,
                                    const uint8_t *__restrict__ want,
                                    const long long *__restrict__ nreq,
@@ -719,41 +695,44 @@ __global__ void edge_reduce_kernel(const int2 *__restrict__ vrec, const int32_t 
                                    double *__restrict__ MC, double *__restrict__ g) {
     for (int64_t le = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; le < nle;
          le += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = upper_index(ebase, nb + 1, le);
-        const int32_t s = bsrc[b];
-        const int2 rs = vrec[s];
-        const int32_t e = rs.x + (int32_t)(le - ebase[b]);
-        if (!want[e]) continue;
+        const int64_t ie = ie0 + le;
+        if (!want[ie]) continue;
+        const int64_t b = upper_index(eb, nb + 1, le);
+        const int32_t ds = vrec[slots[b].v].y;
         double mc = 0.0;
         for (int64_t c = coff[le]; c < coff[le + 1]; ++c) mc += partial[c];
-        const long long nr = nreq[e];
-        MC[e] = mc;
-        g[e] = nr > 0 ? (D[e] + mc / (double)nr) / (double)rs.y : D[e] / (double)rs.y;
+        const long long nr = nreq[ie];
+        MC[ie] = mc;
+        g[ie] = nr > 0 ? (D[ie] + mc / (double)nr) / (double)ds : D[ie] / (double)ds;
     }
 }
 
+// SC of the i-th canonical edge of a graph whose instances are all its vertices, in order:
+// the instance edge of a CSR position e is base + (e - gpos).
 __global__ void finalize_all_kernel(const int32_t *__restrict__ canon,
-                                    const int32_t *__restrict__ rev, int64_t m,
-                                    const double *__restrict__ g, double *__restrict__ sc) {
+                                    const int32_t *__restrict__ rev, int64_t cb, int64_t m,
+                                    int64_t base, int32_t gpos, const double *__restrict__ g,
+                                    double *__restrict__ sc) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t e = canon[i];
-        sc[i] = g[e] + g[rev[e]];
+        const int32_t e = canon[cb + i];
+        sc[i] = g[base + (e - gpos)] + g[base + (rev[e] - gpos)];
     }
 }
 
-__global__ void finalize_query_kernel(const int32_t *__restrict__ qe, int64_t q,
+__global__ void finalize_pairs_kernel(const int64_t *__restrict__ pairs, int64_t q,
                                       const double *__restrict__ g, double *__restrict__ sc) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q;
          j += (int64_t)gridDim.x * blockDim.x)
-        sc[j] = g[qe[2 * j]] + g[qe[2 * j + 1]];
+        sc[j] = g[pairs[2 * j]] + g[pairs[2 * j + 1]];
 }
 
-__global__ void export_kernel(const int32_t *__restrict__ row_of, int64_t nnz,
-                              const int32_t *__restrict__ ttau_src, int32_t *__restrict__ ttau) {
+__global__ void export_ttau_kernel(const int32_t *__restrict__ row_of, int64_t nnz,
+                                   const int32_t *__restrict__ ttau_inst,
+                                   int32_t *__restrict__ ttau) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
          e += (int64_t)gridDim.x * blockDim.x)
-        ttau[e] = ttau_src[row_of[e]];
+        ttau[e] = ttau_inst[row_of[e]];
 }
 
 // ------------------------------------------------------------ host driver
@@ -762,39 +741,184 @@ static unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) 
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-struct Outputs {
-    double *sc = nullptr;       // [m] (all) or [q] (query)
-    const int32_t *edges = nullptr;
-    int64_t q = -1;             // -1: all edges
+struct Request {
+    int32_t graph = 0;
+    saba_aesc_params p{};
+    const int32_t *edges = nullptr;  // device, graph-local ids
+    int64_t q = -1;                  // -1: all edges of the graph
+    double *sc = nullptr;
+    int32_t pid = -1;
+};
+
+struct Exports {  // per CSR position (single graph, all edges)
     int32_t *tau = nullptr, *ttau = nullptr;
     int64_t *nreq = nullptr, *vis0 = nullptr, *vis1 = nullptr;
     double *D = nullptr, *MC = nullptr, *g = nullptr;
 };
 
-static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba_stats *st,
-                     hipStream_t s) {
-    const int32_t n = g->n;
-    const int64_t nnz = g->nnz, m = nnz / 2;
+struct Opts {
+    int64_t mem_budget = 0;
+    int32_t batch_sources = 0;
+    int32_t time_kernels = 0;
+};
+
+static bool same_params(const Request &a, const Request &b) {
+    const saba_aesc_params &x = a.p, &y = b.p;
+    return a.graph == b.graph && x.eps == y.eps && x.delta == y.delta && x.lambda == y.lambda &&
+           x.seed == y.seed && x.group == y.group && x.spread == y.spread &&
+           x.tau_cap == y.tau_cap && x.tilde_tau_max == y.tilde_tau_max &&
+           (x.push_all != 0) == (y.push_all != 0);
+}
+
+static int check_params(const Graph *g, const Request &r) {
+    const saba_aesc_params *p = &r.p;
+    if (r.graph < 0 || r.graph >= g->ngraphs) {
+        set_error("request names a graph the handle does not hold");
+        return SABA_E_INVALID;
+    }
     if (!(p->eps > 0.0) || !(p->delta > 0.0 && p->delta < 1.0) || !(p->lambda >= 0.0) ||
         p->group < 1 || p->spread > 31 ||
-        (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull)) {
+        (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) ||
+        r.q < -1 || (r.q > 0 && !r.edges)) {
         set_error("invalid estimator parameters");
         return SABA_E_INVALID;
     }
-    if (!g->connected || n < 2) {
+    const int32_t a = g->goff[r.graph], z = g->goff[r.graph + 1];
+    if (!g->gconnected[r.graph] || z - a < 2) {
         set_error("the estimator needs a connected graph with at least one edge");
         return SABA_E_DISCONNECTED;
     }
-    if (g->bipartite || !(p->lambda < 1.0)) {
+    if (g->gbipartite[r.graph] || !(p->lambda < 1.0)) {
         set_error("the estimator needs a non-bipartite graph (lambda < 1)");
         return SABA_E_BIPARTITE;
     }
-    const int32_t cap = p->tau_cap > 0 ? p->tau_cap : 4096;
-    const double c = 32.0 * std::log(4.0 * (double)m / p->delta) / (p->eps * p->eps);
-    const bool timing = st && p->time_kernels;
+    return SABA_OK;
+}
+
+static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const Exports *ex,
+                    saba_stats *st, hipStream_t s) {
+    const int32_t *rp = g->h_row_ptr.data();
+    const int32_t *ci = g->h_col_idx.data();
+    for (auto &r : reqs) SABA_TRY(check_params(g, r));
+
+    // parameter sets: requests with equal (graph, parameters) share their instances
+    std::vector<PSet> psets;
+    std::vector<int32_t> pgraph;
+    std::vector<int32_t> plead;  // a request of each parameter set
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        int32_t pid = -1;
+        for (size_t k = 0; k < plead.size(); ++k)
+            if (same_params(reqs[plead[k]], reqs[i])) pid = (int32_t)k;
+        if (pid < 0) {
+            const Request &r = reqs[i];
+            const int64_t m = ((int64_t)rp[g->goff[r.graph + 1]] - rp[g->goff[r.graph]]) / 2;
+            PSet ps;
+            ps.lambda = r.p.lambda;
+            ps.eps = r.p.eps;
+            ps.c = 32.0 * std::log(4.0 * (double)m / r.p.delta) / (r.p.eps * r.p.eps);
+            ps.seed = r.p.seed;
+            ps.G = r.p.group;
+            ps.S = r.p.spread;
+            ps.tau_cap = r.p.tau_cap > 0 ? r.p.tau_cap : 4096;
+            ps.tilde_tau_max = r.p.tilde_tau_max;
+            ps.push_all = r.p.push_all ? 1 : 0;
+            pid = (int32_t)psets.size();
+            psets.push_back(ps);
+            pgraph.push_back(r.graph);
+            plead.push_back((int32_t)i);
+        }
+        reqs[i].pid = pid;
+    }
+    const int32_t P = (int32_t)psets.size();
+
+    // query pairs to the host (validated there against the resident CSR copy)
+    std::vector<std::vector<int32_t>> hq(reqs.size());
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        if (reqs[i].q <= 0) continue;
+        hq[i].resize(2 * reqs[i].q);
+        SABA_HIP_TRY(hipMemcpyAsync(hq[i].data(), reqs[i].edges, sizeof(int32_t) * 2 * reqs[i].q,
+                                    hipMemcpyDeviceToHost, s));
+    }
+    SABA_HIP_TRY(hipStreamSynchronize(s));
+    auto find_pos = [&](int32_t u, int32_t v) -> int32_t {
+        const int32_t *a = ci + rp[u], *z = ci + rp[u + 1];
+        const int32_t *f = std::lower_bound(a, z, v);
+        return (f != z && *f == v) ? (int32_t)(f - ci) : -1;
+    };
+
+    // instances: per parameter set, every vertex of its graph (an all-edges request) or the
+    // endpoints of its query pairs; the instance list is ordered by (parameter set, vertex)
+    std::vector<uint8_t> pall(P, 0);
+    std::vector<std::vector<uint8_t>> mark(P);
+    for (int32_t k = 0; k < P; ++k) {
+        const int32_t gn = g->goff[pgraph[k] + 1] - g->goff[pgraph[k]];
+        mark[k].assign(gn, 0);
+    }
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        const int32_t ga = g->goff[r.graph], gn = g->goff[r.graph + 1] - ga;
+        if (r.q < 0) {
+            pall[r.pid] = 1;
+            continue;
+        }
+        for (int64_t j = 0; j < r.q; ++j) {
+            const int32_t u = hq[i][2 * j], v = hq[i][2 * j + 1];
+            if (u < 0 || v < 0 || u >= gn || v >= gn || find_pos(ga + u, ga + v) < 0) {
+                set_error("a query pair is not an edge of the graph");
+                return SABA_E_NOT_EDGE;
+            }
+            mark[r.pid][u] = 1;
+            mark[r.pid][v] = 1;
+        }
+    }
+    std::vector<int32_t> inst_v, inst_p;
+    std::vector<int64_t> iebase;
+    std::vector<std::vector<int32_t>> inst_of(P);
+    std::vector<int64_t> pbase(P, 0);
+    int64_t NE = 0;
+    for (int32_t k = 0; k < P; ++k) {
+        const int32_t ga = g->goff[pgraph[k]];
+        const int32_t gn = (int32_t)mark[k].size();
+        inst_of[k].assign(gn, -1);
+        pbase[k] = NE;
+        for (int32_t x = 0; x < gn; ++x) {
+            if (!pall[k] && !mark[k][x]) continue;
+            inst_of[k][x] = (int32_t)inst_v.size();
+            inst_v.push_back(ga + x);
+            inst_p.push_back(k);
+            iebase.push_back(NE);
+            NE += rp[ga + x + 1] - rp[ga + x];
+        }
+    }
+    const int64_t ns = (int64_t)inst_v.size();
+    iebase.push_back(NE);
+
+    // wanted instance edges and the instance-edge pairs of every query
+    std::vector<uint8_t> want((size_t)std::max<int64_t>(NE, 1), 0);
+    std::vector<std::vector<int64_t>> qpairs(reqs.size());
+    for (int32_t k = 0; k < P; ++k)
+        if (pall[k]) {
+            const int32_t ga = g->goff[pgraph[k]], gz = g->goff[pgraph[k] + 1];
+            std::fill(want.begin() + pbase[k], want.begin() + pbase[k] + (rp[gz] - rp[ga]), 1);
+        }
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        if (r.q <= 0) continue;
+        const int32_t ga = g->goff[r.graph];
+        qpairs[i].resize(2 * r.q);
+        for (int64_t j = 0; j < r.q; ++j) {
+            const int32_t u = hq[i][2 * j], v = hq[i][2 * j + 1];
+            const int32_t euv = find_pos(ga + u, ga + v), evu = find_pos(ga + v, ga + u);
+            const int64_t a = iebase[inst_of[r.pid][u]] + (euv - rp[ga + u]);
+            const int64_t b = iebase[inst_of[r.pid][v]] + (evu - rp[ga + v]);
+            want[a] = want[b] = 1;
+            qpairs[i][2 * j] = a;
+            qpairs[i][2 * j + 1] = b;
+        }
+    }
+
+    const bool timing = st && opt.time_kernels;
     hipEvent_t ev[4] = {};
-    if (timing)
-        for (auto &e : ev) SABA_HIP_TRY(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t *ev;
         ~EvGuard() {
@@ -802,22 +926,26 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
                 if (ev[i]) (void)hipEventDestroy(ev[i]);
         }
     } evguard{ev};
+    if (timing)
+        for (auto &e : ev) SABA_HIP_TRY(hipEventCreate(&e));
     float walk_ms = 0.f;
     if (timing) SABA_HIP_TRY(hipEventRecord(ev[0], s));
 
     auto &E = g->est;
-    SABA_TRY(E[B_TAU].ensure(sizeof(int32_t) * nnz));
-    SABA_TRY(E[B_D].ensure(sizeof(double) * nnz));
-    SABA_TRY(E[B_NREQ].ensure(sizeof(long long) * nnz));
-    SABA_TRY(E[B_MC].ensure(sizeof(double) * nnz));
-    SABA_TRY(E[B_VIS0].ensure(sizeof(long long) * nnz));
-    SABA_TRY(E[B_VIS1].ensure(sizeof(long long) * nnz));
-    SABA_TRY(E[B_G].ensure(sizeof(double) * nnz));
-    SABA_TRY(E[B_TTAU_SRC].ensure(sizeof(int32_t) * n));
-    SABA_TRY(E[B_MAXTAU_SRC].ensure(sizeof(int32_t) * n));
-    SABA_TRY(E[B_WANT].ensure(nnz));
-    SABA_TRY(E[B_LIST].ensure(sizeof(int32_t) * n));
+    const int64_t NE1 = std::max<int64_t>(NE, 1);
+    SABA_TRY(E[B_PSET].ensure(sizeof(PSet) * std::max(P, 1)));
+    SABA_TRY(E[B_WANT].ensure(NE1));
+    SABA_TRY(E[B_TAU].ensure(sizeof(int32_t) * NE1));
+    SABA_TRY(E[B_D].ensure(sizeof(double) * NE1));
+    SABA_TRY(E[B_NREQ].ensure(sizeof(long long) * NE1));
+    SABA_TRY(E[B_MC].ensure(sizeof(double) * NE1));
+    SABA_TRY(E[B_VIS0].ensure(sizeof(long long) * NE1));
+    SABA_TRY(E[B_VIS1].ensure(sizeof(long long) * NE1));
+    SABA_TRY(E[B_G].ensure(sizeof(double) * NE1));
+    SABA_TRY(E[B_TTAU].ensure(sizeof(int32_t) * std::max<int64_t>(ns, 1)));
     SABA_TRY(E[B_FLAGS].ensure(sizeof(Flags)));
+    PSet *d_psets = E[B_PSET].as<PSet>();
+    uint8_t *d_want = E[B_WANT].as<uint8_t>();
     int32_t *tau = E[B_TAU].as<int32_t>();
     double *D = E[B_D].as<double>();
     long long *nreq = E[B_NREQ].as<long long>();
@@ -825,86 +953,81 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
     auto *vis0 = E[B_VIS0].as<unsigned long long>();
     auto *vis1 = E[B_VIS1].as<unsigned long long>();
     double *gd = E[B_G].as<double>();
-    int32_t *ttau_src = E[B_TTAU_SRC].as<int32_t>();
-    int32_t *maxtau = E[B_MAXTAU_SRC].as<int32_t>();
-    uint8_t *want = E[B_WANT].as<uint8_t>();
-    int32_t *list = E[B_LIST].as<int32_t>();
+    int32_t *ttau_inst = E[B_TTAU].as<int32_t>();
     Flags *fl = E[B_FLAGS].as<Flags>();
+    SABA_HIP_TRY(hipMemcpyAsync(d_psets, psets.data(), sizeof(PSet) * P, hipMemcpyHostToDevice, s));
+    SABA_HIP_TRY(hipMemcpyAsync(d_want, want.data(), NE1, hipMemcpyHostToDevice, s));
     SABA_HIP_TRY(hipMemsetAsync(fl, 0, sizeof(Flags), s));
 
-    tau_kernel<<<grid_for(n, kWavesPerBlock, 1 << 16), kBlock, 0, s>>>(
-        g->vrec, g->col_idx, n, p->lambda, p->eps, cap, tau, maxtau, fl);
-    SABA_HIP_TRY(hipGetLastError());
-
-    // sources and wanted directed edges
-    int64_t ns = n;
-    int32_t *qe = nullptr;
-    if (o.q < 0) {
-        SABA_HIP_TRY(hipMemsetAsync(want, 1, nnz, s));
-        iota_kernel<<<grid_for(n, 256, 1 << 16), 256, 0, s>>>(list, n);
-        SABA_HIP_TRY(hipGetLastError());
-    } else {
-        SABA_TRY(E[B_SRCMARK].ensure(sizeof(long long) * n));
-        SABA_TRY(E[B_SRCPOS].ensure(sizeof(int64_t) * (n + 1)));
-        SABA_TRY(E[B_SCAN].ensure(scan_tmp_bytes(n)));
-        SABA_TRY(E[B_QE].ensure(sizeof(int32_t) * 2 * std::max<int64_t>(o.q, 1)));
-        qe = E[B_QE].as<int32_t>();
-        long long *srcmark = E[B_SRCMARK].as<long long>();
-        int64_t *srcpos = E[B_SRCPOS].as<int64_t>();
-        SABA_HIP_TRY(hipMemsetAsync(want, 0, nnz, s));
-        SABA_HIP_TRY(hipMemsetAsync(srcmark, 0, sizeof(long long) * n, s));
-        if (o.q > 0) {
-            query_mark_kernel<<<grid_for(o.q, 256, 1 << 16), 256, 0, s>>>(
-                g->vrec, g->col_idx, n, o.edges, o.q, want, srcmark, qe, fl);
-            SABA_HIP_TRY(hipGetLastError());
-        }
-        SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(srcmark), srcpos, n, E[B_SCAN].ptr, s));
-        compact_kernel<<<grid_for(n, 256, 1 << 16), 256, 0, s>>>(srcmark, srcpos, n, list);
-        SABA_HIP_TRY(hipGetLastError());
-        Flags hf;
-        SABA_HIP_TRY(hipMemcpyAsync(&ns, srcpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SABA_HIP_TRY(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
-        SABA_HIP_TRY(hipStreamSynchronize(s));
-        if (hf.err & kErrNotEdge) {
-            set_error("a query pair is not an edge of the graph");
-            return SABA_E_NOT_EDGE;
-        }
-    }
-
-    // batch size from the memory budget: two dense FP64 levels, two frontiers, two bitmaps
+    // batches: consecutive instances whose slots fit the memory budget
     size_t freeb = 0, totalb = 0;
     SABA_HIP_TRY(hipMemGetInfo(&freeb, &totalb));
-    int64_t budget = p->mem_budget > 0 ? p->mem_budget
-                                       : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
-    const int64_t nw = ((int64_t)n + 31) / 32;
-    const int64_t nsw = (nnz + 31) / 32;
-    const int64_t per_src = (int64_t)n * (2 * 8 + 2 * 4) + 2 * 4 * nw + 4 * nsw;
-    int64_t B = p->batch_sources > 0 ? p->batch_sources : std::max<int64_t>(1, budget / per_src);
-    B = std::min<int64_t>({B, std::max<int64_t>(ns, 1), 65535});
+    const int64_t budget = opt.mem_budget > 0
+                               ? opt.mem_budget
+                               : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
+    std::vector<int64_t> slot_h(P), slot_bm(P), slot_sb(P), slot_bytes(P);
+    for (int32_t k = 0; k < P; ++k) {
+        const int32_t ga = g->goff[pgraph[k]], gz = g->goff[pgraph[k] + 1];
+        const int64_t gn = gz - ga, gnnz = (int64_t)rp[gz] - rp[ga];
+        slot_h[k] = gn;
+        slot_bm[k] = (gn + 31) / 32;
+        slot_sb[k] = (gnnz + 31) / 32;
+        slot_bytes[k] = gn * (2 * 8 + 2 * 4) + 2 * 4 * slot_bm[k] + 4 * slot_sb[k];
+    }
+    struct Batch {
+        int64_t i0, i1, h, bm, sb, ne;
+    };
+    std::vector<Batch> batches;
+    int64_t maxh = 0, maxbm = 0, maxsb = 0, maxne = 0, maxnb = 0;
+    for (int64_t i = 0; i < ns;) {
+        Batch bt{i, i, 0, 0, 0, 0};
+        int64_t bytes = 0;
+        while (bt.i1 < ns) {
+            const int32_t k = inst_p[bt.i1];
+            if (bt.i1 > bt.i0 && (bytes + slot_bytes[k] > budget || bt.i1 - bt.i0 >= 65535 ||
+                                  (opt.batch_sources > 0 && bt.i1 - bt.i0 >= opt.batch_sources)))
+                break;
+            bytes += slot_bytes[k];
+            bt.h += slot_h[k];
+            bt.bm += slot_bm[k];
+            bt.sb += slot_sb[k];
+            ++bt.i1;
+        }
+        bt.ne = iebase[bt.i1] - iebase[bt.i0];
+        maxh = std::max(maxh, bt.h);
+        maxbm = std::max(maxbm, bt.bm);
+        maxsb = std::max(maxsb, bt.sb);
+        maxne = std::max(maxne, bt.ne);
+        maxnb = std::max(maxnb, bt.i1 - bt.i0);
+        batches.push_back(bt);
+        i = bt.i1;
+    }
 
-    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)(B * n) ||
-                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)(B * nw) ||
-                      E[B_SLOTBM].bytes < sizeof(uint32_t) * (size_t)(B * nsw);
-    SABA_TRY(E[B_HA].ensure(sizeof(double) * B * n));
-    SABA_TRY(E[B_HB].ensure(sizeof(double) * B * n));
-    SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * B * n));
-    SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * B * n));
-    SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * B * nw));
-    SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * B * nw));
-    SABA_TRY(E[B_SLOTBM].ensure(sizeof(uint32_t) * B * nsw));
-    SABA_TRY(E[B_BSRC].ensure(sizeof(int32_t) * B));
-    SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * B));
-    SABA_TRY(E[B_EBASE].ensure(sizeof(int64_t) * (B + 1)));
-    SABA_TRY(E[B_DEG64].ensure(sizeof(long long) * B));
-    SABA_TRY(E[B_SCAN].ensure(std::max(scan_tmp_bytes(B), scan_tmp_bytes(nnz))));
+    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)std::max<int64_t>(maxh, 1) ||
+                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)std::max<int64_t>(maxbm, 1) ||
+                      E[B_SLOTBM].bytes < sizeof(uint32_t) * (size_t)std::max<int64_t>(maxsb, 1);
+    SABA_TRY(E[B_HA].ensure(sizeof(double) * std::max<int64_t>(maxh, 1)));
+    SABA_TRY(E[B_HB].ensure(sizeof(double) * std::max<int64_t>(maxh, 1)));
+    SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * std::max<int64_t>(maxh, 1)));
+    SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * std::max<int64_t>(maxh, 1)));
+    SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * std::max<int64_t>(maxbm, 1)));
+    SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * std::max<int64_t>(maxbm, 1)));
+    SABA_TRY(E[B_SLOTBM].ensure(sizeof(uint32_t) * std::max<int64_t>(maxsb, 1)));
+    SABA_TRY(E[B_SLOT].ensure(sizeof(Slot) * std::max<int64_t>(maxnb, 1)));
+    SABA_TRY(E[B_EB].ensure(sizeof(int64_t) * (maxnb + 1)));
+    SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * std::max<int64_t>(maxnb, 1)));
+    SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * std::max<int64_t>(maxne, 1)));
+    SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (maxne + 1)));
+    SABA_TRY(E[B_SCAN].ensure(scan_tmp_bytes(std::max<int64_t>(maxne, 1))));
     double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
     int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
     uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
     uint32_t *slotbm = E[B_SLOTBM].as<uint32_t>();
-    int32_t *bsrc = E[B_BSRC].as<int32_t>();
+    Slot *d_slots = E[B_SLOT].as<Slot>();
+    int64_t *d_eb = E[B_EB].as<int64_t>();
     BatchState *bs = E[B_BSTATE].as<BatchState>();
-    int64_t *ebase = E[B_EBASE].as<int64_t>();
-    long long *deg64 = E[B_DEG64].as<long long>();
+    long long *chunks = E[B_CHUNKS].as<long long>();
+    int64_t *coff = E[B_COFF].as<int64_t>();
     if (grow || !g->est_clean) {
         // dense vectors and bitmaps start at zero and are kept clean by the sparse clears
         SABA_HIP_TRY(hipMemsetAsync(hA, 0, E[B_HA].bytes, s));
@@ -915,14 +1038,45 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
     }
     g->est_clean = false;  // until this call has cleared everything it touched
 
-    const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
-    int64_t batches = 0;
-    for (int64_t i0 = 0; i0 < ns; i0 += B) {
-        const int32_t nb = (int32_t)std::min<int64_t>(B, ns - i0);
-        ++batches;
+    std::vector<Slot> hslots;
+    std::vector<int64_t> heb;
+    for (const Batch &bt : batches) {
+        const int32_t nb = (int32_t)(bt.i1 - bt.i0);
+        const int64_t ie0 = iebase[bt.i0], nle = bt.ne;
+        hslots.resize(nb);
+        heb.resize(nb + 1);
+        int64_t ho = 0, bo = 0, so = 0, maxgn = 1;
+        for (int32_t b = 0; b < nb; ++b) {
+            const int64_t i = bt.i0 + b;
+            const int32_t k = inst_p[i], gi = pgraph[k];
+            Slot &sl = hslots[b];
+            sl.hoff = ho;
+            sl.bmoff = bo;
+            sl.sboff = so;
+            sl.ie = iebase[i];
+            sl.inst = i;
+            sl.v = inst_v[i];
+            sl.p = k;
+            sl.goff = g->goff[gi];
+            sl.gn = g->goff[gi + 1] - g->goff[gi];
+            sl.gpos = rp[sl.goff];
+            sl.pad = 0;
+            ho += slot_h[k];
+            bo += slot_bm[k];
+            so += slot_sb[k];
+            maxgn = std::max<int64_t>(maxgn, sl.gn);
+            heb[b] = iebase[i] - ie0;
+        }
+        heb[nb] = nle;
+        SABA_HIP_TRY(hipMemcpyAsync(d_slots, hslots.data(), sizeof(Slot) * nb,
+                                    hipMemcpyHostToDevice, s));
+        SABA_HIP_TRY(hipMemcpyAsync(d_eb, heb.data(), sizeof(int64_t) * (nb + 1),
+                                    hipMemcpyHostToDevice, s));
         batch_init_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-            g->vrec, list, i0, nb, n, nw, bsrc, bs, hA, FA, bmA, D, nreq, MC, vis0, vis1, deg64);
+            g->vrec, g->col_idx, d_slots, d_psets, nb, bs, hA, FA, bmA, tau, D, nreq, MC, vis0,
+            vis1, fl);
         SABA_HIP_TRY(hipGetLastError());
+        const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, maxgn / 4096));
         const dim3 grid(ysplit, (unsigned)nb);
         for (int32_t level = 0;; ++level) {
             const int cur = level & 1;
@@ -931,35 +1085,26 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
             uint32_t *bmcur = cur ? bmB : bmA, *bmnext = cur ? bmA : bmB;
             SABA_HIP_TRY(hipMemsetAsync(&fl->any_active, 0, sizeof(int32_t), s));
             level_decide_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-                g->vrec, g->col_idx, bsrc, bs, nb, n, level, hcur, tau, maxtau, D, ttau_src, c,
-                p->push_all, p->tilde_tau_max, fl);
+                g->vrec, g->col_idx, d_slots, d_psets, bs, nb, level, hcur, tau, D, ttau_inst, fl);
             SABA_HIP_TRY(hipGetLastError());
             int32_t any = 0;
             SABA_HIP_TRY(hipMemcpyAsync(&any, &fl->any_active, sizeof(int32_t),
                                         hipMemcpyDeviceToHost, s));
             SABA_HIP_TRY(hipStreamSynchronize(s));
             if (!any) break;
-            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, bs, n, nw, nsw,
-                                                  level, Fcur, bmnext, slotbm, fl);
-            compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(bs, n, nw, level, bmnext,
+            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, level,
+                                                  Fcur, bmnext, slotbm, fl);
+            compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(d_slots, bs, level, bmnext,
                                                                     Fnext);
-            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, bs, n, nw, nsw, level, hcur,
+            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hcur,
                                                 bmcur, slotbm, hnext, Fnext, fl);
-            clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, nw, cur, true, hA, hB, bmA, bmB, FA,
-                                                       FB);
+            clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, cur, true, hA, hB, bmA, bmB,
+                                                       FA, FB);
             SABA_HIP_TRY(hipGetLastError());
         }
-        // walk pairs of the batch's edges
-        SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(deg64), ebase, nb, E[B_SCAN].ptr, s));
-        int64_t nle = 0;
-        SABA_HIP_TRY(hipMemcpyAsync(&nle, ebase + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SABA_HIP_TRY(hipStreamSynchronize(s));
-        SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * std::max<int64_t>(nle, 1)));
-        SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (nle + 1)));
-        long long *chunks = E[B_CHUNKS].as<long long>();
-        int64_t *coff = E[B_COFF].as<int64_t>();
+        // walk pairs of the batch's instance edges
         nreq_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-            g->vrec, bsrc, bs, nb, ebase, tau, ttau_src, want, c, nreq, chunks, fl);
+            g->vrec, d_slots, d_psets, bs, nb, ie0, tau, d_want, nreq, chunks, fl);
         SABA_HIP_TRY(hipGetLastError());
         SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(chunks), coff, nle, E[B_SCAN].ptr, s));
         int64_t T = 0;
@@ -975,9 +1120,9 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         double *partial = E[B_PART].as<double>();
         if (T > 0) {
             if (timing) SABA_HIP_TRY(hipEventRecord(ev[1], s));
-            mc_walk_kernel<<<grid_for(T, kWavesPerBlock, 2048), kBlock, 0, s>>>(
-                g->vrec, g->col_idx, bsrc, bs, nb, n, ebase, coff, nle, tau, ttau_src, nreq, hA,
-                hB, bmA, bmB, nw, p->seed, p->group, p->spread, partial, vis0, vis1);
+            mc_walk_kernel<<<grid_for(T, kWavesPerBlock, kWalkGrid), kBlock, 0, s>>>(
+                g->vrec, g->col_idx, d_slots, d_psets, bs, nb, d_eb, ie0, coff, nle, tau, nreq, hA,
+                hB, bmA, bmB, partial, vis0, vis1, fl);
             SABA_HIP_TRY(hipGetLastError());
             if (timing) {
                 SABA_HIP_TRY(hipEventRecord(ev[2], s));
@@ -988,36 +1133,57 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
             }
         }
         edge_reduce_kernel<<<grid_for(nle, 256, 1 << 16), 256, 0, s>>>(
-            g->vrec, bsrc, nb, ebase, coff, nle, want, nreq, D, partial, MC, gd);
+            g->vrec, d_slots, nb, d_eb, ie0, coff, nle, d_want, nreq, D, partial, MC, gd);
         // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
-        clear_level_kernel<<<grid, kBlock, 0, s>>>(bs, n, nw, -1, false, hA, hB, bmA, bmB, FA, FB);
+        clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, -1, false, hA, hB, bmA, bmB, FA,
+                                                   FB);
         SABA_HIP_TRY(hipGetLastError());
     }
     g->est_clean = true;
 
-    if (o.sc) {
-        if (o.q < 0) {
-            finalize_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, s>>>(g->canon, g->rev, m, gd,
-                                                                         o.sc);
-        } else if (o.q > 0) {
-            finalize_query_kernel<<<grid_for(o.q, 256, 1 << 16), 256, 0, s>>>(qe, o.q, gd, o.sc);
+    // results of every request
+    int64_t npairs = 0;
+    for (auto &qp : qpairs) npairs += (int64_t)qp.size();
+    SABA_TRY(E[B_PAIRS].ensure(sizeof(int64_t) * std::max<int64_t>(npairs, 1)));
+    int64_t *d_pairs = E[B_PAIRS].as<int64_t>();
+    int64_t off = 0;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        if (!r.sc) continue;
+        if (r.q < 0) {
+            const int32_t ga = g->goff[r.graph];
+            const int64_t cb = g->cbase[r.graph], m = g->cbase[r.graph + 1] - cb;
+            if (m > 0)
+                finalize_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, s>>>(
+                    g->canon, g->rev, cb, m, pbase[r.pid], rp[ga], gd, r.sc);
+        } else if (r.q > 0) {
+            SABA_HIP_TRY(hipMemcpyAsync(d_pairs + off, qpairs[i].data(),
+                                        sizeof(int64_t) * qpairs[i].size(), hipMemcpyHostToDevice,
+                                        s));
+            finalize_pairs_kernel<<<grid_for(r.q, 256, 1 << 16), 256, 0, s>>>(d_pairs + off, r.q,
+                                                                             gd, r.sc);
+            off += (int64_t)qpairs[i].size();
         }
         SABA_HIP_TRY(hipGetLastError());
     }
-    auto cp = [&](void *dst, const void *src, size_t bytes) -> int {
-        if (dst) SABA_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
-        return SABA_OK;
-    };
-    SABA_TRY(cp(o.tau, tau, sizeof(int32_t) * nnz));
-    SABA_TRY(cp(o.nreq, nreq, sizeof(int64_t) * nnz));
-    SABA_TRY(cp(o.D, D, sizeof(double) * nnz));
-    SABA_TRY(cp(o.MC, MC, sizeof(double) * nnz));
-    SABA_TRY(cp(o.vis0, vis0, sizeof(int64_t) * nnz));
-    SABA_TRY(cp(o.vis1, vis1, sizeof(int64_t) * nnz));
-    SABA_TRY(cp(o.g, gd, sizeof(double) * nnz));
-    if (o.ttau) {
-        export_kernel<<<grid_for(nnz, 256, 1 << 16), 256, 0, s>>>(g->row_of, nnz, ttau_src, o.ttau);
-        SABA_HIP_TRY(hipGetLastError());
+    if (ex) {  // single graph, one all-edges request: instance edges are CSR positions
+        const int64_t nnz = g->nnz;
+        auto cp = [&](void *dst, const void *src, size_t bytes) -> int {
+            if (dst) SABA_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+            return SABA_OK;
+        };
+        SABA_TRY(cp(ex->tau, tau, sizeof(int32_t) * nnz));
+        SABA_TRY(cp(ex->nreq, nreq, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->D, D, sizeof(double) * nnz));
+        SABA_TRY(cp(ex->MC, MC, sizeof(double) * nnz));
+        SABA_TRY(cp(ex->vis0, vis0, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->vis1, vis1, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->g, gd, sizeof(double) * nnz));
+        if (ex->ttau && nnz > 0) {
+            export_ttau_kernel<<<grid_for(nnz, 256, 1 << 16), 256, 0, s>>>(g->row_of, nnz,
+                                                                           ttau_inst, ex->ttau);
+            SABA_HIP_TRY(hipGetLastError());
+        }
     }
     if (timing) SABA_HIP_TRY(hipEventRecord(ev[3], s));
     Flags hf;
@@ -1029,7 +1195,7 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
         st->walk_steps = (int64_t)hf.walk_steps;
         st->push_edge_visits = (int64_t)hf.push_visits;
         st->sources = ns;
-        st->batches = batches;
+        st->batches = (int64_t)batches.size();
         st->max_tau = hf.max_tau;
         st->max_ttau = hf.max_ttau;
         st->warnings = hf.warnings;
@@ -1039,6 +1205,22 @@ static int aesc_impl(Graph *g, const saba_aesc_params *p, const Outputs &o, saba
             st->kernel_ms = walk_ms;
             st->total_ms = tot;
         }
+    }
+    return SABA_OK;
+}
+
+static Opts opts_of(const saba_aesc_params *p) {
+    Opts o;
+    o.mem_budget = p->mem_budget;
+    o.batch_sources = p->batch_sources;
+    o.time_kernels = p->time_kernels;
+    return o;
+}
+
+static int single_graph(const Graph *g) {
+    if (g->ngraphs != 1) {
+        set_error("this call needs a handle with one graph; use saba_aesc_batch");
+        return SABA_E_INVALID;
     }
     return SABA_OK;
 }
@@ -1055,9 +1237,11 @@ extern "C" int saba_aesc(saba_graph *gh, const saba_aesc_params *p, double *d_sc
         set_error("params or output is NULL");
         return SABA_E_INVALID;
     }
-    Outputs o;
-    o.sc = d_sc;
-    return aesc_impl(G(gh), p, o, st, static_cast<hipStream_t>(stream));
+    SABA_TRY(single_graph(G(gh)));
+    std::vector<Request> reqs(1);
+    reqs[0].p = *p;
+    reqs[0].sc = d_sc;
+    return aesc_run(G(gh), reqs, opts_of(p), nullptr, st, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int saba_aesc_query(saba_graph *gh, const saba_aesc_params *p, const int32_t *d_edges,
@@ -1068,11 +1252,13 @@ extern "C" int saba_aesc_query(saba_graph *gh, const saba_aesc_params *p, const 
         set_error("invalid query arguments");
         return SABA_E_INVALID;
     }
-    Outputs o;
-    o.sc = d_sc;
-    o.edges = d_edges;
-    o.q = q;
-    return aesc_impl(G(gh), p, o, st, static_cast<hipStream_t>(stream));
+    SABA_TRY(single_graph(G(gh)));
+    std::vector<Request> reqs(1);
+    reqs[0].p = *p;
+    reqs[0].edges = d_edges;
+    reqs[0].q = q;
+    reqs[0].sc = d_sc;
+    return aesc_run(G(gh), reqs, opts_of(p), nullptr, st, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int saba_aesc_edge_stats(saba_graph *gh, const saba_aesc_params *p, double *d_sc,
@@ -1085,15 +1271,51 @@ extern "C" int saba_aesc_edge_stats(saba_graph *gh, const saba_aesc_params *p, d
         set_error("params is NULL");
         return SABA_E_INVALID;
     }
-    Outputs o;
-    o.sc = d_sc;
-    o.tau = d_tau;
-    o.ttau = d_ttau;
-    o.nreq = d_nreq;
-    o.D = d_D;
-    o.MC = d_MC;
-    o.vis0 = d_vis0;
-    o.vis1 = d_vis1;
-    o.g = d_g;
-    return aesc_impl(G(gh), p, o, st, static_cast<hipStream_t>(stream));
+    SABA_TRY(single_graph(G(gh)));
+    std::vector<Request> reqs(1);
+    reqs[0].p = *p;
+    reqs[0].sc = d_sc;  // may be NULL: then only the per-edge internals are written
+    Exports ex;
+    ex.tau = d_tau;
+    ex.ttau = d_ttau;
+    ex.nreq = d_nreq;
+    ex.D = d_D;
+    ex.MC = d_MC;
+    ex.vis0 = d_vis0;
+    ex.vis1 = d_vis1;
+    ex.g = d_g;
+    return aesc_run(G(gh), reqs, opts_of(p), &ex, st, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int saba_aesc_batch(saba_graph *gh, const saba_aesc_request *reqs, int32_t nreq,
+                               const saba_batch_options *opt, saba_stats *st, void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (nreq < 0 || (nreq > 0 && !reqs)) {
+        set_error("invalid request list");
+        return SABA_E_INVALID;
+    }
+    std::vector<Request> rs((size_t)nreq);
+    for (int32_t i = 0; i < nreq; ++i) {
+        if (reqs[i].q != 0 && !reqs[i].d_sc) {
+            set_error("a request has no output array");
+            return SABA_E_INVALID;
+        }
+        rs[i].graph = reqs[i].graph;
+        rs[i].p = reqs[i].params;
+        rs[i].edges = reqs[i].d_edges;
+        rs[i].q = reqs[i].q;
+        rs[i].sc = reqs[i].d_sc;
+    }
+    Opts o;
+    if (opt) {
+        o.mem_budget = opt->mem_budget;
+        o.batch_sources = opt->batch_sources;
+        o.time_kernels = opt->time_kernels;
+    }
+    if (nreq == 0) {
+        if (st) *st = saba_stats{};
+        return SABA_OK;
+    }
+    return aesc_run(G(gh), rs, o, nullptr, st, static_cast<hipStream_t>(stream));
 }

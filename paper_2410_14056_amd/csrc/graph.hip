@@ -157,12 +157,15 @@ __global__ void build_slotv_kernel(const int2 *__restrict__ vrec, const int32_t 
         slotv[e] = vrec[col[e]].y > kHubRow ? rev[e] : -1;
 }
 
-static int validate_host(const int32_t *rp, const int32_t *ci, int32_t n, int64_t nnz) {
+static int validate_host(const int32_t *rp, const int32_t *ci, int32_t n, int64_t nnz,
+                         const std::vector<int32_t> &goff) {
     if (rp[0] != 0 || (int64_t)rp[n] != nnz) {
         set_error("row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
         return SABA_E_GRAPH;
     }
+    size_t gi = 0;
     for (int32_t v = 0; v < n; ++v) {
+        while (v >= goff[gi + 1]) ++gi;
         if (rp[v + 1] < rp[v]) {
             set_error("row_ptr is not non-decreasing at vertex " + std::to_string(v));
             return SABA_E_GRAPH;
@@ -175,6 +178,10 @@ static int validate_host(const int32_t *rp, const int32_t *ci, int32_t n, int64_
             }
             if (t == v) {
                 set_error("self-loop at vertex " + std::to_string(v));
+                return SABA_E_GRAPH;
+            }
+            if (t < goff[gi] || t >= goff[gi + 1]) {
+                set_error("edge of vertex " + std::to_string(v) + " leaves its graph");
                 return SABA_E_GRAPH;
             }
             if (e > rp[v] && ci[e - 1] >= t) {
@@ -201,18 +208,21 @@ static void graph_properties(Graph *g) {
         g->d_max = std::max(g->d_max, d);
         g->n_isolated += d == 0;
     }
-    // breadth-first search from vertex 0: connectivity and two-colouring
+    // breadth-first search from the first vertex of each graph: connectivity, two-colouring
     std::vector<int8_t> color(n, -1);
     std::vector<int32_t> queue;
     queue.reserve(n);
-    int32_t reached = 0;
-    bool bip = true;
-    if (n > 0) {
-        color[0] = 0;
-        queue.push_back(0);
+    g->gconnected.assign(g->ngraphs, 0);
+    g->gbipartite.assign(g->ngraphs, 0);
+    for (int32_t k = 0; k < g->ngraphs; ++k) {
+        const int32_t a = g->goff[k], z = g->goff[k + 1];
+        if (a >= z) continue;
+        queue.clear();
+        color[a] = 0;
+        queue.push_back(a);
+        bool bip = true;
         for (size_t h = 0; h < queue.size(); ++h) {
             int32_t x = queue[h];
-            ++reached;
             for (int32_t e = rp[x]; e < rp[x + 1]; ++e) {
                 int32_t y = ci[e];
                 if (color[y] < 0) {
@@ -223,9 +233,11 @@ static void graph_properties(Graph *g) {
                 }
             }
         }
+        g->gconnected[k] = (int64_t)queue.size() == (int64_t)(z - a) ? 1 : 0;
+        g->gbipartite[k] = (g->gconnected[k] && bip) ? 1 : 0;
     }
-    g->connected = (n > 0 && reached == n) ? 1 : 0;
-    g->bipartite = (g->connected && bip) ? 1 : 0;
+    g->connected = (g->ngraphs == 1 && n > 0) ? g->gconnected[0] : 0;
+    g->bipartite = (g->ngraphs == 1 && n > 0) ? g->gbipartite[0] : 0;
 }
 
 static void destroy_graph(Graph *g) {
@@ -251,9 +263,9 @@ extern "C" int saba_version(void) { return SABA_ABI_VERSION; }
 
 extern "C" const char *saba_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
-                                 int64_t nnz, uint32_t flags, void *stream, saba_graph **out) {
-    clear_error();
+static int create_impl(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz,
+                       int32_t ngraphs, const int32_t *offsets, uint32_t flags, void *stream,
+                       saba_graph **out) {
     if (!out) {
         set_error("out is NULL");
         return SABA_E_INVALID;
@@ -283,6 +295,8 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
     g->device = dev;
     g->n = n;
     g->nnz = nnz;
+    g->ngraphs = ngraphs;
+    g->goff.assign(offsets, offsets + ngraphs + 1);
     try {
         g->h_row_ptr.resize((size_t)n + 1);
         g->h_col_idx.resize((size_t)nnz);
@@ -311,7 +325,7 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
         if (nnz > 0) std::memcpy(g->h_col_idx.data(), col_idx, sizeof(int32_t) * (size_t)nnz);
     }
     if (!(flags & SABA_TRUSTED)) {
-        rc = validate_host(g->h_row_ptr.data(), g->h_col_idx.data(), n, nnz);
+        rc = validate_host(g->h_row_ptr.data(), g->h_col_idx.data(), n, nnz, g->goff);
         if (rc != SABA_OK) return fail(rc);
     }
     graph_properties(g);
@@ -319,9 +333,14 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
     // canonical edge order: the entries (u, v) with u < v in CSR order
     std::vector<int32_t> canon;
     canon.reserve((size_t)(nnz / 2));
-    for (int32_t u = 0; u < n; ++u)
-        for (int32_t e = g->h_row_ptr[u]; e < g->h_row_ptr[u + 1]; ++e)
-            if (g->h_col_idx[e] > u) canon.push_back(e);
+    g->cbase.assign(ngraphs + 1, 0);
+    for (int32_t k = 0, u = 0; k < ngraphs; ++k) {
+        g->cbase[k] = (int64_t)canon.size();
+        for (; u < g->goff[k + 1]; ++u)
+            for (int32_t e = g->h_row_ptr[u]; e < g->h_row_ptr[u + 1]; ++e)
+                if (g->h_col_idx[e] > u) canon.push_back(e);
+    }
+    g->cbase[ngraphs] = (int64_t)canon.size();
 
     size_t nb = sizeof(int32_t) * std::max<int64_t>(nnz, 1);
     if (hipMalloc(&g->row_ptr, sizeof(int32_t) * ((size_t)n + 1)) != hipSuccess ||
@@ -361,6 +380,31 @@ extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx,
     return SABA_OK;
 }
 
+extern "C" int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                                 int64_t nnz, uint32_t flags, void *stream, saba_graph **out) {
+    clear_error();
+    const int32_t offsets[2] = {0, n};
+    return create_impl(row_ptr, col_idx, n, nnz, 1, offsets, flags, stream, out);
+}
+
+extern "C" int saba_graph_create_multi(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                                       int64_t nnz, int32_t ngraphs,
+                                       const int32_t *vertex_offsets, uint32_t flags,
+                                       void *stream, saba_graph **out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (ngraphs < 1 || !vertex_offsets || vertex_offsets[0] != 0 || vertex_offsets[ngraphs] != n) {
+        set_error("vertex_offsets must hold ngraphs + 1 entries from 0 to n");
+        return SABA_E_INVALID;
+    }
+    for (int32_t k = 0; k < ngraphs; ++k)
+        if (vertex_offsets[k + 1] < vertex_offsets[k]) {
+            set_error("vertex_offsets must be non-decreasing");
+            return SABA_E_INVALID;
+        }
+    return create_impl(row_ptr, col_idx, n, nnz, ngraphs, vertex_offsets, flags, stream, out);
+}
+
 extern "C" int saba_graph_destroy(saba_graph *g) {
     clear_error();
     destroy_graph(G(g));
@@ -382,5 +426,6 @@ extern "C" int saba_graph_info(const saba_graph *gh, saba_graph_info_t *out) {
     out->n_isolated = g->n_isolated;
     out->connected = g->connected;
     out->bipartite = g->bipartite;
+    out->ngraphs = g->ngraphs;
     return SABA_OK;
 }

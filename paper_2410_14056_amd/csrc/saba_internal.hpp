@@ -52,6 +52,12 @@ struct Graph {
     int32_t n_isolated = 0;
     int32_t connected = 0;
     int32_t bipartite = 0;
+    // A handle may hold several graphs side by side (block-diagonal CSR).  Graph k owns the
+    // vertices [goff[k], goff[k+1]); its canonical edges are canon[cbase[k] .. cbase[k+1]).
+    int32_t ngraphs = 1;
+    std::vector<int32_t> goff;
+    std::vector<int64_t> cbase;
+    std::vector<int8_t> gconnected, gbipartite;
     std::vector<int32_t> h_row_ptr, h_col_idx;
     int32_t *row_ptr = nullptr;
     int32_t *col_idx = nullptr;
@@ -145,6 +151,17 @@ __device__ __forceinline__ int32_t walk_step(const int2 *__restrict__ vrec,
                                              uint32_t l, WalkKey key) {
     int2 r = vrec[cur];
     uint32_t u = hash_w2((uint32_t)cur, l, key.hi) ^ key.lo;
+    uint32_t k = (uint32_t)(((uint64_t)u * (uint32_t)r.y) >> 32);
+    return col[r.x + (int32_t)k];
+}
+
+// The same step for a graph stored at vertex offset goff of a multi-graph handle: the hash
+// sees the graph's own vertex id, so the walk equals the one in the graph alone.
+__device__ __forceinline__ int32_t walk_step_local(const int2 *__restrict__ vrec,
+                                                   const int32_t *__restrict__ col, int32_t cur,
+                                                   uint32_t l, WalkKey key, int32_t goff) {
+    int2 r = vrec[cur];
+    uint32_t u = hash_w2((uint32_t)(cur - goff), l, key.hi) ^ key.lo;
     uint32_t k = (uint32_t)(((uint64_t)u * (uint32_t)r.y) >> 32);
     return col[r.x + (int32_t)k];
 }

@@ -18,8 +18,8 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for want in ("saba_version", "saba_last_error", "saba_graph_create", "saba_graph_destroy",
-                 "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
-                 "saba_aesc_edge_stats"):
+                 "saba_graph_create_multi", "saba_graph_info", "saba_walks", "saba_aesc",
+                 "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch"):
         assert want in names
 
 
@@ -59,4 +59,7 @@ def test_structs_match_header_layout():
     # saba_aesc_params: 3 doubles, 3 uint32, 5 int32, int64 -> 64 bytes
     assert ctypes.sizeof(b.AescParams) == 64
     assert ctypes.sizeof(b.Stats) == 80
-    assert ctypes.sizeof(b.GraphInfo) == 40
+    assert ctypes.sizeof(b.GraphInfo) == 48
+    # saba_aesc_request: 2 x int32, params (64), pointer, int64, pointer -> 96 bytes
+    assert ctypes.sizeof(b.AescRequest) == 96
+    assert ctypes.sizeof(b.BatchOptions) == 16
