@@ -210,6 +210,111 @@ def bench_aesc(args, saba, torch, np):
     return out
 
 
+def _batch_graph(spec):
+    """One graph of the batched workload: (kind, n, seed) -> (graph, lambda upper bound)."""
+    import graphgen
+    kind, n, seed = spec
+    if kind == 0:
+        g = graphgen.largest_component(graphgen.er_gnm(n, 4 * n, seed))
+    elif kind == 1:
+        g = graphgen.largest_component(graphgen.chung_lu(n, 8, 2.3, seed))
+    else:
+        side = max(2, int(round(n ** 0.5)))
+        g = graphgen.largest_component(graphgen.grid_diagonals(side, side, 0.05, seed))
+    if kind == 2:
+        # grids mix so slowly (lambda within 1e-4 of 1) that every tau reaches the cap; any
+        # upper bound below 1 gives the same run, and 1 - 1e-9 bounds it for these sizes
+        lam = 1.0 - 1e-9
+    else:
+        lam = graphgen.spectral_lambda(g)
+    return g.row_ptr, g.col_idx, lam
+
+
+def _batch_graph_indexed(item):
+    k, spec = item
+    return k, _batch_graph(spec)
+
+
+def progress(msg):
+    print(json.dumps({"progress": msg}), file=sys.stderr, flush=True)
+
+
+def bench_batch(args, saba, torch, np):
+    """Batched estimation: 256 graphs of uneven size (n uniform in [1e3, 2e5]; one third each
+    Erdos-Renyi with average degree 8, Chung-Lu with exponent 2.3, square grids with 5% random
+    diagonals), eps drawn from {0.1, 0.2, 0.3}, 32 random query edges per graph, tau capped at
+    128.  One saba_aesc_batch call on a multi-graph handle against one saba_aesc_query call per
+    graph; both must give identical results."""
+    import multiprocessing as mp
+    import graphgen
+    rng = np.random.default_rng(4)
+    G = args.batch_graphs
+    specs = [(k % 3, int(rng.integers(1000, 200001)), 1000 + k) for k in range(G)]
+    epss = [float(rng.choice([0.1, 0.2, 0.3])) for _ in range(G)]
+    t0 = time.perf_counter()
+    # one BLAS thread per worker process: the pool itself supplies the parallelism
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    built = [None] * G
+    try:
+        with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+            for done, (k, res) in enumerate(pool.imap_unordered(_batch_graph_indexed,
+                                                                list(enumerate(specs))), 1):
+                built[k] = res
+                if done % 32 == 0 or done == G:
+                    progress(f"batch workload: {done}/{G} graphs built "
+                             f"({time.perf_counter() - t0:.0f} s)")
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    prep_s = time.perf_counter() - t0
+    graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
+    lams = [lam for _, _, lam in built]
+    qs = []
+    for k, g in enumerate(graphs):
+        ce = graphgen.canonical_edges(g)
+        pick = np.sort(rng.choice(g.m, min(g.m, args.batch_edges), replace=False))
+        qs.append(torch.from_numpy(np.ascontiguousarray(ce[pick])).cuda())
+    nq = sum(int(q.shape[0]) for q in qs)
+    # one call per graph (each graph resident in its own handle, uploaded beforehand)
+    handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
+    saba.aesc_query(handles[0], qs[0], epss[0], lams[0], 1, tau_cap=128)
+    torch.cuda.synchronize()
+    progress("batch workload: one call per graph")
+    t0 = time.perf_counter()
+    single = []
+    for k, (h, q, e, l) in enumerate(zip(handles, qs, epss, lams)):
+        single.append(saba.aesc_query(h, q, e, l, 1, tau_cap=128)[0])
+        if (k + 1) % 64 == 0:
+            progress(f"batch workload: {k + 1}/{G} single calls ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    progress("batch workload: one batched call")
+    del handles
+    mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    reqs = [{"graph": k, "eps": epss[k], "lam": lams[k], "seed": 1, "edges": qs[k], "tau_cap": 128}
+            for k in range(G)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, st = saba.aesc_batch(mg, reqs, time_kernels=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(bool(torch.equal(a, b)) for a, b in zip(single, outs))
+    assert same, "batched results differ from single-graph results"
+    return {"workload": f"batch_{G}graphs_n1e3-2e5_er_cl_grid_q{args.batch_edges}",
+            "graphs": G, "vertices": sum(g.n for g in graphs), "edges": sum(g.m for g in graphs),
+            "query_edges": nq, "prep_s": prep_s,
+            "single_calls_s": t_single, "single_edges_per_s": nq / t_single,
+            "batched_s": t_batch, "batched_edges_per_s": nq / t_batch,
+            "speedup": t_single / t_batch, "identical": same,
+            "walk_steps": st["walk_steps"], "sources": st["sources"], "batches": st["batches"],
+            "walk_kernel_ms": st["kernel_ms"], "tau_capped": bool(st["warnings"] & 1)}
+
+
 def bench_c1(args, saba, torch, np):
     """Config 1: all edges of ER n=2000, m=8000, seed 1 (largest component), eps=0.3, plain walks."""
     import graphgen
@@ -250,7 +355,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "copy"], default="all")
+    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "batch", "copy"],
+                    default="all")
+    ap.add_argument("--batch-graphs", type=int, default=256)
+    ap.add_argument("--batch-edges", type=int, default=32)
     ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--spread", type=int, default=0)
@@ -299,6 +407,13 @@ def main():
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = walks_cpu_baseline(g, args.length, 1)
         del g
+    if args.workload == "batch":
+        b = bench_batch(args, saba, torch, np)
+        out.update({"value": b["batched_edges_per_s"], "unit": "edges/s", "dtype": "f64",
+                    "ms_per_step": b["batched_s"] * 1e3, "config": {"workload": b["workload"]},
+                    "batch": b})
+        print(json.dumps(out), flush=True)
+        return
     if args.workload in ("all", "c1"):
         out["c1"] = bench_c1(args, saba, torch, np)
         if args.workload == "c1":
