@@ -44,6 +44,9 @@ extern "C" {
 #define SABA_E_NOT_EDGE (-7)     /* a query pair is not an edge of the graph */
 #define SABA_E_OVERFLOW (-8)     /* a walk count exceeds the 64-bit range */
 #define SABA_E_NODEVICE (-9)     /* no usable gfx950 device */
+#define SABA_E_BUSY (-10)        /* the server's admission queue is full (backpressure) */
+#define SABA_E_TIMEOUT (-11)     /* a server request has not finished within the wait */
+#define SABA_E_CANCELLED (-12)   /* the server was destroyed before the request finished */
 
 /* saba_graph_create flags */
 #define SABA_DEVICE_PTRS 1u /* row_ptr / col_idx are device pointers */
@@ -124,6 +127,58 @@ typedef struct {
     int32_t batch_sources; /* cap on instances per batch (0: from mem_budget) */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
 } saba_batch_options;
+
+/* Options of saba_server_create; none of them changes a result. */
+typedef struct {
+    int64_t mem_budget;        /* bytes of source scratch over all lanes (0: 8 GiB or 40% of free
+                                  memory); each lane batches sources up to its equal share */
+    int64_t max_queued_edges;  /* admission bound: query edges submitted and not finished; a
+                                  request beyond it is refused with SABA_E_BUSY (0: 2^20) */
+    int64_t arena_edges;       /* query edges whose directed estimates can be held at once; a
+                                  request is admitted to the batches when its 2q entries fit
+                                  (0: 2^22); a request with q > arena_edges is invalid */
+    int32_t lanes;             /* batches in flight, each on its own stream (0: 2; at most 8) */
+    int32_t max_batch_sources; /* sources per batch (0: 4096; at most 65535) */
+} saba_server_options;
+
+/* One query of the server. */
+typedef struct {
+    int32_t graph;            /* index of the graph in the handle */
+    int32_t reserved;
+    saba_aesc_params params;  /* eps, delta, lambda, seed, group, spread, tau_cap, tilde_tau_max,
+                                 push_all (the execution fields are ignored) */
+    const int32_t *edges;     /* [2q] query pairs (host) in the graph's own vertex ids; copied by
+                                 saba_server_submit, so the caller may free them on return */
+    int64_t q;                /* number of pairs, q >= 0 */
+    double *d_sc;             /* [q] results (device), written before the request is reported
+                                 finished; must stay valid until then */
+} saba_server_request;
+
+/* Outcome of one server request. */
+typedef struct {
+    int32_t status;     /* SABA_OK or the error the request failed with */
+    int32_t batches;    /* batches that carried its sources */
+    int64_t instances;  /* sources (distinct endpoints) it needed */
+    double queue_ms;    /* submit -> admission to the batches */
+    double latency_ms;  /* submit -> results written */
+} saba_server_result;
+
+/* Counters of a server since its creation. */
+typedef struct {
+    int64_t submitted;         /* requests accepted by saba_server_submit */
+    int64_t rejected;          /* requests refused with SABA_E_BUSY */
+    int64_t completed;         /* requests finished with SABA_OK */
+    int64_t failed;            /* requests finished with an error */
+    int64_t batches;           /* batches run */
+    int64_t instances;         /* sources run */
+    int64_t walk_steps;        /* walk steps taken */
+    int64_t queued_edges;      /* query edges submitted and not yet finished, now */
+    int64_t queued_requests;   /* requests submitted and not yet finished, now */
+    int64_t peak_queued_edges; /* largest value queued_edges has had */
+    double busy_ms;            /* wall time the lanes spent running batches, summed over lanes */
+} saba_server_stats_t;
+
+typedef struct saba_server saba_server;
 
 /* ABI version (SABA_ABI_VERSION). */
 int saba_version(void);
@@ -220,6 +275,47 @@ int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc,
  */
 int saba_aesc_batch(saba_graph *g, const saba_aesc_request *reqs, int32_t nreq,
                     const saba_batch_options *opt, saba_stats *stats, void *stream);
+
+/*
+ * Query server over a resident handle: spanning-centrality requests (edge sets of one graph
+ * at given parameters; per-edge estimates are independent, Sec. 2.1) are admitted as they
+ * arrive and their sources are batched together into shared launches (Alg. 1 per source).
+ * The server owns host threads (one per lane), one HIP stream per lane, and device scratch
+ * within opt->mem_budget plus the result arena.  g must outlive the server.  Other calls on
+ * g may run meanwhile from one other thread (they use the handle's own scratch).
+ * opt may be NULL.  *out receives the server (NULL on failure).
+ */
+int saba_server_create(saba_graph *g, const saba_server_options *opt, saba_server **out);
+
+/*
+ * Submit one request; never blocks on the GPU.  The pairs are validated here (SABA_E_NOT_EDGE,
+ * SABA_E_INVALID, SABA_E_DISCONNECTED, SABA_E_BIPARTITE, SABA_E_OVERFLOW when eps is too small
+ * for tau_cap, SABA_E_NOMEM when one source of the graph exceeds a lane's budget) and
+ * SABA_E_BUSY is returned while the admission queue is full.  On SABA_OK *ticket names the
+ * request until saba_server_wait reports it finished.  Its d_sc receives exactly what
+ * saba_aesc_query returns for the same graph and parameters alone.
+ */
+int saba_server_submit(saba_server *srv, const saba_server_request *req, uint64_t *ticket);
+
+/*
+ * Wait up to timeout_ms (< 0: without limit; 0: poll) for a request to finish.  Returns
+ * SABA_OK when it finished and its d_sc is written (visible to every stream), the request's
+ * error when it failed, SABA_E_TIMEOUT when it has not finished (the ticket stays valid), or
+ * SABA_E_INVALID for an unknown ticket.  Once a finished request is reported its ticket is
+ * released.  res may be NULL.
+ */
+int saba_server_wait(saba_server *srv, uint64_t ticket, int32_t timeout_ms,
+                     saba_server_result *res);
+
+/* Fill *out with the server's counters. */
+int saba_server_stats(saba_server *srv, saba_server_stats_t *out);
+
+/*
+ * Stop the server: requests not yet in a batch finish with SABA_E_CANCELLED, running batches
+ * complete, the lanes are joined and every resource is freed.  No other call on srv may be in
+ * progress or follow.  NULL is accepted.
+ */
+int saba_server_destroy(saba_server *srv);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@ from ._binding import (  # noqa: F401
     SABA_WALK_NAIVE,
     SabaError,
     SabaGraph,
+    SabaServer,
     WalkResult,
     aesc,
     aesc_batch,

@@ -24,8 +24,11 @@ SABA_WALK_BOUQUET = 1
 _ERRORS = {
     -1: "SABA_E_INVALID", -2: "SABA_E_NOMEM", -3: "SABA_E_HIP", -4: "SABA_E_GRAPH",
     -5: "SABA_E_DISCONNECTED", -6: "SABA_E_BIPARTITE", -7: "SABA_E_NOT_EDGE",
-    -8: "SABA_E_OVERFLOW", -9: "SABA_E_NODEVICE",
+    -8: "SABA_E_OVERFLOW", -9: "SABA_E_NODEVICE", -10: "SABA_E_BUSY", -11: "SABA_E_TIMEOUT",
+    -12: "SABA_E_CANCELLED",
 }
+SABA_E_BUSY = -10
+SABA_E_TIMEOUT = -11
 
 
 class SabaError(RuntimeError):
@@ -78,10 +81,40 @@ class BatchOptions(ctypes.Structure):
                 ("time_kernels", ctypes.c_int32)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("max_queued_edges", ctypes.c_int64),
+                ("arena_edges", ctypes.c_int64), ("lanes", ctypes.c_int32),
+                ("max_batch_sources", ctypes.c_int32)]
+
+
+class ServerRequest(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("reserved", ctypes.c_int32), ("params", AescParams),
+                ("edges", ctypes.c_void_p), ("q", ctypes.c_int64), ("d_sc", ctypes.c_void_p)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batches", ctypes.c_int32),
+                ("instances", ctypes.c_int64), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "rejected", "completed", "failed", "batches", "instances", "walk_steps",
+        "queued_edges", "queued_requests", "peak_queued_edges")] + [("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol the header declares
 EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_create_multi",
            "saba_graph_destroy", "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
-           "saba_aesc_edge_stats", "saba_aesc_batch"]
+           "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
+           "saba_server_wait", "saba_server_stats", "saba_server_destroy"]
 
 _lib = None
 
@@ -107,6 +140,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_aesc_edge_stats.argtypes = [P, ctypes.POINTER(AescParams), P, P, P, P, P, P, P, P, P,
                                        ctypes.POINTER(Stats), P]
     L.saba_aesc_batch.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions), ctypes.POINTER(Stats), P]
+    L.saba_server_create.argtypes = [P, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+    L.saba_server_submit.argtypes = [P, ctypes.POINTER(ServerRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.saba_server_wait.argtypes = [P, ctypes.c_uint64, i32, ctypes.POINTER(ServerResult)]
+    L.saba_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.saba_server_destroy.argtypes = [P]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
     _lib = L
@@ -314,3 +352,75 @@ def aesc_batch(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: i
     _check(lib.saba_aesc_batch(graph.handle, ctypes.cast(arr, ctypes.c_void_p), len(requests),
                                ctypes.byref(opt), ctypes.byref(st), _stream_ptr(stream)))
     return outs, st.as_dict()
+
+
+class SabaServer:
+    """Query server over a resident handle (saba_server_*): requests are admitted as they
+    arrive and their sources run in shared batches on `lanes` concurrent streams."""
+
+    def __init__(self, graph: SabaGraph, lanes: int = 0, mem_budget: int = 0,
+                 max_queued_edges: int = 0, arena_edges: int = 0, max_batch_sources: int = 0,
+                 device="cuda"):
+        lib = load()
+        self.graph = graph  # the handle must outlive the server
+        self.device = device
+        opt = ServerOptions(int(mem_budget), int(max_queued_edges), int(arena_edges), int(lanes),
+                            int(max_batch_sources))
+        h = ctypes.c_void_p()
+        _check(lib.saba_server_create(graph.handle, ctypes.byref(opt), ctypes.byref(h)))
+        self.handle = h
+        self._out = {}
+
+    def submit(self, graph: int, edges, eps: float, lam: float, seed: int, **kw) -> int:
+        """Submit query pairs (host int32 array [q, 2] of the graph's own ids); returns a
+        ticket.  Raises SabaError (name SABA_E_BUSY when the admission queue is full)."""
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        q = e.shape[0]
+        out = torch.empty(q, dtype=torch.float64, device=self.device)
+        # the block may have been freed with work still pending on torch's stream; the
+        # server writes it from its own stream
+        torch.cuda.current_stream(out.device).synchronize()
+        r = ServerRequest()
+        r.graph = int(graph)
+        r.params = _aesc_params(eps, lam, seed, **kw)
+        r.edges = e.ctypes.data if q else None
+        r.q = q
+        r.d_sc = out.data_ptr() if q else None
+        t = ctypes.c_uint64()
+        _check(load().saba_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._out[t.value] = out
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(results tensor, result dict) once the request has finished; None on time-out."""
+        res = ServerResult()
+        rc = load().saba_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms),
+                                     ctypes.byref(res))
+        if rc == SABA_E_TIMEOUT:
+            return None
+        out = self._out.pop(ticket, None)
+        _check(rc)
+        return out, res.as_dict()
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().saba_server_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().saba_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self._out.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsaba.so")
-SOURCES = ["graph.hip", "walks.hip", "aesc.hip"]
+SOURCES = ["graph.hip", "walks.hip", "aesc.hip", "server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -23,6 +23,7 @@ HIPCC_FLAGS = [
     "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-pthread",
 ]
 
 

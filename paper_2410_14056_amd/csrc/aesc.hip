@@ -41,7 +41,7 @@
 #include <tuple>
 #include <vector>
 
-#include "saba_internal.hpp"
+#include "estimator.hpp"
 
 namespace saba {
 
@@ -49,36 +49,6 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kChunk = 64;  // walks per wavefront chunk
 constexpr int kWalkGrid = 2048;
-
-enum : int32_t { kErrOverflow = 1 };
-
-// scratch slots in Graph::est
-enum {
-    B_PSET, B_SLOT, B_EB, B_BSTATE, B_WANT, B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G,
-    B_TTAU, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_CHUNKS, B_COFF, B_PART, B_SCAN,
-    B_FLAGS, B_PAIRS, B_COUNT
-};
-static_assert(B_COUNT <= 32, "Graph::est holds 32 buffers");
-
-struct PSet {  // one parameter set of a call
-    double lambda, eps, c;
-    uint32_t seed, G, S;
-    int32_t tau_cap, tilde_tau_max, push_all;
-};
-
-struct Slot {  // one instance of a batch
-    int64_t hoff;   // first element of its dense vectors and frontier lists
-    int64_t bmoff;  // first word of its vertex bitmaps
-    int64_t sboff;  // first word of its CSR-position bitmap
-    int64_t ie;     // first instance edge
-    int64_t inst;   // instance index
-    int32_t v;      // source vertex (handle ids)
-    int32_t p;      // parameter set
-    int32_t goff;   // first vertex of its graph
-    int32_t gn;     // vertices of its graph
-    int32_t gpos;   // first CSR position of its graph
-    int32_t pad;
-};
 
 struct BatchState {  // one per slot; [2] entries are indexed by level parity
     int32_t active;
@@ -89,18 +59,6 @@ struct BatchState {  // one per slot; [2] entries are indexed by level parity
     double hmax;                    // max of h_ttau once the source has stopped
     int32_t maxtau;
     int32_t ttau;
-};
-
-struct Flags {
-    int32_t err;
-    int32_t any_active;
-    int32_t max_tau;
-    int32_t max_ttau;
-    int32_t warnings;
-    int32_t pad;
-    unsigned long long walk_steps;
-    unsigned long long push_visits;
-    unsigned long long walks;
 };
 
 // ------------------------------------------------------------ wave helpers
@@ -735,12 +693,234 @@ __global__ void export_ttau_kernel(const int32_t *__restrict__ row_of, int64_t n
         ttau[e] = ttau_inst[row_of[e]];
 }
 
-// ------------------------------------------------------------ host driver
-static unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+// ------------------------------------------------------------ batch executor
+unsigned grid_for(int64_t items, int per_block, unsigned cap) {
     int64_t g = (items + per_block - 1) / per_block;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+int check_request(const Graph *g, int32_t graph, const saba_aesc_params &pr, int64_t q,
+                  const void *edges) {
+    const saba_aesc_params *p = &pr;
+    if (graph < 0 || graph >= g->ngraphs) {
+        set_error("request names a graph the handle does not hold");
+        return SABA_E_INVALID;
+    }
+    if (!(p->eps > 0.0) || !(p->delta > 0.0 && p->delta < 1.0) || !(p->lambda >= 0.0) ||
+        p->group < 1 || p->spread > 31 ||
+        (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) || q < -1 ||
+        (q > 0 && !edges)) {
+        set_error("invalid estimator parameters");
+        return SABA_E_INVALID;
+    }
+    const int32_t a = g->goff[graph], z = g->goff[graph + 1];
+    if (!g->gconnected[graph] || z - a < 2) {
+        set_error("the estimator needs a connected graph with at least one edge");
+        return SABA_E_DISCONNECTED;
+    }
+    if (g->gbipartite[graph] || !(p->lambda < 1.0)) {
+        set_error("the estimator needs a non-bipartite graph (lambda < 1)");
+        return SABA_E_BIPARTITE;
+    }
+    return SABA_OK;
+}
+
+PSet make_pset(const Graph *g, int32_t graph, const saba_aesc_params &p) {
+    const int32_t *rp = g->h_row_ptr.data();
+    const int64_t m = ((int64_t)rp[g->goff[graph + 1]] - rp[g->goff[graph]]) / 2;
+    PSet ps;
+    ps.lambda = p.lambda;
+    ps.eps = p.eps;
+    ps.c = 32.0 * std::log(4.0 * (double)m / p.delta) / (p.eps * p.eps);
+    ps.seed = p.seed;
+    ps.G = p.group;
+    ps.S = p.spread;
+    ps.tau_cap = p.tau_cap > 0 ? p.tau_cap : 4096;
+    ps.tilde_tau_max = p.tilde_tau_max;
+    ps.push_all = p.push_all ? 1 : 0;
+    return ps;
+}
+
+bool same_pset(const PSet &a, const PSet &b) {
+    return a.lambda == b.lambda && a.eps == b.eps && a.c == b.c && a.seed == b.seed &&
+           a.G == b.G && a.S == b.S && a.tau_cap == b.tau_cap &&
+           a.tilde_tau_max == b.tilde_tau_max && a.push_all == b.push_all;
+}
+
+SlotSize slot_size(const Graph *g, int32_t graph) {
+    const int32_t *rp = g->h_row_ptr.data();
+    const int32_t ga = g->goff[graph], gz = g->goff[graph + 1];
+    const int64_t gn = gz - ga, gnnz = (int64_t)rp[gz] - rp[ga];
+    SlotSize z;
+    z.h = gn;
+    z.bm = (gn + 31) / 32;
+    z.sb = (gnnz + 31) / 32;
+    z.bytes = gn * (2 * 8 + 2 * 4) + 2 * 4 * z.bm + 4 * z.sb;
+    return z;
+}
+
+int ensure_edge_arrays(Workspace &ws, int64_t ne, int64_t ninst, int32_t np, EdgeArrays *out) {
+    auto &E = ws.b;
+    const int64_t n1 = std::max<int64_t>(ne, 1);
+    SABA_TRY(E[B_PSET].ensure(sizeof(PSet) * std::max(np, 1)));
+    SABA_TRY(E[B_WANT].ensure(n1));
+    SABA_TRY(E[B_TAU].ensure(sizeof(int32_t) * n1));
+    SABA_TRY(E[B_D].ensure(sizeof(double) * n1));
+    SABA_TRY(E[B_NREQ].ensure(sizeof(long long) * n1));
+    SABA_TRY(E[B_MC].ensure(sizeof(double) * n1));
+    SABA_TRY(E[B_VIS0].ensure(sizeof(long long) * n1));
+    SABA_TRY(E[B_VIS1].ensure(sizeof(long long) * n1));
+    SABA_TRY(E[B_G].ensure(sizeof(double) * n1));
+    SABA_TRY(E[B_TTAU].ensure(sizeof(int32_t) * std::max<int64_t>(ninst, 1)));
+    SABA_TRY(E[B_FLAGS].ensure(sizeof(Flags)));
+    out->psets = E[B_PSET].as<PSet>();
+    out->want = E[B_WANT].as<uint8_t>();
+    out->tau = E[B_TAU].as<int32_t>();
+    out->D = E[B_D].as<double>();
+    out->nreq = E[B_NREQ].as<long long>();
+    out->MC = E[B_MC].as<double>();
+    out->vis0 = E[B_VIS0].as<unsigned long long>();
+    out->vis1 = E[B_VIS1].as<unsigned long long>();
+    out->g = E[B_G].as<double>();
+    out->ttau_inst = E[B_TTAU].as<int32_t>();
+    out->fl = E[B_FLAGS].as<Flags>();
+    return SABA_OK;
+}
+
+int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, int64_t ne,
+                 hipStream_t s) {
+    auto &E = ws.b;
+    h = std::max<int64_t>(h, 1);
+    bm = std::max<int64_t>(bm, 1);
+    sb = std::max<int64_t>(sb, 1);
+    nb = std::max<int64_t>(nb, 1);
+    ne = std::max<int64_t>(ne, 1);
+    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)h ||
+                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)bm ||
+                      E[B_SLOTBM].bytes < sizeof(uint32_t) * (size_t)sb;
+    if (grow) ws.clean = false;  // new pools hold garbage until zeroed below
+    SABA_TRY(E[B_HA].ensure(sizeof(double) * h));
+    SABA_TRY(E[B_HB].ensure(sizeof(double) * h));
+    SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * h));
+    SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * h));
+    SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * bm));
+    SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * bm));
+    SABA_TRY(E[B_SLOTBM].ensure(sizeof(uint32_t) * sb));
+    SABA_TRY(E[B_SLOT].ensure(sizeof(Slot) * nb));
+    SABA_TRY(E[B_EB].ensure(sizeof(int64_t) * (nb + 1)));
+    SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * nb));
+    SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * ne));
+    SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (ne + 1)));
+    SABA_TRY(E[B_SCAN].ensure(scan_tmp_bytes(ne)));
+    if (grow || !ws.clean) {
+        // dense vectors and bitmaps start at zero and are kept clean by the sparse clears
+        SABA_HIP_TRY(hipMemsetAsync(E[B_HA].ptr, 0, E[B_HA].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(E[B_HB].ptr, 0, E[B_HB].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(E[B_BMA].ptr, 0, E[B_BMA].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(E[B_BMB].ptr, 0, E[B_BMB].bytes, s));
+        SABA_HIP_TRY(hipMemsetAsync(E[B_SLOTBM].ptr, 0, E[B_SLOTBM].bytes, s));
+        ws.clean = true;
+    }
+    return SABA_OK;
+}
+
+int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
+              const std::vector<int64_t> &heb, int64_t ie0, int64_t nle, int64_t maxgn,
+              BatchTiming *tm, hipStream_t s) {
+    auto &E = ws.b;
+    const int32_t nb = (int32_t)hslots.size();
+    if (nb == 0) return SABA_OK;
+    if (nb > 65535) {
+        set_error("a batch holds at most 65535 instances");
+        return SABA_E_INVALID;
+    }
+    double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
+    int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
+    uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
+    uint32_t *slotbm = E[B_SLOTBM].as<uint32_t>();
+    Slot *d_slots = E[B_SLOT].as<Slot>();
+    int64_t *d_eb = E[B_EB].as<int64_t>();
+    BatchState *bs = E[B_BSTATE].as<BatchState>();
+    long long *chunks = E[B_CHUNKS].as<long long>();
+    int64_t *coff = E[B_COFF].as<int64_t>();
+    Flags *fl = ea.fl;
+    ws.clean = false;  // until the batch has cleared everything it touched
+
+    SABA_HIP_TRY(hipMemcpyAsync(d_slots, hslots.data(), sizeof(Slot) * nb, hipMemcpyHostToDevice,
+                                s));
+    SABA_HIP_TRY(hipMemcpyAsync(d_eb, heb.data(), sizeof(int64_t) * (nb + 1),
+                                hipMemcpyHostToDevice, s));
+    batch_init_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
+        g->vrec, g->col_idx, d_slots, ea.psets, nb, bs, hA, FA, bmA, ea.tau, ea.D, ea.nreq, ea.MC,
+        ea.vis0, ea.vis1, fl);
+    SABA_HIP_TRY(hipGetLastError());
+    const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, maxgn / 4096));
+    const dim3 grid(ysplit, (unsigned)nb);
+    for (int32_t level = 0;; ++level) {
+        const int cur = level & 1;
+        double *hcur = cur ? hB : hA, *hnext = cur ? hA : hB;
+        int32_t *Fcur = cur ? FB : FA, *Fnext = cur ? FA : FB;
+        uint32_t *bmcur = cur ? bmB : bmA, *bmnext = cur ? bmA : bmB;
+        SABA_HIP_TRY(hipMemsetAsync(&fl->any_active, 0, sizeof(int32_t), s));
+        level_decide_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
+            g->vrec, g->col_idx, d_slots, ea.psets, bs, nb, level, hcur, ea.tau, ea.D,
+            ea.ttau_inst, fl);
+        SABA_HIP_TRY(hipGetLastError());
+        int32_t any = 0;
+        SABA_HIP_TRY(
+            hipMemcpyAsync(&any, &fl->any_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SABA_HIP_TRY(hipStreamSynchronize(s));
+        if (!any) break;
+        expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, level,
+                                              Fcur, bmnext, slotbm, fl);
+        compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(d_slots, bs, level, bmnext, Fnext);
+        pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hcur, bmcur,
+                                            slotbm, hnext, Fnext, fl);
+        clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, cur, true, hA, hB, bmA, bmB, FA,
+                                                   FB);
+        SABA_HIP_TRY(hipGetLastError());
+    }
+    // walk pairs of the batch's instance edges
+    nreq_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
+        g->vrec, d_slots, ea.psets, bs, nb, ie0, ea.tau, ea.want, ea.nreq, chunks, fl);
+    SABA_HIP_TRY(hipGetLastError());
+    SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(chunks), coff, nle, E[B_SCAN].ptr, s));
+    int64_t T = 0;
+    int32_t err = 0;
+    SABA_HIP_TRY(hipMemcpyAsync(&T, coff + nle, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SABA_HIP_TRY(hipMemcpyAsync(&err, &fl->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SABA_HIP_TRY(hipStreamSynchronize(s));
+    if (err & kErrOverflow) {
+        set_error("walk count overflows the 64-bit range (eps too small?)");
+        return SABA_E_OVERFLOW;  // the pools stay marked dirty: re-zeroed before the next use
+    }
+    SABA_TRY(E[B_PART].ensure(sizeof(double) * std::max<int64_t>(T, 1)));
+    double *partial = E[B_PART].as<double>();
+    if (T > 0) {
+        const bool timing = tm && tm->on;
+        if (timing) SABA_HIP_TRY(hipEventRecord(tm->a, s));
+        mc_walk_kernel<<<grid_for(T, kWavesPerBlock, kWalkGrid), kBlock, 0, s>>>(
+            g->vrec, g->col_idx, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq,
+            hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl);
+        SABA_HIP_TRY(hipGetLastError());
+        if (timing) {
+            SABA_HIP_TRY(hipEventRecord(tm->b, s));
+            SABA_HIP_TRY(hipEventSynchronize(tm->b));
+            float ms = 0.f;
+            SABA_HIP_TRY(hipEventElapsedTime(&ms, tm->a, tm->b));
+            tm->walk_ms += ms;
+        }
+    }
+    edge_reduce_kernel<<<grid_for(nle, 256, 1 << 16), 256, 0, s>>>(
+        g->vrec, d_slots, nb, d_eb, ie0, coff, nle, ea.want, ea.nreq, ea.D, partial, ea.MC, ea.g);
+    // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
+    clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, -1, false, hA, hB, bmA, bmB, FA, FB);
+    SABA_HIP_TRY(hipGetLastError());
+    ws.clean = true;
+    return SABA_OK;
+}
+
+// ------------------------------------------------------------ synchronous calls
 struct Request {
     int32_t graph = 0;
     saba_aesc_params p{};
@@ -770,36 +950,11 @@ static bool same_params(const Request &a, const Request &b) {
            (x.push_all != 0) == (y.push_all != 0);
 }
 
-static int check_params(const Graph *g, const Request &r) {
-    const saba_aesc_params *p = &r.p;
-    if (r.graph < 0 || r.graph >= g->ngraphs) {
-        set_error("request names a graph the handle does not hold");
-        return SABA_E_INVALID;
-    }
-    if (!(p->eps > 0.0) || !(p->delta > 0.0 && p->delta < 1.0) || !(p->lambda >= 0.0) ||
-        p->group < 1 || p->spread > 31 ||
-        (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) ||
-        r.q < -1 || (r.q > 0 && !r.edges)) {
-        set_error("invalid estimator parameters");
-        return SABA_E_INVALID;
-    }
-    const int32_t a = g->goff[r.graph], z = g->goff[r.graph + 1];
-    if (!g->gconnected[r.graph] || z - a < 2) {
-        set_error("the estimator needs a connected graph with at least one edge");
-        return SABA_E_DISCONNECTED;
-    }
-    if (g->gbipartite[r.graph] || !(p->lambda < 1.0)) {
-        set_error("the estimator needs a non-bipartite graph (lambda < 1)");
-        return SABA_E_BIPARTITE;
-    }
-    return SABA_OK;
-}
-
 static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const Exports *ex,
                     saba_stats *st, hipStream_t s) {
     const int32_t *rp = g->h_row_ptr.data();
     const int32_t *ci = g->h_col_idx.data();
-    for (auto &r : reqs) SABA_TRY(check_params(g, r));
+    for (auto &r : reqs) SABA_TRY(check_request(g, r.graph, r.p, r.q, r.edges));
 
     // parameter sets: requests with equal (graph, parameters) share their instances
     std::vector<PSet> psets;
@@ -810,21 +965,9 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         for (size_t k = 0; k < plead.size(); ++k)
             if (same_params(reqs[plead[k]], reqs[i])) pid = (int32_t)k;
         if (pid < 0) {
-            const Request &r = reqs[i];
-            const int64_t m = ((int64_t)rp[g->goff[r.graph + 1]] - rp[g->goff[r.graph]]) / 2;
-            PSet ps;
-            ps.lambda = r.p.lambda;
-            ps.eps = r.p.eps;
-            ps.c = 32.0 * std::log(4.0 * (double)m / r.p.delta) / (r.p.eps * r.p.eps);
-            ps.seed = r.p.seed;
-            ps.G = r.p.group;
-            ps.S = r.p.spread;
-            ps.tau_cap = r.p.tau_cap > 0 ? r.p.tau_cap : 4096;
-            ps.tilde_tau_max = r.p.tilde_tau_max;
-            ps.push_all = r.p.push_all ? 1 : 0;
             pid = (int32_t)psets.size();
-            psets.push_back(ps);
-            pgraph.push_back(r.graph);
+            psets.push_back(make_pset(g, reqs[i].graph, reqs[i].p));
+            pgraph.push_back(reqs[i].graph);
             plead.push_back((int32_t)i);
         }
         reqs[i].pid = pid;
@@ -917,47 +1060,32 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         }
     }
 
-    const bool timing = st && opt.time_kernels;
-    hipEvent_t ev[4] = {};
+    BatchTiming tm;
+    tm.on = st && opt.time_kernels;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     struct EvGuard {
-        hipEvent_t *ev;
+        hipEvent_t *e[4];
         ~EvGuard() {
-            for (int i = 0; i < 4; ++i)
-                if (ev[i]) (void)hipEventDestroy(ev[i]);
+            for (auto *x : e)
+                if (*x) (void)hipEventDestroy(*x);
         }
-    } evguard{ev};
-    if (timing)
-        for (auto &e : ev) SABA_HIP_TRY(hipEventCreate(&e));
-    float walk_ms = 0.f;
-    if (timing) SABA_HIP_TRY(hipEventRecord(ev[0], s));
+    } evguard{{&ev0, &ev1, &tm.a, &tm.b}};
+    if (tm.on) {
+        SABA_HIP_TRY(hipEventCreate(&ev0));
+        SABA_HIP_TRY(hipEventCreate(&ev1));
+        SABA_HIP_TRY(hipEventCreate(&tm.a));
+        SABA_HIP_TRY(hipEventCreate(&tm.b));
+        SABA_HIP_TRY(hipEventRecord(ev0, s));
+    }
 
-    auto &E = g->est;
-    const int64_t NE1 = std::max<int64_t>(NE, 1);
-    SABA_TRY(E[B_PSET].ensure(sizeof(PSet) * std::max(P, 1)));
-    SABA_TRY(E[B_WANT].ensure(NE1));
-    SABA_TRY(E[B_TAU].ensure(sizeof(int32_t) * NE1));
-    SABA_TRY(E[B_D].ensure(sizeof(double) * NE1));
-    SABA_TRY(E[B_NREQ].ensure(sizeof(long long) * NE1));
-    SABA_TRY(E[B_MC].ensure(sizeof(double) * NE1));
-    SABA_TRY(E[B_VIS0].ensure(sizeof(long long) * NE1));
-    SABA_TRY(E[B_VIS1].ensure(sizeof(long long) * NE1));
-    SABA_TRY(E[B_G].ensure(sizeof(double) * NE1));
-    SABA_TRY(E[B_TTAU].ensure(sizeof(int32_t) * std::max<int64_t>(ns, 1)));
-    SABA_TRY(E[B_FLAGS].ensure(sizeof(Flags)));
-    PSet *d_psets = E[B_PSET].as<PSet>();
-    uint8_t *d_want = E[B_WANT].as<uint8_t>();
-    int32_t *tau = E[B_TAU].as<int32_t>();
-    double *D = E[B_D].as<double>();
-    long long *nreq = E[B_NREQ].as<long long>();
-    double *MC = E[B_MC].as<double>();
-    auto *vis0 = E[B_VIS0].as<unsigned long long>();
-    auto *vis1 = E[B_VIS1].as<unsigned long long>();
-    double *gd = E[B_G].as<double>();
-    int32_t *ttau_inst = E[B_TTAU].as<int32_t>();
-    Flags *fl = E[B_FLAGS].as<Flags>();
-    SABA_HIP_TRY(hipMemcpyAsync(d_psets, psets.data(), sizeof(PSet) * P, hipMemcpyHostToDevice, s));
-    SABA_HIP_TRY(hipMemcpyAsync(d_want, want.data(), NE1, hipMemcpyHostToDevice, s));
-    SABA_HIP_TRY(hipMemsetAsync(fl, 0, sizeof(Flags), s));
+    Workspace &ws = g->est;
+    EdgeArrays ea;
+    SABA_TRY(ensure_edge_arrays(ws, NE, ns, P, &ea));
+    SABA_HIP_TRY(hipMemcpyAsync(const_cast<PSet *>(ea.psets), psets.data(), sizeof(PSet) * P,
+                                hipMemcpyHostToDevice, s));
+    SABA_HIP_TRY(hipMemcpyAsync(const_cast<uint8_t *>(ea.want), want.data(),
+                                std::max<int64_t>(NE, 1), hipMemcpyHostToDevice, s));
+    SABA_HIP_TRY(hipMemsetAsync(ea.fl, 0, sizeof(Flags), s));
 
     // batches: consecutive instances whose slots fit the memory budget
     size_t freeb = 0, totalb = 0;
@@ -965,15 +1093,8 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     const int64_t budget = opt.mem_budget > 0
                                ? opt.mem_budget
                                : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
-    std::vector<int64_t> slot_h(P), slot_bm(P), slot_sb(P), slot_bytes(P);
-    for (int32_t k = 0; k < P; ++k) {
-        const int32_t ga = g->goff[pgraph[k]], gz = g->goff[pgraph[k] + 1];
-        const int64_t gn = gz - ga, gnnz = (int64_t)rp[gz] - rp[ga];
-        slot_h[k] = gn;
-        slot_bm[k] = (gn + 31) / 32;
-        slot_sb[k] = (gnnz + 31) / 32;
-        slot_bytes[k] = gn * (2 * 8 + 2 * 4) + 2 * 4 * slot_bm[k] + 4 * slot_sb[k];
-    }
+    std::vector<SlotSize> ssz(P);
+    for (int32_t k = 0; k < P; ++k) ssz[k] = slot_size(g, pgraph[k]);
     struct Batch {
         int64_t i0, i1, h, bm, sb, ne;
     };
@@ -983,14 +1104,14 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         Batch bt{i, i, 0, 0, 0, 0};
         int64_t bytes = 0;
         while (bt.i1 < ns) {
-            const int32_t k = inst_p[bt.i1];
-            if (bt.i1 > bt.i0 && (bytes + slot_bytes[k] > budget || bt.i1 - bt.i0 >= 65535 ||
+            const SlotSize &z = ssz[inst_p[bt.i1]];
+            if (bt.i1 > bt.i0 && (bytes + z.bytes > budget || bt.i1 - bt.i0 >= 65535 ||
                                   (opt.batch_sources > 0 && bt.i1 - bt.i0 >= opt.batch_sources)))
                 break;
-            bytes += slot_bytes[k];
-            bt.h += slot_h[k];
-            bt.bm += slot_bm[k];
-            bt.sb += slot_sb[k];
+            bytes += z.bytes;
+            bt.h += z.h;
+            bt.bm += z.bm;
+            bt.sb += z.sb;
             ++bt.i1;
         }
         bt.ne = iebase[bt.i1] - iebase[bt.i0];
@@ -1002,47 +1123,13 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         batches.push_back(bt);
         i = bt.i1;
     }
-
-    const bool grow = E[B_HA].bytes < sizeof(double) * (size_t)std::max<int64_t>(maxh, 1) ||
-                      E[B_BMA].bytes < sizeof(uint32_t) * (size_t)std::max<int64_t>(maxbm, 1) ||
-                      E[B_SLOTBM].bytes < sizeof(uint32_t) * (size_t)std::max<int64_t>(maxsb, 1);
-    SABA_TRY(E[B_HA].ensure(sizeof(double) * std::max<int64_t>(maxh, 1)));
-    SABA_TRY(E[B_HB].ensure(sizeof(double) * std::max<int64_t>(maxh, 1)));
-    SABA_TRY(E[B_FA].ensure(sizeof(int32_t) * std::max<int64_t>(maxh, 1)));
-    SABA_TRY(E[B_FB].ensure(sizeof(int32_t) * std::max<int64_t>(maxh, 1)));
-    SABA_TRY(E[B_BMA].ensure(sizeof(uint32_t) * std::max<int64_t>(maxbm, 1)));
-    SABA_TRY(E[B_BMB].ensure(sizeof(uint32_t) * std::max<int64_t>(maxbm, 1)));
-    SABA_TRY(E[B_SLOTBM].ensure(sizeof(uint32_t) * std::max<int64_t>(maxsb, 1)));
-    SABA_TRY(E[B_SLOT].ensure(sizeof(Slot) * std::max<int64_t>(maxnb, 1)));
-    SABA_TRY(E[B_EB].ensure(sizeof(int64_t) * (maxnb + 1)));
-    SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * std::max<int64_t>(maxnb, 1)));
-    SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * std::max<int64_t>(maxne, 1)));
-    SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (maxne + 1)));
-    SABA_TRY(E[B_SCAN].ensure(scan_tmp_bytes(std::max<int64_t>(maxne, 1))));
-    double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
-    int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
-    uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
-    uint32_t *slotbm = E[B_SLOTBM].as<uint32_t>();
-    Slot *d_slots = E[B_SLOT].as<Slot>();
-    int64_t *d_eb = E[B_EB].as<int64_t>();
-    BatchState *bs = E[B_BSTATE].as<BatchState>();
-    long long *chunks = E[B_CHUNKS].as<long long>();
-    int64_t *coff = E[B_COFF].as<int64_t>();
-    if (grow || !g->est_clean) {
-        // dense vectors and bitmaps start at zero and are kept clean by the sparse clears
-        SABA_HIP_TRY(hipMemsetAsync(hA, 0, E[B_HA].bytes, s));
-        SABA_HIP_TRY(hipMemsetAsync(hB, 0, E[B_HB].bytes, s));
-        SABA_HIP_TRY(hipMemsetAsync(bmA, 0, E[B_BMA].bytes, s));
-        SABA_HIP_TRY(hipMemsetAsync(bmB, 0, E[B_BMB].bytes, s));
-        SABA_HIP_TRY(hipMemsetAsync(slotbm, 0, E[B_SLOTBM].bytes, s));
-    }
-    g->est_clean = false;  // until this call has cleared everything it touched
+    SABA_TRY(ensure_pools(ws, maxh, maxbm, maxsb, maxnb, maxne, s));
 
     std::vector<Slot> hslots;
     std::vector<int64_t> heb;
     for (const Batch &bt : batches) {
         const int32_t nb = (int32_t)(bt.i1 - bt.i0);
-        const int64_t ie0 = iebase[bt.i0], nle = bt.ne;
+        const int64_t ie0 = iebase[bt.i0];
         hslots.resize(nb);
         heb.resize(nb + 1);
         int64_t ho = 0, bo = 0, so = 0, maxgn = 1;
@@ -1061,91 +1148,21 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             sl.gn = g->goff[gi + 1] - g->goff[gi];
             sl.gpos = rp[sl.goff];
             sl.pad = 0;
-            ho += slot_h[k];
-            bo += slot_bm[k];
-            so += slot_sb[k];
+            ho += ssz[k].h;
+            bo += ssz[k].bm;
+            so += ssz[k].sb;
             maxgn = std::max<int64_t>(maxgn, sl.gn);
             heb[b] = iebase[i] - ie0;
         }
-        heb[nb] = nle;
-        SABA_HIP_TRY(hipMemcpyAsync(d_slots, hslots.data(), sizeof(Slot) * nb,
-                                    hipMemcpyHostToDevice, s));
-        SABA_HIP_TRY(hipMemcpyAsync(d_eb, heb.data(), sizeof(int64_t) * (nb + 1),
-                                    hipMemcpyHostToDevice, s));
-        batch_init_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-            g->vrec, g->col_idx, d_slots, d_psets, nb, bs, hA, FA, bmA, tau, D, nreq, MC, vis0,
-            vis1, fl);
-        SABA_HIP_TRY(hipGetLastError());
-        const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, maxgn / 4096));
-        const dim3 grid(ysplit, (unsigned)nb);
-        for (int32_t level = 0;; ++level) {
-            const int cur = level & 1;
-            double *hcur = cur ? hB : hA, *hnext = cur ? hA : hB;
-            int32_t *Fcur = cur ? FB : FA, *Fnext = cur ? FA : FB;
-            uint32_t *bmcur = cur ? bmB : bmA, *bmnext = cur ? bmA : bmB;
-            SABA_HIP_TRY(hipMemsetAsync(&fl->any_active, 0, sizeof(int32_t), s));
-            level_decide_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-                g->vrec, g->col_idx, d_slots, d_psets, bs, nb, level, hcur, tau, D, ttau_inst, fl);
-            SABA_HIP_TRY(hipGetLastError());
-            int32_t any = 0;
-            SABA_HIP_TRY(hipMemcpyAsync(&any, &fl->any_active, sizeof(int32_t),
-                                        hipMemcpyDeviceToHost, s));
-            SABA_HIP_TRY(hipStreamSynchronize(s));
-            if (!any) break;
-            expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, level,
-                                                  Fcur, bmnext, slotbm, fl);
-            compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(d_slots, bs, level, bmnext,
-                                                                    Fnext);
-            pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hcur,
-                                                bmcur, slotbm, hnext, Fnext, fl);
-            clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, cur, true, hA, hB, bmA, bmB,
-                                                       FA, FB);
-            SABA_HIP_TRY(hipGetLastError());
-        }
-        // walk pairs of the batch's instance edges
-        nreq_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
-            g->vrec, d_slots, d_psets, bs, nb, ie0, tau, d_want, nreq, chunks, fl);
-        SABA_HIP_TRY(hipGetLastError());
-        SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(chunks), coff, nle, E[B_SCAN].ptr, s));
-        int64_t T = 0;
-        Flags hf;
-        SABA_HIP_TRY(hipMemcpyAsync(&T, coff + nle, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SABA_HIP_TRY(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
-        SABA_HIP_TRY(hipStreamSynchronize(s));
-        if (hf.err & kErrOverflow) {
-            set_error("walk count overflows the 64-bit range (eps too small?)");
-            return SABA_E_OVERFLOW;  // scratch stays marked dirty: re-zeroed on the next call
-        }
-        SABA_TRY(E[B_PART].ensure(sizeof(double) * std::max<int64_t>(T, 1)));
-        double *partial = E[B_PART].as<double>();
-        if (T > 0) {
-            if (timing) SABA_HIP_TRY(hipEventRecord(ev[1], s));
-            mc_walk_kernel<<<grid_for(T, kWavesPerBlock, kWalkGrid), kBlock, 0, s>>>(
-                g->vrec, g->col_idx, d_slots, d_psets, bs, nb, d_eb, ie0, coff, nle, tau, nreq, hA,
-                hB, bmA, bmB, partial, vis0, vis1, fl);
-            SABA_HIP_TRY(hipGetLastError());
-            if (timing) {
-                SABA_HIP_TRY(hipEventRecord(ev[2], s));
-                SABA_HIP_TRY(hipEventSynchronize(ev[2]));
-                float ms = 0.f;
-                SABA_HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[2]));
-                walk_ms += ms;
-            }
-        }
-        edge_reduce_kernel<<<grid_for(nle, 256, 1 << 16), 256, 0, s>>>(
-            g->vrec, d_slots, nb, d_eb, ie0, coff, nle, d_want, nreq, D, partial, MC, gd);
-        // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
-        clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, -1, false, hA, hB, bmA, bmB, FA,
-                                                   FB);
-        SABA_HIP_TRY(hipGetLastError());
+        heb[nb] = bt.ne;
+        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, &tm, s));
     }
-    g->est_clean = true;
 
     // results of every request
     int64_t npairs = 0;
     for (auto &qp : qpairs) npairs += (int64_t)qp.size();
-    SABA_TRY(E[B_PAIRS].ensure(sizeof(int64_t) * std::max<int64_t>(npairs, 1)));
-    int64_t *d_pairs = E[B_PAIRS].as<int64_t>();
+    SABA_TRY(ws.b[B_PAIRS].ensure(sizeof(int64_t) * std::max<int64_t>(npairs, 1)));
+    int64_t *d_pairs = ws.b[B_PAIRS].as<int64_t>();
     int64_t off = 0;
     for (size_t i = 0; i < reqs.size(); ++i) {
         const Request &r = reqs[i];
@@ -1155,13 +1172,13 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             const int64_t cb = g->cbase[r.graph], m = g->cbase[r.graph + 1] - cb;
             if (m > 0)
                 finalize_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, s>>>(
-                    g->canon, g->rev, cb, m, pbase[r.pid], rp[ga], gd, r.sc);
+                    g->canon, g->rev, cb, m, pbase[r.pid], rp[ga], ea.g, r.sc);
         } else if (r.q > 0) {
             SABA_HIP_TRY(hipMemcpyAsync(d_pairs + off, qpairs[i].data(),
                                         sizeof(int64_t) * qpairs[i].size(), hipMemcpyHostToDevice,
                                         s));
             finalize_pairs_kernel<<<grid_for(r.q, 256, 1 << 16), 256, 0, s>>>(d_pairs + off, r.q,
-                                                                             gd, r.sc);
+                                                                             ea.g, r.sc);
             off += (int64_t)qpairs[i].size();
         }
         SABA_HIP_TRY(hipGetLastError());
@@ -1172,22 +1189,22 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             if (dst) SABA_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
             return SABA_OK;
         };
-        SABA_TRY(cp(ex->tau, tau, sizeof(int32_t) * nnz));
-        SABA_TRY(cp(ex->nreq, nreq, sizeof(int64_t) * nnz));
-        SABA_TRY(cp(ex->D, D, sizeof(double) * nnz));
-        SABA_TRY(cp(ex->MC, MC, sizeof(double) * nnz));
-        SABA_TRY(cp(ex->vis0, vis0, sizeof(int64_t) * nnz));
-        SABA_TRY(cp(ex->vis1, vis1, sizeof(int64_t) * nnz));
-        SABA_TRY(cp(ex->g, gd, sizeof(double) * nnz));
+        SABA_TRY(cp(ex->tau, ea.tau, sizeof(int32_t) * nnz));
+        SABA_TRY(cp(ex->nreq, ea.nreq, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->D, ea.D, sizeof(double) * nnz));
+        SABA_TRY(cp(ex->MC, ea.MC, sizeof(double) * nnz));
+        SABA_TRY(cp(ex->vis0, ea.vis0, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->vis1, ea.vis1, sizeof(int64_t) * nnz));
+        SABA_TRY(cp(ex->g, ea.g, sizeof(double) * nnz));
         if (ex->ttau && nnz > 0) {
             export_ttau_kernel<<<grid_for(nnz, 256, 1 << 16), 256, 0, s>>>(g->row_of, nnz,
-                                                                           ttau_inst, ex->ttau);
+                                                                           ea.ttau_inst, ex->ttau);
             SABA_HIP_TRY(hipGetLastError());
         }
     }
-    if (timing) SABA_HIP_TRY(hipEventRecord(ev[3], s));
+    if (tm.on) SABA_HIP_TRY(hipEventRecord(ev1, s));
     Flags hf;
-    SABA_HIP_TRY(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
+    SABA_HIP_TRY(hipMemcpyAsync(&hf, ea.fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
     SABA_HIP_TRY(hipStreamSynchronize(s));
     if (st) {
         *st = saba_stats{};
@@ -1199,10 +1216,10 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         st->max_tau = hf.max_tau;
         st->max_ttau = hf.max_ttau;
         st->warnings = hf.warnings;
-        if (timing) {
+        if (tm.on) {
             float tot = 0.f;
-            SABA_HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev[3]));
-            st->kernel_ms = walk_ms;
+            SABA_HIP_TRY(hipEventElapsedTime(&tot, ev0, ev1));
+            st->kernel_ms = tm.walk_ms;
             st->total_ms = tot;
         }
     }

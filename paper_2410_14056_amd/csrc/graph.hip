@@ -19,8 +19,9 @@ void clear_error() { g_last_error.clear(); }
 
 int DevBuf::ensure(size_t want) {
     if (want <= bytes && ptr) return SABA_OK;
+    const size_t grown = bytes + bytes / 4;
     release();
-    size_t sz = std::max<size_t>(want, 256);
+    size_t sz = std::max<size_t>(std::max(want, grown), 256);
     hipError_t e = hipMalloc(&ptr, sz);
     if (e != hipSuccess) {
         ptr = nullptr;
@@ -251,7 +252,7 @@ static void destroy_graph(Graph *g) {
     if (g->row_of) (void)hipFree(g->row_of);
     if (g->slotv) (void)hipFree(g->slotv);
     for (auto &b : g->walk_scratch) b.release();
-    for (auto &b : g->est) b.release();
+    g->est.release();
     delete g;
 }
 

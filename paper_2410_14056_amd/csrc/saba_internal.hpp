@@ -31,7 +31,8 @@ void clear_error();
         if (_rc != SABA_OK) return _rc; \
     } while (0)
 
-// Grow-only device buffer owned by a graph handle.
+// Grow-only device buffer.  A buffer that has to grow is reallocated with a quarter of
+// headroom, so a sequence of slowly growing requests reallocates only a few times.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -39,6 +40,18 @@ struct DevBuf {
     void release();
     template <class T>
     T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Scratch of one estimator stream: per-batch pools and per-instance-edge arrays.  `clean`
+// records that the dense vectors and bitmaps of the pools are all zero (the estimator keeps
+// them so by clearing exactly what it touched).
+struct Workspace {
+    DevBuf b[32];
+    bool clean = false;
+    void release() {
+        for (auto &x : b) x.release();
+        clean = false;
+    }
 };
 
 // Device-resident graph.  vrec[v] = (row start, degree) so one 8-byte gather gives
@@ -66,10 +79,9 @@ struct Graph {
     int32_t *canon = nullptr;
     int32_t *row_of = nullptr;  // source vertex of each CSR entry
     int32_t *slotv = nullptr;   // rev[e] if the row of col[e] is longer than kHubRow, else -1
-    bool est_clean = false;     // estimator scratch vectors are all zero
-    // reusable scratch
-    DevBuf walk_scratch[4];
-    DevBuf est[32];
+    // reusable scratch of the synchronous calls
+    DevBuf walk_scratch[8];
+    Workspace est;
 };
 
 // Rows longer than this are "hub rows": the estimator finds their terms through a bitmap

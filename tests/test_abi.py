@@ -19,7 +19,9 @@ def test_header_declares_the_boundary():
     names = declared()
     for want in ("saba_version", "saba_last_error", "saba_graph_create", "saba_graph_destroy",
                  "saba_graph_create_multi", "saba_graph_info", "saba_walks", "saba_aesc",
-                 "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch"):
+                 "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch",
+                 "saba_server_create", "saba_server_submit", "saba_server_wait",
+                 "saba_server_stats", "saba_server_destroy"):
         assert want in names
 
 
@@ -63,3 +65,57 @@ def test_structs_match_header_layout():
     # saba_aesc_request: 2 x int32, params (64), pointer, int64, pointer -> 96 bytes
     assert ctypes.sizeof(b.AescRequest) == 96
     assert ctypes.sizeof(b.BatchOptions) == 16
+
+
+def test_server_structs_match_the_c_compiler(tmp_path):
+    """sizeof and field offsets as gcc lays the header's structs out, against the binding."""
+    import ctypes
+    from paper_2410_14056_amd import _binding as b
+    checks = {
+        "saba_server_options": (b.ServerOptions, ["mem_budget", "max_queued_edges", "arena_edges",
+                                                  "lanes", "max_batch_sources"]),
+        "saba_server_request": (b.ServerRequest, ["graph", "params", "edges", "q", "d_sc"]),
+        "saba_server_result": (b.ServerResult, ["status", "batches", "instances", "queue_ms",
+                                                "latency_ms"]),
+        "saba_server_stats_t": (b.ServerStats, [f for f, _ in b.ServerStats._fields_]),
+        "saba_aesc_request": (b.AescRequest, ["graph", "params", "d_edges", "q", "d_sc"]),
+        "saba_aesc_params": (b.AescParams, ["eps", "delta", "seed", "tau_cap", "mem_budget"]),
+        "saba_stats": (b.Stats, ["walks", "warnings", "kernel_ms", "count_ms"]),
+        "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources"]),
+        "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saba.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                         text=True, check=True).stdout.splitlines())
+    for cname, (cls, fields) in checks.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in fields:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_server_entry_points_reject_null_handles():
+    """Host-side argument checks of the server calls (no device is touched)."""
+    import ctypes
+    import paper_2410_14056_amd as saba
+    from paper_2410_14056_amd import _binding as b
+    lib = saba.load()
+    out = ctypes.c_void_p(123)
+    assert lib.saba_server_create(None, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    t = ctypes.c_uint64()
+    assert lib.saba_server_submit(None, None, ctypes.byref(t)) == -1
+    assert lib.saba_server_wait(None, ctypes.c_uint64(1), 0, None) == -1
+    assert lib.saba_server_stats(None, None) == -1
+    assert lib.saba_server_destroy(None) == 0
+    assert b"NULL" in lib.saba_last_error() or lib.saba_last_error() == b""

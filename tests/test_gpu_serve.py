@@ -1,0 +1,160 @@
+"""Query server (saba_server_*): continuous batching must not change any result.  Every served
+request is compared bit for bit with the same request run alone through saba_aesc_query on a
+handle holding only its graph, under batch sizes and lane counts that force its sources to be
+split across batches and streams, and with requests arriving while others run."""
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def saba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_14056_amd as saba
+    saba.load()
+    return saba
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    gs = [
+        graphgen.largest_component(graphgen.er_gnm(300, 1200, 3)),
+        graphgen.largest_component(graphgen.chung_lu(3000, 8, 2.3, 5)),
+        graphgen.largest_component(graphgen.grid_diagonals(12, 15, 0.05, 2)),
+        graphgen.toy_graph(),
+    ]
+    lams = [graphgen.spectral_lambda(g) for g in gs]
+    return gs, lams
+
+
+def _requests(gs, lams, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        k = int(rng.integers(len(gs)))
+        g = gs[k]
+        ce = graphgen.canonical_edges(g)
+        q = int(rng.integers(1, min(g.m, 40) + 1))
+        e = ce[rng.choice(g.m, q, replace=False)].copy()
+        flip = rng.random(q) < 0.5  # either orientation is a valid query
+        e[flip] = e[flip][:, ::-1]
+        reqs.append({"graph": k, "edges": np.ascontiguousarray(e, dtype=np.int32),
+                     "eps": float(rng.choice([0.1, 0.2, 0.3])), "seed": int(rng.integers(1, 4)),
+                     "tau_cap": 64})
+    return reqs
+
+
+def _alone(saba, gs, lams, r):
+    import torch
+    sg = saba.SabaGraph.from_graph(gs[r["graph"]])
+    sc, _ = saba.aesc_query(sg, torch.from_numpy(r["edges"]).cuda(), r["eps"], lams[r["graph"]],
+                            r["seed"], tau_cap=r["tau_cap"])
+    return sc.cpu().numpy()
+
+
+def _submit(srv, lams, r):
+    return srv.submit(r["graph"], r["edges"], r["eps"], lams[r["graph"]], r["seed"],
+                      tau_cap=r["tau_cap"])
+
+
+def test_served_results_equal_alone(saba, orc, graphs):
+    gs, lams = graphs
+    mg = saba.SabaGraph.from_graphs(gs)
+    reqs = _requests(gs, lams, 14, 1)
+    expect = [_alone(saba, gs, lams, r) for r in reqs]
+    with saba.SabaServer(mg, lanes=2, max_batch_sources=5) as srv:
+        tickets = [_submit(srv, lams, r) for r in reqs]
+        for t, r, e in zip(tickets, reqs, expect):
+            sc, res = srv.wait(t)
+            assert res["status"] == 0
+            assert res["instances"] == len(np.unique(r["edges"]))
+            assert res["batches"] >= 1 and res["latency_ms"] >= res["queue_ms"] >= 0.0
+            assert np.array_equal(sc.cpu().numpy(), e)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0 and st["queued_edges"] == 0
+        assert st["instances"] == sum(len(np.unique(r["edges"])) for r in reqs)
+        assert st["batches"] >= 2
+    # and the oracle (Alg. 1 for the first graph, all edges) agrees on the served values
+    r0 = next(r for r in reqs if r["graph"] == 0)
+    so, _ = orc.aesc(gs[0], r0["eps"], lams[0], r0["seed"], tau_cap=64, query=r0["edges"])
+    np.testing.assert_allclose(expect[reqs.index(r0)], so, rtol=1e-12, atol=1e-15)
+
+
+def test_staggered_arrivals_and_lanes(saba, graphs):
+    """Requests submitted while others run, waited for out of order, on three lanes with tiny
+    batches, plus duplicate pairs in one request: still identical to running alone."""
+    gs, lams = graphs
+    mg = saba.SabaGraph.from_graphs(gs)
+    reqs = _requests(gs, lams, 12, 2)
+    dup = dict(reqs[0])
+    dup["edges"] = np.ascontiguousarray(np.concatenate([reqs[0]["edges"],
+                                                        reqs[0]["edges"][::-1, ::-1]]))
+    reqs.append(dup)
+    expect = [_alone(saba, gs, lams, r) for r in reqs]
+    got = {}
+    with saba.SabaServer(mg, lanes=3, max_batch_sources=3) as srv:
+        live = []
+        for i, r in enumerate(reqs):
+            live.append((i, _submit(srv, lams, r)))
+            if i % 4 == 3:  # wait for an earlier one while later ones keep arriving
+                j, t = live.pop(0)
+                got[j] = srv.wait(t)[0].cpu().numpy()
+        for j, t in reversed(live):
+            got[j] = srv.wait(t)[0].cpu().numpy()
+    for i, e in enumerate(expect):
+        assert np.array_equal(got[i], e), i
+    q0 = len(reqs[0]["edges"])
+    assert np.array_equal(got[len(reqs) - 1][:q0], got[len(reqs) - 1][q0:][::-1])
+
+
+def test_backpressure_and_errors(saba, graphs):
+    gs, lams = graphs
+    mg = saba.SabaGraph.from_graphs(gs)
+    big = graphgen.canonical_edges(gs[1])[:200]
+    with saba.SabaServer(mg, lanes=1, max_queued_edges=250, arena_edges=300) as srv:
+        t0 = srv.submit(1, big, 0.1, lams[1], 1, tau_cap=64)
+        # the queue holds 200 edges until that request finishes: 100 more exceed the bound
+        with pytest.raises(saba.SabaError) as ei:
+            srv.submit(1, big[:100], 0.1, lams[1], 1, tau_cap=64)
+        assert ei.value.name == "SABA_E_BUSY"
+        sc0, _ = srv.wait(t0)
+        t1 = srv.submit(1, big[:100], 0.1, lams[1], 1, tau_cap=64)
+        sc1, _ = srv.wait(t1)
+        assert np.array_equal(sc1.cpu().numpy(), sc0.cpu().numpy()[:100])
+        assert srv.stats()["rejected"] == 1
+        with pytest.raises(saba.SabaError) as ei:
+            srv.submit(0, np.array([[0, 0]], dtype=np.int32), 0.2, lams[0], 1)
+        assert ei.value.name == "SABA_E_NOT_EDGE"
+        with pytest.raises(saba.SabaError) as ei:  # more pairs than the arena holds
+            srv.submit(1, graphgen.canonical_edges(gs[1])[:301], 0.2, lams[1], 1)
+        assert ei.value.name == "SABA_E_INVALID"
+        with pytest.raises(saba.SabaError) as ei:
+            srv.submit(7, big[:1], 0.2, 0.5, 1)
+        assert ei.value.name == "SABA_E_INVALID"
+        with pytest.raises(saba.SabaError) as ei:
+            srv.wait(987654)
+        assert ei.value.name == "SABA_E_INVALID"
+        t = srv.submit(2, np.zeros((0, 2), dtype=np.int32), 0.2, lams[2], 1)
+        sc, res = srv.wait(t, timeout_ms=0)
+        assert sc.numel() == 0 and res["status"] == 0
+
+
+def test_destroy_with_requests_in_flight(saba, graphs):
+    """Destroying a busy server cancels what has not started and returns."""
+    gs, lams = graphs
+    mg = saba.SabaGraph.from_graphs(gs)
+    srv = saba.SabaServer(mg, lanes=2, max_batch_sources=2)
+    for r in _requests(gs, lams, 20, 3):
+        _submit(srv, lams, r)
+    srv.close()
+    # the handle is still usable afterwards
+    import torch
+    e = torch.from_numpy(graphgen.canonical_edges(gs[3])[:2].copy()).cuda()
+    sg = saba.SabaGraph.from_graph(gs[3])
+    sc, _ = saba.aesc_query(sg, e, 0.2, lams[3], 1)
+    assert sc.numel() == 2
