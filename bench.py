@@ -239,31 +239,22 @@ def progress(msg):
     print(json.dumps({"progress": msg}), file=sys.stderr, flush=True)
 
 
-def bench_batch(args, saba, torch, np):
-    """Batched estimation: 256 graphs of uneven size (n uniform in [1e3, 2e5]; one third each
-    Erdos-Renyi with average degree 8, Chung-Lu with exponent 2.3, square grids with 5% random
-    diagonals), eps drawn from {0.1, 0.2, 0.3}, 32 random query edges per graph, tau capped at
-    128.  One saba_aesc_batch call on a multi-graph handle against one saba_aesc_query call per
-    graph; both must give identical results."""
+def parallel_build(fn, items, label):
+    """Run fn over (index, spec) items in a spawn pool with one BLAS thread per worker (the
+    pool supplies the parallelism); returns the results by index, printing progress."""
     import multiprocessing as mp
-    import graphgen
-    rng = np.random.default_rng(4)
-    G = args.batch_graphs
-    specs = [(k % 3, int(rng.integers(1000, 200001)), 1000 + k) for k in range(G)]
-    epss = [float(rng.choice([0.1, 0.2, 0.3])) for _ in range(G)]
     t0 = time.perf_counter()
-    # one BLAS thread per worker process: the pool itself supplies the parallelism
     saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
     for k in saved:
         os.environ[k] = "1"
-    built = [None] * G
+    built = [None] * len(items)
+    step = max(1, len(items) // 8)
     try:
         with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-            for done, (k, res) in enumerate(pool.imap_unordered(_batch_graph_indexed,
-                                                                list(enumerate(specs))), 1):
+            for done, (k, res) in enumerate(pool.imap_unordered(fn, list(enumerate(items))), 1):
                 built[k] = res
-                if done % 32 == 0 or done == G:
-                    progress(f"batch workload: {done}/{G} graphs built "
+                if done % step == 0 or done == len(items):
+                    progress(f"{label}: {done}/{len(items)} graphs built "
                              f"({time.perf_counter() - t0:.0f} s)")
     finally:
         for k, v in saved.items():
@@ -271,6 +262,22 @@ def bench_batch(args, saba, torch, np):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+    return built
+
+
+def bench_batch(args, saba, torch, np):
+    """Batched estimation: 256 graphs of uneven size (n uniform in [1e3, 2e5]; one third each
+    Erdos-Renyi with average degree 8, Chung-Lu with exponent 2.3, square grids with 5% random
+    diagonals), eps drawn from {0.1, 0.2, 0.3}, 32 random query edges per graph, tau capped at
+    128.  One saba_aesc_batch call on a multi-graph handle against one saba_aesc_query call per
+    graph; both must give identical results."""
+    import graphgen
+    rng = np.random.default_rng(4)
+    G = args.batch_graphs
+    specs = [(k % 3, int(rng.integers(1000, 200001)), 1000 + k) for k in range(G)]
+    epss = [float(rng.choice([0.1, 0.2, 0.3])) for _ in range(G)]
+    t0 = time.perf_counter()
+    built = parallel_build(_batch_graph_indexed, specs, "batch workload")
     prep_s = time.perf_counter() - t0
     graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
     lams = [lam for _, _, lam in built]
@@ -315,6 +322,191 @@ def bench_batch(args, saba, torch, np):
             "walk_kernel_ms": st["kernel_ms"], "tau_capped": bool(st["warnings"] & 1)}
 
 
+def _serve_graph_indexed(item):
+    """One resident graph of the serving workload: the Chung-Lu generator of the 10^6-vertex
+    estimator workload (average degree 10, exponent 2.5) at its own size and seed."""
+    import graphgen
+    k, (n, seed) = item
+    g = graphgen.largest_component(graphgen.chung_lu(n, 10, 2.5, seed))
+    return k, (g.row_ptr, g.col_idx, graphgen.spectral_lambda(g))
+
+
+class _Collector:
+    """Waits for served tickets on its own thread (the wait call releases the GIL) and keeps
+    each request's outcome."""
+
+    def __init__(self, srv):
+        import queue
+        import threading
+        self.srv, self.q, self.done = srv, queue.Queue(), []
+        self.th = threading.Thread(target=self._run, daemon=True)
+        self.th.start()
+
+    def _run(self):
+        while True:
+            item = self.q.get()
+            if item is None:
+                return
+            ticket, q, keep = item
+            sc, res = self.srv.wait(ticket)
+            res["q"] = q
+            res["t_done"] = time.perf_counter()
+            if keep is not None:
+                keep[ticket] = sc
+            self.done.append(res)
+
+    def finish(self):
+        self.q.put(None)
+        self.th.join()
+        return self.done
+
+
+def _latency_summary(done, t_start):
+    import numpy as np
+    if not done:
+        return {"completed": 0}
+    lat = np.array([d["latency_ms"] for d in done])
+    edges = sum(d["q"] for d in done)
+    t_end = max(d["t_done"] for d in done)
+    return {"completed": len(done), "edges": edges,
+            "edges_per_s": edges / (t_end - t_start), "requests_per_s": len(done) / (t_end - t_start),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "queue_p50_ms": float(np.percentile([d["queue_ms"] for d in done], 50)),
+            "mean_batches_per_request": float(np.mean([d["batches"] for d in done]))}
+
+
+def bench_serve(args, saba, torch, np):
+    """Serving: 16 resident Chung-Lu graphs (n_i = round(10^(4 + 2i/15)), i = 0..15, seeds
+    1..16, largest components), SC query requests of 1-4096 uniformly chosen edges of one
+    uniformly chosen graph at eps drawn from {0.1, 0.2, 0.3}.
+      offered:   Poisson arrivals at --serve-rate requests/s for --serve-seconds, into a server
+                 whose admission queue holds --serve-queue-edges edges (beyond it requests are
+                 refused: backpressure); throughput and latency of what was served;
+      sustained: Poisson arrivals at --serve-sustain-frac of the throughput measured above, for
+                 --serve-sustain-seconds, with an unbounded queue: p50 / p99 latency;
+      plain:     the same --serve-compare requests one saba_aesc_query call each (one graph per
+                 launch) against all of them submitted to the server at once; the results must
+                 be identical."""
+    import graphgen
+    ns = [int(round(10 ** (4 + 2 * i / 15))) for i in range(16)]
+    t0 = time.perf_counter()
+    built = parallel_build(_serve_graph_indexed, [(n, i + 1) for i, n in enumerate(ns)],
+                           "serve workload")
+    prep_s = time.perf_counter() - t0
+    graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
+    lams = [lam for _, _, lam in built]
+    ces = [graphgen.canonical_edges(g) for g in graphs]
+    mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    budget = int(args.serve_mem_gib * (1 << 30))
+
+    def server(**kw):
+        return saba.SabaServer(mg, lanes=args.serve_lanes, mem_budget=budget,
+                               max_batch_sources=args.serve_max_batch, **kw)
+
+    def stream(seed):
+        rng = np.random.default_rng(seed)
+        while True:
+            k = int(rng.integers(len(graphs)))
+            q = int(rng.integers(1, 4097))
+            m = ces[k].shape[0]
+            pick = rng.choice(m, q, replace=False) if q < m else np.arange(m)
+            yield k, np.ascontiguousarray(ces[k][pick]), float(rng.choice([0.1, 0.2, 0.3]))
+
+    def submit(srv, req):
+        k, e, eps = req
+        return srv.submit(k, e, eps, lams[k], 1)
+
+    def open_loop(srv, rate, seconds, seed, label):
+        rng = np.random.default_rng(seed + 100)
+        gen = stream(seed)
+        col = _Collector(srv)
+        offered = rejected = 0
+        t_start = time.perf_counter()
+        t_next = 0.0
+        t_report = t_start + 10.0
+        while t_next < seconds:
+            now = time.perf_counter() - t_start
+            if now < t_next:
+                time.sleep(t_next - now)
+            req = next(gen)
+            offered += 1
+            try:
+                col.q.put((submit(srv, req), len(req[1]), None))
+            except saba.SabaError as e:
+                if e.name != "SABA_E_BUSY":
+                    raise
+                rejected += 1
+            t_next += float(rng.exponential(1.0 / rate))
+            if time.perf_counter() > t_report:
+                progress(f"serve {label}: {offered} offered, {rejected} refused, "
+                         f"{len(col.done)} finished")
+                t_report += 10.0
+        t_arrivals = time.perf_counter() - t_start
+        progress(f"serve {label}: arrivals over ({offered} offered, {rejected} refused); draining")
+        done = col.finish()
+        out = _latency_summary(done, t_start)
+        out.update({"offered_rate": rate, "arrival_seconds": t_arrivals, "offered": offered,
+                    "refused": rejected, "failed": sum(1 for d in done if d["status"] != 0)})
+        return out
+
+    # warm the lanes' scratch on the largest graph
+    with server() as srv:
+        t = srv.submit(15, ces[15][:256], 0.1, lams[15], 1)
+        srv.wait(t)
+    torch.cuda.synchronize()
+
+    res = {"workload": "serve_16_chung_lu_n1e4-1e6_k10_b2.5_q1-4096_eps0.1-0.3",
+           "graphs": len(graphs), "vertices": sum(g.n for g in graphs),
+           "edges": sum(g.m for g in graphs), "prep_s": prep_s, "lanes": args.serve_lanes,
+           "mem_budget_gib": args.serve_mem_gib}
+    progress("serve workload: offered load")
+    with server(max_queued_edges=args.serve_queue_edges) as srv:
+        res["offered"] = open_loop(srv, args.serve_rate, args.serve_seconds, 11, "offered")
+        res["offered"]["queue_bound_edges"] = args.serve_queue_edges
+        res["offered"]["server"] = srv.stats()
+    # the refusals favour small requests, so the capacity in requests/s is taken from the
+    # edge throughput and the mean request size (2048.5 edges)
+    cap = res["offered"].get("edges_per_s", 0.0) / 2048.5
+    rate = max(0.2, args.serve_sustain_frac * cap)
+    progress(f"serve workload: sustained load at {rate:.2f} requests/s")
+    with server(max_queued_edges=1 << 40) as srv:
+        res["sustained"] = open_loop(srv, rate, args.serve_sustain_seconds, 12, "sustained")
+        res["sustained"]["server"] = srv.stats()
+
+    # plain one-request-per-call path against the server on the same requests
+    progress("serve workload: plain calls against the server")
+    gen = stream(13)
+    reqs = [next(gen) for _ in range(args.serve_compare)]
+    handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
+    dev = [torch.from_numpy(e).cuda() for _, e, _ in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [saba.aesc_query(handles[k], d, eps, lams[k], 1, mem_budget=budget)[0]
+             for (k, _, eps), d in zip(reqs, dev)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del handles
+    keep = {}
+    with server() as srv:
+        col = _Collector(srv)
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:
+            tickets.append(submit(srv, r))
+            col.q.put((tickets[-1], len(r[1]), keep))
+        col.finish()
+        t_served = time.perf_counter() - t0
+    same = all(bool(torch.equal(p, keep[t])) for p, t in zip(plain, tickets))
+    assert same, "served results differ from the plain per-request results"
+    nedge = sum(len(e) for _, e, _ in reqs)
+    res["plain_vs_served"] = {"requests": len(reqs), "edges": nedge, "plain_s": t_plain,
+                              "plain_edges_per_s": nedge / t_plain, "served_s": t_served,
+                              "served_edges_per_s": nedge / t_served,
+                              "speedup": t_plain / t_served, "identical": same}
+    return res
+
+
 def bench_c1(args, saba, torch, np):
     """Config 1: all edges of ER n=2000, m=8000, seed 1 (largest component), eps=0.3, plain walks."""
     import graphgen
@@ -355,10 +547,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "batch", "copy"],
+    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "batch", "serve", "copy"],
                     default="all")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-edges", type=int, default=32)
+    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-mem-gib", type=float, default=32.0)
+    ap.add_argument("--serve-max-batch", type=int, default=0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-queue-edges", type=int, default=1 << 15)
+    ap.add_argument("--serve-sustain-frac", type=float, default=0.7)
+    ap.add_argument("--serve-sustain-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-compare", type=int, default=48)
     ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--spread", type=int, default=0)
@@ -412,6 +613,14 @@ def main():
         out.update({"value": b["batched_edges_per_s"], "unit": "edges/s", "dtype": "f64",
                     "ms_per_step": b["batched_s"] * 1e3, "config": {"workload": b["workload"]},
                     "batch": b})
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "serve":
+        r = bench_serve(args, saba, torch, np)
+        sus = r["sustained"]
+        out.update({"metric": METRIC, "value": r["offered"]["edges_per_s"], "unit": "edges/s",
+                    "dtype": "f64", "ms_per_step": None, "config": {"workload": r["workload"]},
+                    "p50_ms": sus.get("p50_ms"), "p99_ms": sus.get("p99_ms"), "serve": r})
         print(json.dumps(out), flush=True)
         return
     if args.workload in ("all", "c1"):

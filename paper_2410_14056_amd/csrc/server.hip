@@ -448,6 +448,44 @@ extern "C" int saba_server_create(saba_graph *gh, const saba_server_options *opt
         }
         sv->lanes.push_back(std::move(ln));
     }
+    // Pools at their largest under a lane's budget, allocated and zeroed once here so that no
+    // batch reallocates them (a reallocation would also stall the other lanes).  A pool entry
+    // count over any batch is bounded by the budget times the best entries-per-byte ratio of a
+    // graph, plus one slot, and by max_batch slots of the largest graph.
+    {
+        double rh = 0.0, rbm = 0.0, rsb = 0.0;
+        int64_t mh = 0, mbm = 0, msb = 0;
+        for (int32_t k = 0; k < g->ngraphs; ++k) {
+            const SlotSize z = slot_size(g, k);
+            if (z.bytes <= 0) continue;
+            rh = std::max(rh, (double)z.h / (double)z.bytes);
+            rbm = std::max(rbm, (double)z.bm / (double)z.bytes);
+            rsb = std::max(rsb, (double)z.sb / (double)z.bytes);
+            mh = std::max(mh, z.h);
+            mbm = std::max(mbm, z.bm);
+            msb = std::max(msb, z.sb);
+        }
+        auto cap = [&](double ratio, int64_t mx) {
+            const double by_budget = ratio * (double)sv->lane_budget + (double)mx;
+            const double by_count = (double)sv->max_batch * (double)mx;
+            return (int64_t)std::min(by_budget, by_count);
+        };
+        const int64_t ph = cap(rh, mh), pbm = cap(rbm, mbm), psb = cap(rsb, msb);
+        for (auto &ln : sv->lanes) {
+            int rc = ensure_pools(ln->ws, ph, pbm, psb, sv->max_batch, (int64_t)sv->max_batch * 64,
+                                  ln->s);
+            if (rc == SABA_OK && hipStreamSynchronize(ln->s) != hipSuccess) {
+                set_error("zeroing the server's pools failed");
+                rc = SABA_E_HIP;
+            }
+            if (rc != SABA_OK) {
+                const std::string msg = saba_last_error();
+                shutdown(sv.get());
+                set_error(msg);
+                return rc;
+            }
+        }
+    }
     try {
         for (auto &ln : sv->lanes) ln->th = std::thread(&Server::lane_main, sv.get(), ln.get());
     } catch (...) {
@@ -467,7 +505,17 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
         set_error("invalid request (the server takes q >= 0 query pairs and an output)");
         return SABA_E_INVALID;
     }
+    const auto t_entry = Clock::now();
     const Graph *g = sv->g;
+    {
+        // refuse cheaply while the queue is full, before the pairs are validated
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->st.queued_edges > 0 && sv->st.queued_edges + rq->q > sv->max_queued_edges) {
+            sv->st.rejected += 1;
+            set_error("the admission queue is full");
+            return SABA_E_BUSY;
+        }
+    }
     SABA_TRY(check_request(g, rq->graph, rq->params, rq->q, rq->edges));
     if (rq->q > sv->arena_edges) {
         set_error("the request has more pairs than the server's result arena holds");
@@ -522,7 +570,7 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
     }
     r->ninst = (int64_t)r->insts.size();
     r->remaining = r->ninst;
-    r->t_submit = Clock::now();
+    r->t_submit = t_entry;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->stopping) {
