@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void batch_init_kernel(
     double *__restrict__ hA, int32_t *__restrict__ FA, uint32_t *__restrict__ bmA,
     int32_t *__restrict__ tau, double *__restrict__ D, long long *__restrict__ nreq,
     double *__restrict__ MC, unsigned long long *__restrict__ vis0,
-    unsigned long long *__restrict__ vis1, Flags *__restrict__ fl) {
+    unsigned long long *__restrict__ vis1, int2 *__restrict__ hubs0, Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (b >= nb) return;
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(kBlock) void batch_init_kernel(
         hA[sl.hoff + sl_local] = 1.0;
         FA[sl.hoff] = sl.v;
         bmA[sl.bmoff + (sl_local >> 5)] = 1u << (sl_local & 31);
+        if (r.y > kHubRow) hubs0[atomicAdd(&fl->nhub[0], 1)] = make_int2((int32_t)b, sl.v);
         atomicMax(&fl->max_tau, mx);
         if (capped) atomicOr(&fl->warnings, 1);
     }
@@ -167,8 +168,11 @@ __global__ __launch_bounds__(kBlock) void level_decide_kernel(
     int32_t *__restrict__ ttau_inst, Flags *__restrict__ fl) {
     const int lane = __lane_id();
     const int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (b >= nb || !bs[b].active) return;
     const int cur = level & 1, nxt = cur ^ 1;
+    // the hub-row list of level l + 1 is filled by this level's compaction (its previous
+    // contents, level l - 1's hub rows, were last used by the previous level's expansion)
+    if (blockIdx.x == 0 && threadIdx.x == 0) fl->nhub[nxt] = 0;
+    if (b >= nb || !bs[b].active) return;
     const Slot sl = slots[b];
     const PSet ps = psets[sl.p];
     const double *h = hcur_all + sl.hoff;  // indexed by graph-local vertex ids
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void level_decide_kernel(
 // its own row and the exclusive prefix of the row lengths over the wavefront.  Hub rows
 // count as empty when `skip_hubs` is set (they are handled separately).
 struct WaveRows {
-    int32_t x, start, len, pre, total;
+    int32_t x, start, deg, len, pre, total;  // len = deg, or 0 for a skipped hub row
 };
 
 __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
@@ -228,11 +232,13 @@ __device__ __forceinline__ WaveRows wave_rows(const int2 *__restrict__ vrec,
     WaveRows w;
     w.x = -1;
     w.start = 0;
+    w.deg = 0;
     w.len = 0;
     if (base + lane < fsz) {
         w.x = F[base + lane];
         const int2 r = vrec[w.x];
         w.start = r.x;
+        w.deg = r.y;
         w.len = (skip_hubs && r.y > kHubRow) ? 0 : r.y;
     }
     int32_t inc = w.len;
@@ -261,29 +267,125 @@ __device__ __forceinline__ int wave_owner(int32_t pre, int32_t j) {
     return lo;
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const int32_t lo = __builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(uint64_t)x);
+    const int32_t hi = __builtin_amdgcn_readfirstlane((int32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, int64_t len,
+                                               int64_t key) {
+    // largest i in [0, len) with a[i] <= key (a non-decreasing, a[0] <= key)
+    int64_t lo = 0, hi = len;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= key)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Frontier groups.  A level's frontier lists are cut into groups of 64 vertices per slot and
+// gofs[b] (b < nb) is the first group of slot b (inactive slots have none; gofs[nb] = total).
+// Wavefront w of the push kernels takes groups w, w + W, w + 2W, ... of the whole batch (W
+// wavefronts in the grid), so a slot with a huge frontier is spread over the whole grid and the
+// heavy first groups of the slots (frontiers are in ascending vertex order) land on different
+// wavefronts.  Hub rows are not part of the groups' work: they go to the hub-row lists.
+constexpr int kPushGrid = 2048;
+constexpr int kHubGrid = 1024;  // blocks of the hub-row kernels
+
+__global__ __launch_bounds__(1024) void group_scan_kernel(const BatchState *__restrict__ bs,
+                                                          int32_t nb, int parity,
+                                                          int64_t *__restrict__ gofs) {
+    __shared__ long long wtot[16];
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int32_t per = (nb + 1023) / 1024;
+    const int32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    auto groups = [&](int32_t b) -> long long {
+        return bs[b].active ? ((long long)bs[b].fsz[parity] + 63) / 64 : 0;
+    };
+    long long loc = 0;
+    for (int32_t b = b0; b < b1; ++b) loc += groups(b);
+    long long inc = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    long long run = inc - loc;
+    for (int k = 0; k < wave; ++k) run += wtot[k];
+    for (int32_t b = b0; b < b1; ++b) {
+        gofs[b] = run;
+        run += groups(b);
+    }
+    if (tid == 1023) gofs[nb] = run;
+}
+
+struct GroupCursor {  // the slot of the current group of a wavefront (all fields wave-uniform)
+    int64_t b = -1, gbase = 0, gnext = 0;
+};
+
+// Moves the cursor to the slot holding group gi (called when gi >= cursor.gnext).
+__device__ __forceinline__ void group_seek(GroupCursor &c, const int64_t *__restrict__ gofs,
+                                           int32_t nb, int64_t gi) {
+    c.b = uniform64(upper_index(gofs, nb + 1, gi));
+    c.gbase = uniform64(gofs[c.b]);
+    c.gnext = uniform64(gofs[c.b + 1]);
+}
+
+// First group, stride and total of this wavefront's groups (all wave-uniform).
+__device__ __forceinline__ void wave_groups(const int64_t *__restrict__ gofs, int32_t nb,
+                                            int64_t &first, int64_t &stride, int64_t &total) {
+    total = uniform64(gofs[nb]);
+    stride = (int64_t)gridDim.x * kWavesPerBlock;
+    first = uniform64((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+}
+
 // Push the current support one hop: set the bit of every neighbour in the next level's
 // support bitmap and, for neighbours with hub rows, the bit of the reverse CSR position in
 // the slot's CSR-position bitmap.  Fire-and-forget atomics; the next frontier list is built
-// from the bitmap afterwards, in ascending vertex order.
+// from the bitmap afterwards, in ascending vertex order.  Ordinary rows go by frontier groups
+// here; hub rows of the frontier are expanded by expand_hub_kernel.
+__device__ __forceinline__ void expand_entry(const int32_t *__restrict__ col,
+                                             const int32_t *__restrict__ slotv, const Slot &sl,
+                                             uint32_t *__restrict__ bm, uint32_t *__restrict__ sbm,
+                                             int32_t e) {
+    const int32_t x = col[e] - sl.goff;
+    atomicOr(bm + (x >> 5), 1u << (x & 31));
+    const int32_t slot = slotv[e];
+    if (slot >= 0) {
+        const int32_t ls = slot - sl.gpos;
+        atomicOr(sbm + (ls >> 5), 1u << (ls & 31));
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ slotv, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
-    int32_t level, const int32_t *__restrict__ Fcur_all, uint32_t *__restrict__ bmnext_all,
+    const int32_t *__restrict__ slotv, const Slot *__restrict__ slots,
+    const BatchState *__restrict__ bs, int32_t nb, int32_t level, const int64_t *__restrict__ gofs,
+    const int32_t *__restrict__ Fcur_all, uint32_t *__restrict__ bmnext_all,
     uint32_t *__restrict__ slotbm_all, Flags *__restrict__ fl) {
-    const int64_t b = blockIdx.y;
-    if (!bs[b].active) return;
     const int cur = level & 1;
-    const Slot sl = slots[b];
-    const int32_t *F = Fcur_all + sl.hoff;
-    uint32_t *bm = bmnext_all + sl.bmoff;
-    uint32_t *sbm = slotbm_all + sl.sboff;
-    const int32_t fsz = bs[b].fsz[cur];
     const int lane = __lane_id();
-    const int64_t wstride = (int64_t)gridDim.x * kBlock;
+    int64_t first, stride, total;
+    wave_groups(gofs, nb, first, stride, total);
+    GroupCursor gc;
+    Slot sl{};
+    int32_t fsz = 0;
     unsigned long long visits = 0;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
-         base += wstride) {
-        const WaveRows w = wave_rows(vrec, F, base, fsz, false);
+    for (int64_t gi = first; gi < total; gi += stride) {
+        if (gi >= gc.gnext) {
+            group_seek(gc, gofs, nb, gi);
+            sl = slots[gc.b];
+            fsz = bs[gc.b].fsz[cur];
+        }
+        const int32_t *F = Fcur_all + sl.hoff;
+        uint32_t *bm = bmnext_all + sl.bmoff;
+        uint32_t *sbm = slotbm_all + sl.sboff;
+        const WaveRows w = wave_rows(vrec, F, (gi - gc.gbase) * 64, fsz, true);
         if (lane == 0) visits += w.total;
         for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
             // cross-lane reads happen with every lane active; only memory accesses are masked
@@ -292,27 +394,45 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
             const int32_t jc = inr ? j : w.total - 1;
             const int o = wave_owner(w.pre, jc);
             const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
-            if (inr) {
-                const int32_t e = ost + (jc - opre);
-                const int32_t x = col[e] - sl.goff;
-                atomicOr(bm + (x >> 5), 1u << (x & 31));
-                const int32_t slot = slotv[e];
-                if (slot >= 0) {
-                    const int32_t ls = slot - sl.gpos;
-                    atomicOr(sbm + (ls >> 5), 1u << (ls & 31));
-                }
-            }
+            if (inr) expand_entry(col, slotv, sl, bm, sbm, ost + (jc - opre));
         }
     }
     visits = wave_sum_ll((long long)visits);
     if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
+// Hub rows of the current frontier (the list of this level's parity): one block per row.
+__global__ __launch_bounds__(kBlock) void expand_hub_kernel(
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ slotv, const Slot *__restrict__ slots,
+    const BatchState *__restrict__ bs, int32_t level, const int2 *__restrict__ hubs_all,
+    int64_t hubcap, uint32_t *__restrict__ bmnext_all, uint32_t *__restrict__ slotbm_all,
+    Flags *__restrict__ fl) {
+    const int cur = level & 1;
+    const int2 *hubs = hubs_all + cur * hubcap;
+    const int32_t nh = fl->nhub[cur];
+    unsigned long long visits = 0;
+    for (int32_t k = blockIdx.x; k < nh; k += gridDim.x) {
+        const int2 hb = hubs[k];
+        if (!bs[hb.x].active) continue;  // the list was made before this level's stop test
+        const Slot sl = slots[hb.x];
+        const int2 r = vrec[hb.y];
+        uint32_t *bm = bmnext_all + sl.bmoff;
+        uint32_t *sbm = slotbm_all + sl.sboff;
+        for (int32_t i = threadIdx.x; i < r.y; i += kBlock)
+            expand_entry(col, slotv, sl, bm, sbm, r.x + i);
+        if (threadIdx.x == 0) visits += (unsigned long long)r.y;
+    }
+    if (threadIdx.x == 0 && visits) atomicAdd(&fl->push_visits, visits);
+}
+
 // Next frontier list of each active instance: the set bits of its next-level support bitmap,
-// in ascending vertex order (one block per instance).
+// in ascending vertex order (one block per instance).  Its hub rows are also appended, in any
+// order, to the hub-row list of the next level's parity.
 __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
-    const Slot *__restrict__ slots, BatchState *__restrict__ bs, int32_t level,
-    const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all) {
+    const int2 *__restrict__ vrec, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
+    int32_t level, const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all,
+    int2 *__restrict__ hubs_all, int64_t hubcap, Flags *__restrict__ fl) {
     __shared__ uint32_t wave_tot[kWavesPerBlock];
     __shared__ int32_t carry;
     const int64_t b = blockIdx.x;
@@ -346,7 +466,10 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
         while (rest) {
             const int bit = __builtin_ctz(rest);
             rest &= rest - 1;
-            Fn[pos++] = sl.goff + (int32_t)(wi * 32 + bit);
+            const int32_t x = sl.goff + (int32_t)(wi * 32 + bit);
+            Fn[pos++] = x;
+            if (vrec[x].y > kHubRow)
+                hubs_all[nxt * hubcap + atomicAdd(&fl->nhub[nxt], 1)] = make_int2((int32_t)b, x);
         }
         __syncthreads();
         if (threadIdx.x == 0) carry += (int32_t)all;
@@ -355,42 +478,59 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
     if (threadIdx.x == 0) bs[b].fsz[nxt] = carry;
 }
 
-constexpr int kFoldWindow = 256;  // LDS values per wavefront in the hub-row fold
-
 // h_{l+1}(x) = (left fold over Gamma(x) in CSR order of h_l) / d(x) for x in the next support.
-// Only terms in the support of h_l are folded (the others are zero), in row order:
-//  - ordinary rows: the wavefront walks the concatenated rows of its 64 vertices and checks
-//    each neighbour in the current support bitmap;
-//  - hub rows: the set bits of the CSR-position bitmap over the row mark exactly the occupied
-//    positions; their values are staged in LDS in row order and folded by one lane.
-// Also accumulates the support volume and maximum of h_{l+1}, and clears the hub-row bits.
+// Only terms in the support of h_l are nonzero, and adding +0.0 leaves a sum of non-negative
+// numbers bit-identical, so both kernels below produce the sequential fold exactly.
+//  - pull_kernel, ordinary rows: the wavefront walks the concatenated rows of its 64 vertices,
+//    fetches one entry per lane (h_l where the support bitmap has the neighbour, else 0),
+//    stages the 64 values in LDS and each lane folds its own row's part in row order;
+//  - pull_hub_kernel, hub rows: the set bits of the CSR-position bitmap over the row mark
+//    exactly the in-support positions; they are listed in row order, their values staged in
+//    LDS and folded by one lane.  The row's bits are cleared on the way.
+// Both accumulate the support volume and maximum of h_{l+1} per slot.
 __global__ __launch_bounds__(kBlock) void pull_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
-    BatchState *__restrict__ bs, int32_t level, const double *__restrict__ hcur_all,
-    const uint32_t *__restrict__ bmcur_all, uint32_t *__restrict__ slotbm_all,
+    BatchState *__restrict__ bs, int32_t nb, int32_t level, const int64_t *__restrict__ gofs,
+    const double *__restrict__ hcur_all, const uint32_t *__restrict__ bmcur_all,
     double *__restrict__ hnext_all, const int32_t *__restrict__ Fnext_all,
     Flags *__restrict__ fl) {
-    __shared__ double stage[kWavesPerBlock][kFoldWindow];
-    const int64_t b = blockIdx.y;
-    if (!bs[b].active) return;
+    __shared__ double stage[kWavesPerBlock][64];
     const int nxt = (level & 1) ^ 1;
-    const Slot sl = slots[b];
-    const double *h = hcur_all + sl.hoff;  // indexed by graph-local vertex ids
-    const uint32_t *bm = bmcur_all + sl.bmoff;
-    uint32_t *sbm = slotbm_all + sl.sboff;
-    double *hn = hnext_all + sl.hoff;
-    const int32_t *F = Fnext_all + sl.hoff;
-    const int32_t fsz = bs[b].fsz[nxt];
     const int lane = __lane_id();
     double *lds = stage[threadIdx.x >> 6];
-    const int64_t wstride = (int64_t)gridDim.x * kBlock;
+    int64_t first, stride, total;
+    wave_groups(gofs, nb, first, stride, total);
+    GroupCursor gc;
+    Slot sl{};
+    int32_t fsz = 0;
     unsigned long long visits = 0, vol = 0;
     double hmax = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < fsz;
-         base += wstride) {
-        const WaveRows w = wave_rows(vrec, F, base, fsz, true);
+    // support volume and maximum of h_{l+1} are flushed to their slot when the wavefront
+    // moves on to another slot, and at the end
+    auto flush = [&]() {
+        const unsigned long long v = (unsigned long long)wave_sum_ll((long long)vol);
+        const double hm = wave_max_d(hmax);
+        if (lane == 0 && gc.b >= 0 && v) {
+            atomicAdd(&bs[gc.b].vol[nxt], v);
+            atomicMax(&bs[gc.b].hmaxbits[nxt], (unsigned long long)__double_as_longlong(hm));
+        }
+        vol = 0;
+        hmax = 0.0;
+    };
+    for (int64_t gi = first; gi < total; gi += stride) {
+        if (gi >= gc.gnext) {
+            flush();
+            group_seek(gc, gofs, nb, gi);
+            sl = slots[gc.b];
+            fsz = bs[gc.b].fsz[nxt];
+        }
+        const double *h = hcur_all + sl.hoff;  // indexed by graph-local vertex ids
+        const uint32_t *bm = bmcur_all + sl.bmoff;
+        double *hn = hnext_all + sl.hoff;
+        const int32_t *F = Fnext_all + sl.hoff;
+        const WaveRows w = wave_rows(vrec, F, (gi - gc.gbase) * 64, fsz, true);
         if (lane == 0) visits += w.total;
-        double acc = 0.0;  // the fold of this lane's own (ordinary) row
+        double acc = 0.0;  // the fold of this lane's own row
         for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
             const int32_t j = j0 + lane;
             const bool inr = j < w.total;
@@ -398,106 +538,128 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
             const int o = wave_owner(w.pre, jc);
             const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
             double v = 0.0;
-            bool nz = false;
             if (inr) {
                 const int32_t y = col[ost + (jc - opre)];
                 const int32_t yl = y - sl.goff;
-                if (bm[yl >> 5] & (1u << (yl & 31))) {
-                    v = h[yl];
-                    nz = true;
-                }
+                if (bm[yl >> 5] & (1u << (yl & 31))) v = h[yl];
             }
-            unsigned long long m = __ballot(nz);
-            while (m) {  // ascending lanes = ascending row positions
-                const int src = __builtin_ctzll(m);
-                m &= m - 1;
-                const double t = __shfl(v, src);
-                const int owner = __shfl(o, src);
-                if (lane == owner) acc += t;
-            }
+            lds[lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t k0 = max(w.pre, j0) - j0, k1 = min(w.pre + w.len, j0 + 64) - j0;
+            for (int32_t k = k0; k < k1; ++k) acc += lds[k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        // hub rows of this group, one at a time
-        const int2 rr = (w.x >= 0) ? vrec[w.x] : make_int2(0, 0);
-        unsigned long long hubs = __ballot(rr.y > kHubRow);
-        while (hubs) {
-            const int hl = __builtin_ctzll(hubs);
-            hubs &= hubs - 1;
-            const int32_t a = __shfl(rr.x, hl) - sl.gpos, d = __shfl(rr.y, hl);
-            const int32_t e1 = a + d;  // local row positions [a, e1)
-            const int64_t wfirst = a >> 5, wlast = (e1 - 1) >> 5;
-            double hacc = 0.0;
-            for (int64_t wc = wfirst; wc <= wlast; wc += 64) {
-                const int64_t wi = wc + lane;
-                uint32_t word = 0;
-                if (wi <= wlast) {
-                    word = sbm[wi];
-                    if (wi == wfirst) word &= ~0u << (a & 31);
-                    if (wi == wlast && (e1 & 31)) word &= (1u << (e1 & 31)) - 1u;
-                }
-                const int32_t cnt = __popc(word);
-                int32_t inc = cnt;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int32_t t = __shfl_up(inc, o);
-                    if (lane >= o) inc += t;
-                }
-                const int32_t T = __builtin_amdgcn_readfirstlane(__shfl(inc, 63));
-                const int32_t pos0 = inc - cnt;
-                for (int32_t r0 = 0; r0 < T; r0 += kFoldWindow) {
-                    uint32_t rest = word;
-                    int32_t p = pos0;
-                    while (rest) {
-                        const int bit = __builtin_ctz(rest);
-                        rest &= rest - 1;
-                        if (p >= r0 && p < r0 + kFoldWindow) {
-                            const int32_t y = col[sl.gpos + wi * 32 + bit];
-                            lds[p - r0] = h[y - sl.goff];
-                        }
-                        ++p;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (lane == 0) {
-                        const int32_t cntw = min(kFoldWindow, T - r0);
-                        for (int32_t i = 0; i < cntw; ++i) hacc += lds[i];
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-                // this row's bits are consumed: clear them (boundary words are shared)
-                if (wi <= wlast) {
-                    const bool edge = (wi == wfirst && (a & 31)) || (wi == wlast && (e1 & 31));
-                    if (edge) {
-                        uint32_t mask = ~0u;
-                        if (wi == wfirst) mask &= ~0u << (a & 31);
-                        if (wi == wlast && (e1 & 31)) mask &= (1u << (e1 & 31)) - 1u;
-                        atomicAnd(sbm + wi, ~mask);
-                    } else {
-                        sbm[wi] = 0u;
-                    }
-                }
-            }
-            hacc = __shfl(hacc, 0);
-            if (lane == hl) acc = hacc;
-        }
-        if (w.x >= 0) {
-            const double hv = acc / (double)rr.y;
+        if (w.x >= 0 && w.deg <= kHubRow) {
+            const double hv = acc / (double)w.deg;
             hn[w.x - sl.goff] = hv;
-            vol += (unsigned long long)rr.y;
+            vol += (unsigned long long)w.deg;
             hmax = fmax(hmax, hv);
         }
     }
+    flush();
     visits = wave_sum_ll((long long)visits);
-    vol = wave_sum_ll((long long)vol);
-    hmax = wave_max_d(hmax);
-    if (lane == 0) {
-        if (visits) atomicAdd(&fl->push_visits, visits);
-        if (vol) {
-            atomicAdd(&bs[b].vol[nxt], vol);
-            atomicMax(&bs[b].hmaxbits[nxt], (unsigned long long)__double_as_longlong(hmax));
+    if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
+}
+
+constexpr int kHubSpan = 2048;  // row positions per pass (64 bitmap words, one per lane)
+constexpr int kHubVals = 256;   // values staged per fold step
+
+__global__ __launch_bounds__(kBlock) void pull_hub_kernel(
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    BatchState *__restrict__ bs, int32_t level, const int2 *__restrict__ hubs_all,
+    int64_t hubcap, const double *__restrict__ hcur_all, uint32_t *__restrict__ slotbm_all,
+    double *__restrict__ hnext_all, Flags *__restrict__ fl) {
+    __shared__ int32_t spos[kWavesPerBlock][kHubSpan];
+    __shared__ double sval[kWavesPerBlock][kHubVals];
+    const int nxt = (level & 1) ^ 1;
+    const int lane = __lane_id();
+    int32_t *lpos = spos[threadIdx.x >> 6];
+    double *lval = sval[threadIdx.x >> 6];
+    const int2 *hubs = hubs_all + nxt * hubcap;
+    const int32_t nh = __builtin_amdgcn_readfirstlane(fl->nhub[nxt]);
+    const int32_t nwaves = (int32_t)gridDim.x * kWavesPerBlock;
+    unsigned long long visits = 0;
+    for (int32_t k = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * kWavesPerBlock +
+                                                              (threadIdx.x >> 6)));
+         k < nh; k += nwaves) {
+        const int2 hb = hubs[k];
+        const Slot sl = slots[hb.x];
+        const double *h = hcur_all + sl.hoff;
+        uint32_t *sbm = slotbm_all + sl.sboff;
+        const int2 r = vrec[hb.y];
+        const int32_t a = r.x - sl.gpos, e1 = a + r.y;  // local row positions [a, e1)
+        const int64_t wfirst = a >> 5, wlast = (e1 - 1) >> 5;
+        double hacc = 0.0;  // lane 0's fold of the row
+        for (int64_t wc = wfirst; wc <= wlast; wc += 64) {
+            const int64_t wi = wc + lane;
+            uint32_t word = 0;
+            if (wi <= wlast) {
+                word = sbm[wi];
+                if (wi == wfirst) word &= ~0u << (a & 31);
+                if (wi == wlast && (e1 & 31)) word &= (1u << (e1 & 31)) - 1u;
+            }
+            const int32_t cnt = __popc(word);
+            int32_t inc = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            const int32_t T = __builtin_amdgcn_readfirstlane(__shfl(inc, 63));
+            // in-support positions of this pass, in row order
+            {
+                uint32_t rest = word;
+                int32_t p = inc - cnt;
+                while (rest) {
+                    const int bit = __builtin_ctz(rest);
+                    rest &= rest - 1;
+                    lpos[p++] = (int32_t)(wi * 32 + bit);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int32_t r0 = 0; r0 < T; r0 += kHubVals) {
+                for (int32_t q = 0; q < kHubVals; q += 64) {
+                    const int32_t i = r0 + q + lane;
+                    if (i < T) lval[q + lane] = h[col[sl.gpos + lpos[i]] - sl.goff];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane == 0) {
+                    const int32_t n = min(kHubVals, T - r0);
+                    for (int32_t i = 0; i < n; ++i) hacc += lval[i];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // this row's bits are consumed: clear them (boundary words are shared)
+            if (wi <= wlast) {
+                const bool edge = (wi == wfirst && (a & 31)) || (wi == wlast && (e1 & 31));
+                if (edge) {
+                    uint32_t mask = ~0u;
+                    if (wi == wfirst) mask &= ~0u << (a & 31);
+                    if (wi == wlast && (e1 & 31)) mask &= (1u << (e1 & 31)) - 1u;
+                    atomicAnd(sbm + wi, ~mask);
+                } else {
+                    sbm[wi] = 0u;
+                }
+            }
+            if (lane == 0) visits += (unsigned long long)T;
+        }
+        if (lane == 0) {
+            const double hv = hacc / (double)r.y;
+            hnext_all[sl.hoff + (hb.y - sl.goff)] = hv;
+            atomicAdd(&bs[hb.x].vol[nxt], (unsigned long long)r.y);
+            atomicMax(&bs[hb.x].hmaxbits[nxt], (unsigned long long)__double_as_longlong(hv));
         }
     }
+    if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
 // After a level: zero h_l and its support bitmap over the support, so both are clean when the
@@ -565,20 +727,6 @@ __global__ __launch_bounds__(kBlock) void nreq_kernel(
     }
 }
 
-__device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, int64_t len,
-                                               int64_t key) {
-    // largest i in [0, len) with a[i] <= key (a non-decreasing, a[0] <= key)
-    int64_t lo = 0, hi = len;
-    while (hi - lo > 1) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] <= key)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // The walk pairs (Alg. 1 inner loop).  Chunk c of local edge le holds walks
 // j = 64 (c - coff[le]) + lane; j < n walk from s (side 0, index j), n <= j < 2n walk from t
 // (side 1, index j - n).  Each walk sums h_ttau over its positions 1..L.  The persistent grid
@@ -643,25 +791,58 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     }
 }
 
-// Per instance edge: MC = its chunk sums in chunk order; g(s,t) = (D + MC / n) / d_s.
-__global__ void edge_reduce_kernel(const int2 *__restrict__ vrec, const Slot *__restrict__ slots,
-                                   int32_t nb, const int64_t *__restrict__ eb, int64_t ie0,
-                                   const int64_t *__restrict__ coff, int64_t nle,
-                                   const uint8_t *__restrict__ want,
-                                   const long long *__restrict__ nreq,
-                                   const double *__restrict__ D, const double *__restrict__ partial,
-                                   double *__restrict__ MC, double *__restrict__ g) {
-    for (int64_t le = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; le < nle;
-         le += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ie = ie0 + le;
-        if (!want[ie]) continue;
-        const int64_t b = upper_index(eb, nb + 1, le);
-        const int32_t ds = vrec[slots[b].v].y;
-        double mc = 0.0;
-        for (int64_t c = coff[le]; c < coff[le + 1]; ++c) mc += partial[c];
-        const long long nr = nreq[ie];
-        MC[ie] = mc;
-        g[ie] = nr > 0 ? (D[ie] + mc / (double)nr) / (double)ds : D[ie] / (double)ds;
+// Per instance edge: MC = the sum of its chunk sums; g(s,t) = (D + MC / n) / d_s.  The order of
+// that sum depends only on the edge's chunk count: up to kSerialChunks chunks are added left to
+// right by one lane; more are split over the 64 lanes of a wavefront (lane l adds chunks
+// l, l + 64, ... left to right) and the lane sums are combined in the butterfly order of lane 0.
+// Neither depends on where the edge sits in its batch.
+constexpr int64_t kSerialChunks = 64;
+
+__device__ __forceinline__ void edge_finish(const int2 *__restrict__ vrec,
+                                            const Slot *__restrict__ slots, int32_t nb,
+                                            const int64_t *__restrict__ eb, int64_t le,
+                                            int64_t ie, const long long *__restrict__ nreq,
+                                            const double *__restrict__ D, double mc,
+                                            double *__restrict__ MC, double *__restrict__ g) {
+    const int64_t b = upper_index(eb, nb + 1, le);
+    const int32_t ds = vrec[slots[b].v].y;
+    const long long nr = nreq[ie];
+    MC[ie] = mc;
+    g[ie] = nr > 0 ? (D[ie] + mc / (double)nr) / (double)ds : D[ie] / (double)ds;
+}
+
+__global__ __launch_bounds__(kBlock) void edge_reduce_kernel(
+    const int2 *__restrict__ vrec, const Slot *__restrict__ slots, int32_t nb,
+    const int64_t *__restrict__ eb, int64_t ie0, const int64_t *__restrict__ coff, int64_t nle,
+    const uint8_t *__restrict__ want, const long long *__restrict__ nreq,
+    const double *__restrict__ D, const double *__restrict__ partial, double *__restrict__ MC,
+    double *__restrict__ g) {
+    const int lane = __lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    // each wavefront owns 64 consecutive edges per round; the round count is wave-uniform
+    for (int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * 64;
+         base < nle; base += nwaves * 64) {
+        const int64_t le = base + lane;
+        const bool mine = le < nle && want[ie0 + le];
+        const int64_t c0 = mine ? coff[le] : 0, c1 = mine ? coff[le + 1] : 0;
+        const bool big = mine && (c1 - c0) > kSerialChunks;
+        if (mine && !big) {
+            double mc = 0.0;
+            for (int64_t c = c0; c < c1; ++c) mc += partial[c];
+            edge_finish(vrec, slots, nb, eb, le, ie0 + le, nreq, D, mc, MC, g);
+        }
+        unsigned long long bigs = __ballot(big);
+        while (bigs) {  // wave-uniform: the ballot is the same in every lane
+            const int src = __builtin_ctzll(bigs);
+            bigs &= bigs - 1;
+            const int64_t b0 = __shfl(c0, src), b1 = __shfl(c1, src);
+            double part = 0.0;
+            for (int64_t c = b0 + lane; c < b1; c += 64) part += partial[c];
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+            // lanes may round the butterfly differently: lane 0's order is the defined one
+            const double tot = __shfl(part, 0);
+            if (lane == src) edge_finish(vrec, slots, nb, eb, le, ie0 + le, nreq, D, tot, MC, g);
+        }
     }
 }
 
@@ -755,7 +936,8 @@ SlotSize slot_size(const Graph *g, int32_t graph) {
     z.h = gn;
     z.bm = (gn + 31) / 32;
     z.sb = (gnnz + 31) / 32;
-    z.bytes = gn * (2 * 8 + 2 * 4) + 2 * 4 * z.bm + 4 * z.sb;
+    z.hubs = g->ghubs[graph];
+    z.bytes = gn * (2 * 8 + 2 * 4) + 2 * 4 * z.bm + 4 * z.sb + 2 * 8 * z.hubs;
     return z;
 }
 
@@ -787,8 +969,8 @@ int ensure_edge_arrays(Workspace &ws, int64_t ne, int64_t ninst, int32_t np, Edg
     return SABA_OK;
 }
 
-int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, int64_t ne,
-                 hipStream_t s) {
+int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs, int64_t nb,
+                 int64_t ne, hipStream_t s) {
     auto &E = ws.b;
     h = std::max<int64_t>(h, 1);
     bm = std::max<int64_t>(bm, 1);
@@ -809,6 +991,8 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, i
     SABA_TRY(E[B_SLOT].ensure(sizeof(Slot) * nb));
     SABA_TRY(E[B_EB].ensure(sizeof(int64_t) * (nb + 1)));
     SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * nb));
+    SABA_TRY(E[B_GOFS].ensure(sizeof(int64_t) * 2 * (nb + 1)));
+    SABA_TRY(E[B_HUBS].ensure(sizeof(int2) * 2 * std::max<int64_t>(hubs, 1)));
     SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * ne));
     SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (ne + 1)));
     SABA_TRY(E[B_SCAN].ensure(scan_tmp_bytes(ne)));
@@ -826,7 +1010,7 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, i
 
 int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
               const std::vector<int64_t> &heb, int64_t ie0, int64_t nle, int64_t maxgn,
-              BatchTiming *tm, hipStream_t s) {
+              int64_t hubcap, BatchTiming *tm, hipStream_t s) {
     auto &E = ws.b;
     const int32_t nb = (int32_t)hslots.size();
     if (nb == 0) return SABA_OK;
@@ -843,6 +1027,9 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     BatchState *bs = E[B_BSTATE].as<BatchState>();
     long long *chunks = E[B_CHUNKS].as<long long>();
     int64_t *coff = E[B_COFF].as<int64_t>();
+    int64_t *gofs_cur = E[B_GOFS].as<int64_t>(), *gofs_nxt = gofs_cur + (nb + 1);
+    int2 *hubs = E[B_HUBS].as<int2>();
+    hubcap = std::max<int64_t>(hubcap, 1);
     Flags *fl = ea.fl;
     ws.clean = false;  // until the batch has cleared everything it touched
 
@@ -850,9 +1037,10 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
                                 s));
     SABA_HIP_TRY(hipMemcpyAsync(d_eb, heb.data(), sizeof(int64_t) * (nb + 1),
                                 hipMemcpyHostToDevice, s));
+    SABA_HIP_TRY(hipMemsetAsync(&fl->nhub[0], 0, 2 * sizeof(int32_t), s));
     batch_init_kernel<<<grid_for(nb, kWavesPerBlock), kBlock, 0, s>>>(
         g->vrec, g->col_idx, d_slots, ea.psets, nb, bs, hA, FA, bmA, ea.tau, ea.D, ea.nreq, ea.MC,
-        ea.vis0, ea.vis1, fl);
+        ea.vis0, ea.vis1, hubs, fl);
     SABA_HIP_TRY(hipGetLastError());
     const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, maxgn / 4096));
     const dim3 grid(ysplit, (unsigned)nb);
@@ -871,11 +1059,18 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
             hipMemcpyAsync(&any, &fl->any_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         SABA_HIP_TRY(hipStreamSynchronize(s));
         if (!any) break;
-        expand_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, level,
-                                              Fcur, bmnext, slotbm, fl);
-        compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(d_slots, bs, level, bmnext, Fnext);
-        pull_kernel<<<grid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hcur, bmcur,
-                                            slotbm, hnext, Fnext, fl);
+        group_scan_kernel<<<1, 1024, 0, s>>>(bs, nb, cur, gofs_cur);
+        expand_kernel<<<kPushGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, nb,
+                                                   level, gofs_cur, Fcur, bmnext, slotbm, fl);
+        expand_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs,
+                                                      level, hubs, hubcap, bmnext, slotbm, fl);
+        compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(g->vrec, d_slots, bs, level,
+                                                                bmnext, Fnext, hubs, hubcap, fl);
+        group_scan_kernel<<<1, 1024, 0, s>>>(bs, nb, cur ^ 1, gofs_nxt);
+        pull_kernel<<<kPushGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, nb, level,
+                                                 gofs_nxt, hcur, bmcur, hnext, Fnext, fl);
+        pull_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hubs,
+                                                    hubcap, hcur, slotbm, hnext, fl);
         clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, cur, true, hA, hB, bmA, bmB, FA,
                                                    FB);
         SABA_HIP_TRY(hipGetLastError());
@@ -911,7 +1106,7 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
             tm->walk_ms += ms;
         }
     }
-    edge_reduce_kernel<<<grid_for(nle, 256, 1 << 16), 256, 0, s>>>(
+    edge_reduce_kernel<<<grid_for(nle, kBlock, 1 << 16), kBlock, 0, s>>>(
         g->vrec, d_slots, nb, d_eb, ie0, coff, nle, ea.want, ea.nreq, ea.D, partial, ea.MC, ea.g);
     // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
     clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, -1, false, hA, hB, bmA, bmB, FA, FB);
@@ -1096,12 +1291,12 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     std::vector<SlotSize> ssz(P);
     for (int32_t k = 0; k < P; ++k) ssz[k] = slot_size(g, pgraph[k]);
     struct Batch {
-        int64_t i0, i1, h, bm, sb, ne;
+        int64_t i0, i1, h, bm, sb, hubs, ne;
     };
     std::vector<Batch> batches;
-    int64_t maxh = 0, maxbm = 0, maxsb = 0, maxne = 0, maxnb = 0;
+    int64_t maxh = 0, maxbm = 0, maxsb = 0, maxhubs = 0, maxne = 0, maxnb = 0;
     for (int64_t i = 0; i < ns;) {
-        Batch bt{i, i, 0, 0, 0, 0};
+        Batch bt{i, i, 0, 0, 0, 0, 0};
         int64_t bytes = 0;
         while (bt.i1 < ns) {
             const SlotSize &z = ssz[inst_p[bt.i1]];
@@ -1112,18 +1307,20 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             bt.h += z.h;
             bt.bm += z.bm;
             bt.sb += z.sb;
+            bt.hubs += z.hubs;
             ++bt.i1;
         }
         bt.ne = iebase[bt.i1] - iebase[bt.i0];
         maxh = std::max(maxh, bt.h);
         maxbm = std::max(maxbm, bt.bm);
         maxsb = std::max(maxsb, bt.sb);
+        maxhubs = std::max(maxhubs, bt.hubs);
         maxne = std::max(maxne, bt.ne);
         maxnb = std::max(maxnb, bt.i1 - bt.i0);
         batches.push_back(bt);
         i = bt.i1;
     }
-    SABA_TRY(ensure_pools(ws, maxh, maxbm, maxsb, maxnb, maxne, s));
+    SABA_TRY(ensure_pools(ws, maxh, maxbm, maxsb, maxhubs, maxnb, maxne, s));
 
     std::vector<Slot> hslots;
     std::vector<int64_t> heb;
@@ -1155,7 +1352,7 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             heb[b] = iebase[i] - ie0;
         }
         heb[nb] = bt.ne;
-        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, &tm, s));
+        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, bt.hubs, &tm, s));
     }
 
     // results of every request

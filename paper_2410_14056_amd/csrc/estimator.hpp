@@ -19,7 +19,7 @@ namespace saba {
 enum {
     B_PSET, B_SLOT, B_EB, B_BSTATE, B_WANT, B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G,
     B_TTAU, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_CHUNKS, B_COFF, B_PART, B_SCAN,
-    B_FLAGS, B_PAIRS, B_MAP, B_COUNT
+    B_FLAGS, B_PAIRS, B_MAP, B_GOFS, B_HUBS, B_COUNT
 };
 static_assert(B_COUNT <= 32, "Workspace holds 32 buffers");
 
@@ -48,6 +48,7 @@ struct Slot {  // one instance of a batch
 struct Flags {
     int32_t err;
     int32_t any_active;
+    int32_t nhub[2];  // entries of the hub-row lists of the two level parities
     int32_t max_tau;
     int32_t max_ttau;
     int32_t warnings;
@@ -72,9 +73,10 @@ struct EdgeArrays {
 };
 
 // Dense scratch of one slot of a graph: two FP64 levels and two frontier lists of gn entries,
-// two vertex bitmaps and one bitmap over the graph's CSR positions.
+// two vertex bitmaps, one bitmap over the graph's CSR positions, and room for the graph's hub
+// rows in the two hub-row lists.
 struct SlotSize {
-    int64_t h, bm, sb, bytes;
+    int64_t h, bm, sb, hubs, bytes;
 };
 
 struct BatchTiming {
@@ -94,10 +96,10 @@ SlotSize slot_size(const Graph *g, int32_t graph);
 
 // Instance-edge arrays for ne instance edges, ninst instances and np parameter sets.
 int ensure_edge_arrays(Workspace &ws, int64_t ne, int64_t ninst, int32_t np, EdgeArrays *out);
-// Pools for batches of up to nb slots holding h / bm / sb pool entries and ne instance edges.
-// Newly allocated pools are zeroed on stream s.
-int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, int64_t ne,
-                 hipStream_t s);
+// Pools for batches of up to nb slots holding h / bm / sb / hubs pool entries and ne instance
+// edges.  Newly allocated pools are zeroed on stream s.
+int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs, int64_t nb,
+                 int64_t ne, hipStream_t s);
 // Runs one batch on stream s.  hslots carry pool offsets (laid out by the caller within the
 // sizes given to ensure_pools) and instance edges ie relative to the arrays; eb[b] is the first
 // instance edge of slot b relative to ie0 (eb[nb] = nle).  Leaves every pool entry it touched
@@ -105,6 +107,6 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t nb, i
 // reached the end of the batch.
 int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
               const std::vector<int64_t> &eb, int64_t ie0, int64_t nle, int64_t maxgn,
-              BatchTiming *tm, hipStream_t s);
+              int64_t hubs, BatchTiming *tm, hipStream_t s);
 
 }  // namespace saba

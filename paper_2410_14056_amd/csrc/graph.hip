@@ -239,6 +239,9 @@ static void graph_properties(Graph *g) {
     }
     g->connected = (g->ngraphs == 1 && n > 0) ? g->gconnected[0] : 0;
     g->bipartite = (g->ngraphs == 1 && n > 0) ? g->gbipartite[0] : 0;
+    g->ghubs.assign(g->ngraphs, 0);
+    for (int32_t k = 0; k < g->ngraphs; ++k)
+        for (int32_t v = g->goff[k]; v < g->goff[k + 1]; ++v) g->ghubs[k] += rp[v + 1] - rp[v] > kHubRow;
 }
 
 static void destroy_graph(Graph *g) {

@@ -71,6 +71,7 @@ struct Graph {
     std::vector<int32_t> goff;
     std::vector<int64_t> cbase;
     std::vector<int8_t> gconnected, gbipartite;
+    std::vector<int64_t> ghubs;  // vertices of each graph whose rows are hub rows
     std::vector<int32_t> h_row_ptr, h_col_idx;
     int32_t *row_ptr = nullptr;
     int32_t *col_idx = nullptr;

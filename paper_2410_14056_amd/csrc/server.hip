@@ -188,7 +188,7 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
     std::vector<Slot> slots(nb);
     std::vector<int64_t> eb(nb + 1);
     std::vector<int64_t> map;
-    int64_t ne = 0, ho = 0, bo = 0, so = 0, maxgn = 1;
+    int64_t ne = 0, ho = 0, bo = 0, so = 0, hubs = 0, maxgn = 1;
     for (int32_t b = 0; b < nb; ++b) {
         const Inst &x = batch[b];
         const Req &r = *x.req;
@@ -215,6 +215,7 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
         ho += r.sz.h;
         bo += r.sz.bm;
         so += r.sz.sb;
+        hubs += r.sz.hubs;
         maxgn = std::max<int64_t>(maxgn, sl.gn);
         eb[b] = ne;
         for (size_t k = 0; k < x.want.size(); k += 2) {
@@ -239,8 +240,8 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
         SABA_HIP_TRY(hipMemcpyAsync(ln.map.ptr, map.data(), sizeof(int64_t) * map.size(),
                                     hipMemcpyHostToDevice, s));
     SABA_HIP_TRY(hipMemsetAsync(ea.fl, 0, sizeof(Flags), s));
-    SABA_TRY(ensure_pools(ln.ws, ho, bo, so, nb, ne, s));
-    SABA_TRY(run_batch(g, ln.ws, ea, slots, eb, 0, ne, maxgn, nullptr, s));
+    SABA_TRY(ensure_pools(ln.ws, ho, bo, so, hubs, nb, ne, s));
+    SABA_TRY(run_batch(g, ln.ws, ea, slots, eb, 0, ne, maxgn, hubs, nullptr, s));
     if (nmap > 0) {
         scatter_kernel<<<grid_for(nmap, 256, 1 << 14), 256, 0, s>>>(
             ln.map.as<int64_t>(), nmap, ea.g, arena_buf.as<double>());
@@ -453,17 +454,19 @@ extern "C" int saba_server_create(saba_graph *gh, const saba_server_options *opt
     // count over any batch is bounded by the budget times the best entries-per-byte ratio of a
     // graph, plus one slot, and by max_batch slots of the largest graph.
     {
-        double rh = 0.0, rbm = 0.0, rsb = 0.0;
-        int64_t mh = 0, mbm = 0, msb = 0;
+        double rh = 0.0, rbm = 0.0, rsb = 0.0, rhub = 0.0;
+        int64_t mh = 0, mbm = 0, msb = 0, mhub = 0;
         for (int32_t k = 0; k < g->ngraphs; ++k) {
             const SlotSize z = slot_size(g, k);
             if (z.bytes <= 0) continue;
             rh = std::max(rh, (double)z.h / (double)z.bytes);
             rbm = std::max(rbm, (double)z.bm / (double)z.bytes);
             rsb = std::max(rsb, (double)z.sb / (double)z.bytes);
+            rhub = std::max(rhub, (double)z.hubs / (double)z.bytes);
             mh = std::max(mh, z.h);
             mbm = std::max(mbm, z.bm);
             msb = std::max(msb, z.sb);
+            mhub = std::max(mhub, z.hubs);
         }
         auto cap = [&](double ratio, int64_t mx) {
             const double by_budget = ratio * (double)sv->lane_budget + (double)mx;
@@ -471,9 +474,10 @@ extern "C" int saba_server_create(saba_graph *gh, const saba_server_options *opt
             return (int64_t)std::min(by_budget, by_count);
         };
         const int64_t ph = cap(rh, mh), pbm = cap(rbm, mbm), psb = cap(rsb, msb);
+        const int64_t phub = cap(rhub, mhub);
         for (auto &ln : sv->lanes) {
-            int rc = ensure_pools(ln->ws, ph, pbm, psb, sv->max_batch, (int64_t)sv->max_batch * 64,
-                                  ln->s);
+            int rc = ensure_pools(ln->ws, ph, pbm, psb, phub, sv->max_batch,
+                                  (int64_t)sv->max_batch * 64, ln->s);
             if (rc == SABA_OK && hipStreamSynchronize(ln->s) != hipSuccess) {
                 set_error("zeroing the server's pools failed");
                 rc = SABA_E_HIP;
