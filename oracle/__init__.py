@@ -51,8 +51,12 @@ def lib():
         L.orc_walk_key.restype = None
         L.orc_walk_path.argtypes = [P, P, i32, i32, u32, u32, P]
         L.orc_walk_path.restype = i32
-        L.orc_walks_histogram.argtypes = [P, P, i32, P, i64, i32, u32, u32, u32, P, P, i32]
+        L.orc_walks_histogram.argtypes = [P, P, i32, P, i64, i32, u32, u32, u32, i32, P, P, i32]
         L.orc_walks_histogram.restype = i32
+        L.orc_distinct8.argtypes = [P, P, i32, P, i64, i32, u32, u32, u32, i32, i32, P]
+        L.orc_distinct8.restype = i32
+        L.orc_xorshift32.argtypes = [u32]
+        L.orc_xorshift32.restype = u32
         L.orc_aesc.argtypes = [P, P, i32, f64, f64, f64, u32, u32, u32, i32, i32, i32, P, i64, P,
                                P, P, P, P, P, P, P, P, i32]
         L.orc_aesc.restype = i32
@@ -108,16 +112,36 @@ def walk_path(g, start, L, key_hi, key_lo):
     return path
 
 
-def walks_histogram(g, sources, L, seed, G=1, S=0, nthreads=0):
+SAMPLER_KEYED, SAMPLER_KEYED_MOD, SAMPLER_STREAM_MOD, SAMPLER_LITERAL = 0, 1, 2, 3
+
+
+def walks_histogram(g, sources, L, seed, G=1, S=0, nthreads=0, sampler=SAMPLER_KEYED):
     """Endpoint and visit histograms (int64[n] each) of the walks started at `sources`."""
     src = np.ascontiguousarray(sources, dtype=np.int32)
     ep = np.zeros(g.n, dtype=np.int64)
     vi = np.zeros(g.n, dtype=np.int64)
     rc = lib().orc_walks_histogram(_p(g.row_ptr), _p(g.col_idx), g.n, _p(src), int(src.size),
-                                   int(L), seed, G, S, _p(ep), _p(vi), int(nthreads))
+                                   int(L), seed, G, S, int(sampler), _p(ep), _p(vi),
+                                   int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_walks_histogram failed ({rc})")
     return ep, vi
+
+
+def distinct8(g, sources, L, seed, G=1, S=0, sampler=SAMPLER_KEYED, order=1):
+    """Branching statistics: hist[k] = (8-walk vector, position) pairs with k distinct
+    vertices; order 0 = the given order, 1 = by start vertex then rank (bouquet order)."""
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    hist = np.zeros(9, dtype=np.int64)
+    rc = lib().orc_distinct8(_p(g.row_ptr), _p(g.col_idx), g.n, _p(src), int(src.size), int(L),
+                             seed, G, S, int(sampler), int(order), _p(hist))
+    if rc != 0:
+        raise ValueError(f"orc_distinct8 failed ({rc})")
+    return hist
+
+
+def xorshift32(x):
+    return int(lib().orc_xorshift32(x & 0xFFFFFFFF))
 
 
 def cconst(eps, delta, m):

@@ -131,6 +131,59 @@ static int32_t orc_step(const int32_t *row_ptr, const int32_t *col_idx, int32_t 
     return col_idx[row_ptr[cur] + (int32_t)k];
 }
 
+/* ------------------------------------------------------------------ */
+/* Samplers of the walk benchmark, the neighbour-choice functions the paper compares
+ * (Sec. 3.3 and the Table 4, 5 and 7 experiments).  The estimator uses sampler 0 only.
+ *   0  keyed Eq. (5): u = Murmur2(cur|l, key_hi) XOR key_lo, k = floor(u d / 2^32);
+ *   1  keyed Eq. (4): the same u, k = u mod d (the modulo the paper removes);
+ *   2  Eq. (3): rand() mod d with a sequential generator per walk, here Marsaglia's
+ *      xorshift32 (shifts 13, 17, 5; Marsaglia 2003), seeded with key_hi XOR key_lo
+ *      (0x9E3779B9 if that is zero) and advanced once before every step;
+ *   3  Eq. (5) read literally: u = X_W XOR Murmur2(cur|l, 0) with the unkeyed hash and the
+ *      walk's seed X_W = key_hi XOR key_lo fixed for the whole walk, k = floor(u d / 2^32).
+ *      Every step then reads the same top bits of X_W, so a walk is decided by a few bits
+ *      of its seed; kept as the negative ablation. */
+uint32_t orc_xorshift32(uint32_t x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
+
+typedef struct {
+    uint32_t key_hi, key_lo, x;
+} orc_walker;
+
+static void orc_walker_init(int32_t sampler, uint32_t key_hi, uint32_t key_lo, orc_walker *w)
+{
+    w->key_hi = key_hi;
+    w->key_lo = key_lo;
+    w->x = key_hi ^ key_lo;
+    if (sampler == 2 && w->x == 0) w->x = 0x9E3779B9u;
+}
+
+static int32_t orc_step_sampler(const int32_t *row_ptr, const int32_t *col_idx, int32_t cur,
+                                uint32_t l, int32_t sampler, orc_walker *w)
+{
+    uint32_t d = (uint32_t)(row_ptr[cur + 1] - row_ptr[cur]);
+    uint32_t words[2];
+    uint32_t k;
+    words[0] = (uint32_t)cur;
+    words[1] = l;
+    if (sampler == 1) {
+        k = (orc_hash_words(words, 2, w->key_hi) ^ w->key_lo) % d;
+    } else if (sampler == 2) {
+        w->x = orc_xorshift32(w->x);
+        k = w->x % d;
+    } else if (sampler == 3) {
+        k = orc_choice((w->key_hi ^ w->key_lo) ^ orc_hash_words(words, 2, 0u), d);
+    } else {
+        return orc_step(row_ptr, col_idx, cur, l, w->key_hi, w->key_lo);
+    }
+    return col_idx[row_ptr[cur] + (int32_t)k];
+}
+
 /* Alg. 2: the whole path of one walk, positions 0..L (path has L+1 slots). */
 int32_t orc_walk_path(const int32_t *row_ptr, const int32_t *col_idx, int32_t start,
                       int32_t L, uint32_t key_hi, uint32_t key_lo, int32_t *path)
@@ -153,9 +206,10 @@ int32_t orc_walk_path(const int32_t *row_ptr, const int32_t *col_idx, int32_t st
  * (s, 0, 0) and index r. */
 int32_t orc_walks_histogram(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
                             const int32_t *sources, int64_t n_walks, int32_t L,
-                            uint32_t seed, uint32_t G, uint32_t S,
+                            uint32_t seed, uint32_t G, uint32_t S, int32_t sampler,
                             int64_t *endpoint, int64_t *visits, int32_t nthreads)
 {
+    if (sampler < 0 || sampler > 3) return -3;
     int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_walks > 0 ? n_walks : 1));
     int64_t *seen = (int64_t *)calloc((size_t)n, sizeof(int64_t));
     if (!rank || !seen) {
@@ -180,10 +234,12 @@ int32_t orc_walks_histogram(const int32_t *row_ptr, const int32_t *col_idx, int3
 #endif
     for (int64_t j = 0; j < n_walks; ++j) {
         uint32_t khi, klo;
+        orc_walker w;
         orc_walk_key(seed, (uint32_t)sources[j], 0u, 0u, (uint64_t)rank[j], G, S, &khi, &klo);
+        orc_walker_init(sampler, khi, klo, &w);
         int32_t cur = sources[j];
         for (int32_t l = 1; l <= L; ++l) {
-            cur = orc_step(row_ptr, col_idx, cur, (uint32_t)l, khi, klo);
+            cur = orc_step_sampler(row_ptr, col_idx, cur, (uint32_t)l, sampler, &w);
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
@@ -197,6 +253,82 @@ int32_t orc_walks_histogram(const int32_t *row_ptr, const int32_t *col_idx, int3
     free(rank);
     free(seen);
     return 0;
+}
+
+/* Branching statistics (the Table 5 experiment): the walks are taken in an order, cut
+ * into consecutive vectors of 8 walks (a last, partial vector is left out), and for
+ * every vector and every position l = 1..L the number of distinct vertices among its
+ * 8 walks is counted: hist[k] = number of (vector, position) pairs with k distinct
+ * vertices (k = 1..8; hist[0] stays 0).  order 0: the order the sources are given;
+ * order 1: by start vertex, then by rank (the bouquet order). */
+static const int32_t *orc_sort_src;
+static const int64_t *orc_sort_rank;
+static int orc_cmp_bouquet(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    if (orc_sort_src[x] != orc_sort_src[y]) return orc_sort_src[x] < orc_sort_src[y] ? -1 : 1;
+    if (orc_sort_rank[x] != orc_sort_rank[y]) return orc_sort_rank[x] < orc_sort_rank[y] ? -1 : 1;
+    return 0;
+}
+
+int32_t orc_distinct8(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                      const int32_t *sources, int64_t n_walks, int32_t L, uint32_t seed,
+                      uint32_t G, uint32_t S, int32_t sampler, int32_t order, int64_t *hist)
+{
+    int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_walks > 0 ? n_walks : 1));
+    int64_t *seen = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_walks > 0 ? n_walks : 1));
+    int32_t *path = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_walks > 0 ? n_walks : 1) *
+                                      (size_t)(L + 1));
+    int32_t rc = 0;
+    memset(hist, 0, sizeof(int64_t) * 9);
+    if (!rank || !seen || !ord || !path || sampler < 0 || sampler > 3) {
+        rc = -2;
+        goto done;
+    }
+    for (int64_t j = 0; j < n_walks; ++j) {
+        int32_t s = sources[j];
+        if (s < 0 || s >= n || row_ptr[s + 1] == row_ptr[s]) {
+            rc = -1;
+            goto done;
+        }
+        rank[j] = seen[s]++;
+        ord[j] = j;
+    }
+    if (order == 1) {
+        orc_sort_src = sources;
+        orc_sort_rank = rank;
+        qsort(ord, (size_t)n_walks, sizeof(int64_t), orc_cmp_bouquet);
+    }
+    for (int64_t j = 0; j < n_walks; ++j) {
+        uint32_t khi, klo;
+        orc_walker w;
+        orc_walk_key(seed, (uint32_t)sources[j], 0u, 0u, (uint64_t)rank[j], G, S, &khi, &klo);
+        orc_walker_init(sampler, khi, klo, &w);
+        int32_t *p = path + (size_t)j * (size_t)(L + 1);
+        p[0] = sources[j];
+        for (int32_t l = 1; l <= L; ++l)
+            p[l] = orc_step_sampler(row_ptr, col_idx, p[l - 1], (uint32_t)l, sampler, &w);
+    }
+    for (int64_t v = 0; v + 8 <= n_walks; v += 8) {
+        for (int32_t l = 1; l <= L; ++l) {
+            int32_t k = 0;
+            for (int32_t a = 0; a < 8; ++a) {
+                int32_t x = path[(size_t)ord[v + a] * (size_t)(L + 1) + (size_t)l];
+                int32_t first = 1;
+                for (int32_t b = 0; b < a; ++b)
+                    if (path[(size_t)ord[v + b] * (size_t)(L + 1) + (size_t)l] == x) first = 0;
+                k += first;
+            }
+            hist[k] += 1;
+        }
+    }
+done:
+    free(rank);
+    free(seen);
+    free(ord);
+    free(path);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

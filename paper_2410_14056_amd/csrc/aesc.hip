@@ -429,8 +429,14 @@ __global__ __launch_bounds__(kBlock) void expand_hub_kernel(
 // Next frontier list of each active instance: the set bits of its next-level support bitmap,
 // in ascending vertex order (one block per instance).  Its hub rows are also appended, in any
 // order, to the hub-row list of the next level's parity.
+// Hub bits of the 32 vertices v0 .. v0 + 31 (handle ids) from the handle's hub bitmap.
+__device__ __forceinline__ uint32_t hub_word(const uint32_t *__restrict__ hubbm, int32_t v0) {
+    const int32_t w = v0 >> 5, sh = v0 & 31;
+    return sh == 0 ? hubbm[w] : (hubbm[w] >> sh) | (hubbm[w + 1] << (32 - sh));
+}
+
 __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
-    const int2 *__restrict__ vrec, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
+    const uint32_t *__restrict__ hubbm, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
     int32_t level, const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all,
     int2 *__restrict__ hubs_all, int64_t hubcap, Flags *__restrict__ fl) {
     __shared__ uint32_t wave_tot[kWavesPerBlock];
@@ -463,12 +469,13 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
         }
         int32_t pos = carry + (int32_t)(before + inc - cnt);
         uint32_t rest = word;
+        const uint32_t hw = word ? hub_word(hubbm, sl.goff + (int32_t)(wi * 32)) : 0u;
         while (rest) {
             const int bit = __builtin_ctz(rest);
             rest &= rest - 1;
             const int32_t x = sl.goff + (int32_t)(wi * 32 + bit);
             Fn[pos++] = x;
-            if (vrec[x].y > kHubRow)
+            if ((hw >> bit) & 1u)
                 hubs_all[nxt * hubcap + atomicAdd(&fl->nhub[nxt], 1)] = make_int2((int32_t)b, x);
         }
         __syncthreads();
@@ -1064,7 +1071,7 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
                                                    level, gofs_cur, Fcur, bmnext, slotbm, fl);
         expand_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs,
                                                       level, hubs, hubcap, bmnext, slotbm, fl);
-        compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(g->vrec, d_slots, bs, level,
+        compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(g->hubbm, d_slots, bs, level,
                                                                 bmnext, Fnext, hubs, hubcap, fl);
         group_scan_kernel<<<1, 1024, 0, s>>>(bs, nb, cur ^ 1, gofs_nxt);
         pull_kernel<<<kPushGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, nb, level,

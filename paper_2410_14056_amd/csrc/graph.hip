@@ -254,6 +254,7 @@ static void destroy_graph(Graph *g) {
     if (g->canon) (void)hipFree(g->canon);
     if (g->row_of) (void)hipFree(g->row_of);
     if (g->slotv) (void)hipFree(g->slotv);
+    if (g->hubbm) (void)hipFree(g->hubbm);
     for (auto &b : g->walk_scratch) b.release();
     g->est.release();
     delete g;
@@ -347,7 +348,11 @@ static int create_impl(const int32_t *row_ptr, const int32_t *col_idx, int32_t n
     g->cbase[ngraphs] = (int64_t)canon.size();
 
     size_t nb = sizeof(int32_t) * std::max<int64_t>(nnz, 1);
+    std::vector<uint32_t> hubbm((size_t)n / 32 + 2, 0u);
+    for (int32_t v = 0; v < n; ++v)
+        if (g->h_row_ptr[v + 1] - g->h_row_ptr[v] > kHubRow) hubbm[v >> 5] |= 1u << (v & 31);
     if (hipMalloc(&g->row_ptr, sizeof(int32_t) * ((size_t)n + 1)) != hipSuccess ||
+        hipMalloc(&g->hubbm, sizeof(uint32_t) * hubbm.size()) != hipSuccess ||
         hipMalloc(&g->col_idx, nb) != hipSuccess ||
         hipMalloc(&g->vrec, sizeof(int2) * std::max<int32_t>(n, 1)) != hipSuccess ||
         hipMalloc(&g->rev, nb) != hipSuccess || hipMalloc(&g->row_of, nb) != hipSuccess ||
@@ -362,7 +367,9 @@ static int create_impl(const int32_t *row_ptr, const int32_t *col_idx, int32_t n
         (nnz > 0 && hipMemcpyAsync(g->col_idx, g->h_col_idx.data(), sizeof(int32_t) * (size_t)nnz,
                                    hipMemcpyHostToDevice, s) != hipSuccess) ||
         (!canon.empty() && hipMemcpyAsync(g->canon, canon.data(), sizeof(int32_t) * canon.size(),
-                                          hipMemcpyHostToDevice, s) != hipSuccess)) {
+                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemcpyAsync(g->hubbm, hubbm.data(), sizeof(uint32_t) * hubbm.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess) {
         (void)hipGetLastError();
         set_error("upload of the graph failed");
         return fail(SABA_E_HIP);

@@ -80,6 +80,7 @@ struct Graph {
     int32_t *canon = nullptr;
     int32_t *row_of = nullptr;  // source vertex of each CSR entry
     int32_t *slotv = nullptr;   // rev[e] if the row of col[e] is longer than kHubRow, else -1
+    uint32_t *hubbm = nullptr;  // bit v set if the row of v is longer than kHubRow (n/32 + 2 words)
     // reusable scratch of the synchronous calls
     DevBuf walk_scratch[8];
     Workspace est;
