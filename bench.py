@@ -150,6 +150,71 @@ def bench_walks(args, saba, torch, np):
     }
 
 
+def _hist_percentile(h, q):
+    """Smallest k with at least a fraction q of the (vector, position) pairs at <= k distinct."""
+    import numpy as np
+    c = np.cumsum(h) / max(1, h.sum())
+    return int(np.searchsorted(c, q - 1e-12))
+
+
+def bench_ablation(args, saba, torch, np):
+    """The paper's comparison of neighbour-choice functions and walk arrangements (the Table 7
+    and Table 5 experiments) on the walk benchmark graph: each (execution mode, sampler, key
+    grouping) runs the 2^24 x 64 workload for throughput, and a paper-shaped workload (4096
+    uniform sources x 256 walks x 15 steps) for the branching statistics of 8-walk vectors."""
+    import graphgen
+    g = graphgen.rmat(args.scale, 16, 0.57, 0.19, 0.19, 1)
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    W, L = 1 << args.walks_log2, args.length
+    src = torch.from_numpy(graphgen.uniform_sources(g, W, 1)).cuda()
+    few = torch.from_numpy(np.repeat(graphgen.uniform_sources(g, 4096, 2), 256)).cuda()
+    NV, BQ = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET
+    rows_def = [
+        ("naive, Eq. (3) per-walk stream, modulo", NV, 2, 1, 0),
+        ("naive, Eq. (4) keyed hash, modulo", NV, 1, 1, 0),
+        ("naive, Eq. (5) keyed hash, scaled", NV, 0, 1, 0),
+        ("bouquet, Eq. (4) keyed hash, modulo", BQ, 1, 1, 0),
+        ("bouquet, Eq. (5) keyed hash, scaled (headline)", BQ, 0, 1, 0),
+        ("bouquet, Eq. (5) keyed, SABA groups G=64 S=20", BQ, 0, 64, 20),
+        ("bouquet, Eq. (5) keyed, SABA groups G=64 S=12", BQ, 0, 64, 12),
+        ("bouquet, Eq. (5) keyed, SABA groups G=256 S=4", BQ, 0, 256, 4),
+        ("bouquet, Eq. (4) keyed modulo, groups G=64 S=20", BQ, 1, 64, 20),
+        ("bouquet, Eq. (5) read literally (negative)", BQ, 3, 1, 0),
+    ]
+    ep = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    vi = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    rows = []
+    for name, mode, sampler, G, S in rows_def:
+        progress(f"ablation: {name}")
+        saba.walks(sg, src, L, 1, group=G, spread=S, mode=mode, sampler=sampler, endpoint=ep,
+                   visits=vi)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            saba.walks(sg, src, L, 1, group=G, spread=S, mode=mode, sampler=sampler,
+                       endpoint=ep, visits=vi)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert int(vi.sum().item()) == W * L
+        h = saba.walks(sg, few, 15, 1, group=G, spread=S, mode=mode, sampler=sampler,
+                       distinct=True).distinct.cpu().numpy()
+        rows.append({"name": name, "mode": "naive" if mode == NV else "bouquet",
+                     "sampler": sampler, "group": G, "spread": S, "ms_per_step": dt * 1e3,
+                     "walk_steps_per_s": W * L / dt,
+                     "distinct_mean": float((h * np.arange(9)).sum() / max(1, h.sum())),
+                     "distinct_p1": _hist_percentile(h, 0.01),
+                     "distinct_p10": _hist_percentile(h, 0.10),
+                     "distinct_p25": _hist_percentile(h, 0.25),
+                     "distinct_hist": h.tolist()})
+    base = rows[0]["walk_steps_per_s"]
+    for r in rows:
+        r["speedup_vs_first"] = r["walk_steps_per_s"] / base
+    return {"workload": f"rmat{args.scale}_ef16_walks_2^{args.walks_log2}x{L}_samplers",
+            "branching_workload": f"rmat{args.scale}: 4096 uniform sources x 256 walks x 15 steps",
+            "rows": rows}
+
+
 def bench_aesc(args, saba, torch, np):
     import graphgen
     t0 = time.perf_counter()
@@ -547,7 +612,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["all", "walks", "aesc", "c1", "batch", "serve", "copy"],
+    ap.add_argument("--workload",
+                    choices=["all", "walks", "aesc", "c1", "batch", "serve", "ablation", "copy"],
                     default="all")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-edges", type=int, default=32)
@@ -613,6 +679,13 @@ def main():
         out.update({"value": b["batched_edges_per_s"], "unit": "edges/s", "dtype": "f64",
                     "ms_per_step": b["batched_s"] * 1e3, "config": {"workload": b["workload"]},
                     "batch": b})
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "ablation":
+        a = bench_ablation(args, saba, torch, np)
+        head = next(r for r in a["rows"] if "headline" in r["name"])
+        out.update({"value": head["walk_steps_per_s"], "ms_per_step": head["ms_per_step"],
+                    "config": {"workload": a["workload"]}, "ablation": a})
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serve":

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define SABA_ABI_VERSION 1
+#define SABA_ABI_VERSION 2
 
 /* status codes */
 #define SABA_OK 0
@@ -55,6 +55,18 @@ extern "C" {
 /* walk execution modes (results are identical in both) */
 #define SABA_WALK_NAIVE 0   /* one lane per walk, walks in the order the sources are given */
 #define SABA_WALK_BOUQUET 1 /* walks of one start vertex run side by side in a wavefront */
+
+/* neighbour-choice functions of the walk benchmark (the paper's comparison, Sec. 3.3).  The
+ * estimator always uses SABA_SAMPLER_KEYED. */
+#define SABA_SAMPLER_KEYED 0      /* Eq. (5), keyed: u = Murmur2(cur|l, key_hi) ^ key_lo,
+                                     k = floor(u d / 2^32) */
+#define SABA_SAMPLER_KEYED_MOD 1  /* Eq. (4), keyed: the same u, k = u mod d */
+#define SABA_SAMPLER_STREAM_MOD 2 /* Eq. (3): per-walk xorshift32 stream (shifts 13, 17, 5)
+                                     seeded with key_hi ^ key_lo (0x9E3779B9 if zero),
+                                     advanced once per step, k = x mod d */
+#define SABA_SAMPLER_LITERAL 3    /* Eq. (5) read literally: u = (key_hi ^ key_lo) ^
+                                     Murmur2(cur|l, 0), k = floor(u d / 2^32); each walk is
+                                     decided by a few top bits of its seed (negative ablation) */
 
 typedef struct saba_graph saba_graph;
 
@@ -93,6 +105,15 @@ typedef struct {
     int32_t mode;            /* SABA_WALK_NAIVE or SABA_WALK_BOUQUET */
     int32_t time_kernels;    /* nonzero: fill saba_stats kernel_ms / total_ms (synchronises) */
     const int32_t *d_sources; /* [n_walks] start vertex of each walk (device) */
+    int32_t sampler;         /* SABA_SAMPLER_* (0: keyed Eq. (5)) */
+    int32_t reserved;
+    int64_t *d_distinct;     /* NULL, or [9] int64 (device): branching statistics (the Table 5
+                                experiment).  The walks are cut into consecutive vectors of 8
+                                in the order the mode runs them (naive: the order of
+                                d_sources; bouquet: by start vertex, then rank), a last partial
+                                vector left out; d_distinct[k] receives the number of (vector,
+                                position l = 1..L) pairs with k distinct vertices.  Slower
+                                kernels are used while it is set; results are unchanged. */
 } saba_walk_params;
 
 typedef struct {
@@ -219,9 +240,10 @@ int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
  * Random-walk generation (Alg. 2 / Alg. 3, neighbour choice of Eq. (5), bouquet
  * arrangement of Sec. 3.3), the synthetic benchmark of Sec. 5.4.
  *   Walk j starts at d_sources[j] (which must not be isolated).  The walks that
- *   start at a vertex s are numbered r = 0, 1, ... and walk r of s draws its
- *   choices from the key of address (s, 0, 0) and index r under (seed, G, S), so
- *   the result depends only on the multiset of sources.
+ *   start at a vertex s are numbered r = 0, 1, ... in the order of d_sources and
+ *   walk r of s draws its choices from the key of address (s, 0, 0) and index r
+ *   under (seed, G, S) with the chosen sampler, so the histograms depend only on
+ *   the multiset of sources.
  *   d_endpoint[n] (int64): walks ending at each vertex after L steps.
  *   d_visits[n] (int64): visits at positions 1..L.
  *   Both outputs are overwritten (the library clears them on `stream`).

@@ -5,6 +5,10 @@ include/saba.h); this package is its Python binding.
 """
 from ._binding import (  # noqa: F401
     EXPORTS,
+    SABA_SAMPLER_KEYED,
+    SABA_SAMPLER_KEYED_MOD,
+    SABA_SAMPLER_LITERAL,
+    SABA_SAMPLER_STREAM_MOD,
     SABA_WALK_BOUQUET,
     SABA_WALK_NAIVE,
     SabaError,

@@ -20,6 +20,10 @@ SABA_DEVICE_PTRS = 1
 SABA_TRUSTED = 2
 SABA_WALK_NAIVE = 0
 SABA_WALK_BOUQUET = 1
+SABA_SAMPLER_KEYED = 0
+SABA_SAMPLER_KEYED_MOD = 1
+SABA_SAMPLER_STREAM_MOD = 2
+SABA_SAMPLER_LITERAL = 3
 
 _ERRORS = {
     -1: "SABA_E_INVALID", -2: "SABA_E_NOMEM", -3: "SABA_E_HIP", -4: "SABA_E_GRAPH",
@@ -60,7 +64,9 @@ class Stats(ctypes.Structure):
 class WalkParams(ctypes.Structure):
     _fields_ = [("n_walks", ctypes.c_int64), ("length", ctypes.c_int32), ("seed", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("spread", ctypes.c_uint32), ("mode", ctypes.c_int32),
-                ("time_kernels", ctypes.c_int32), ("d_sources", ctypes.c_void_p)]
+                ("time_kernels", ctypes.c_int32), ("d_sources", ctypes.c_void_p),
+                ("sampler", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_distinct", ctypes.c_void_p)]
 
 
 class AescParams(ctypes.Structure):
@@ -242,25 +248,30 @@ class WalkResult:
     endpoint: torch.Tensor
     visits: torch.Tensor
     stats: dict
+    distinct: torch.Tensor | None = None
 
 
 def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group: int = 1,
           spread: int = 0, mode: int = SABA_WALK_BOUQUET, time_kernels: bool = False,
           endpoint: torch.Tensor | None = None, visits: torch.Tensor | None = None,
-          stream=None) -> WalkResult:
-    """saba_walks: endpoint / visit histograms of the walks started at `sources` (int32, device)."""
+          stream=None, sampler: int = SABA_SAMPLER_KEYED,
+          distinct: bool = False) -> WalkResult:
+    """saba_walks: endpoint / visit histograms of the walks started at `sources` (int32,
+    device); with distinct=True also the branching statistics (int64 [9])."""
     assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
     dev = sources.device
     if endpoint is None:
         endpoint = torch.empty(graph.n, dtype=torch.int64, device=dev)
     if visits is None:
         visits = torch.empty(graph.n, dtype=torch.int64, device=dev)
+    dist = torch.empty(9, dtype=torch.int64, device=dev) if distinct else None
     p = WalkParams(sources.numel(), int(length), seed & 0xFFFFFFFF, int(group), int(spread),
-                   int(mode), int(bool(time_kernels)), sources.data_ptr())
+                   int(mode), int(bool(time_kernels)), sources.data_ptr(), int(sampler), 0,
+                   None if dist is None else dist.data_ptr())
     st = Stats()
     _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
                              ctypes.byref(st), _stream_ptr(stream)))
-    return WalkResult(endpoint, visits, st.as_dict())
+    return WalkResult(endpoint, visits, st.as_dict(), dist)
 
 
 def _aesc_params(eps, lam, seed, delta=0.01, group=1, spread=0, tau_cap=0, tilde_tau_max=-1,

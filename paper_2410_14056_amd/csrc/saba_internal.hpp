@@ -180,4 +180,47 @@ __device__ __forceinline__ int32_t walk_step_local(const int2 *__restrict__ vrec
     return col[r.x + (int32_t)k];
 }
 
+// Samplers of the walk benchmark (SABA_SAMPLER_*).  A walker carries its key and, for the
+// per-walk stream of Eq. (3), the generator state.
+struct Walker {
+    WalkKey key;
+    uint32_t x;
+};
+
+template <int SM>
+__device__ __forceinline__ Walker walker_init(WalkKey key) {
+    Walker w;
+    w.key = key;
+    w.x = key.hi ^ key.lo;
+    if (SM == SABA_SAMPLER_STREAM_MOD && w.x == 0u) w.x = 0x9E3779B9u;
+    return w;
+}
+
+// One step with sampler SM: keyed Eq. (5) (multiply-high), keyed Eq. (4) (modulo), the
+// Eq. (3) stream (Marsaglia's xorshift32, shifts 13 / 17 / 5, then modulo) or Eq. (5) read
+// literally (unkeyed step hash XOR the walk's fixed seed, multiply-high).
+template <int SM>
+__device__ __forceinline__ int32_t walker_step(const int2 *__restrict__ vrec,
+                                               const int32_t *__restrict__ col, int32_t cur,
+                                               uint32_t l, Walker &w) {
+    if (SM == SABA_SAMPLER_KEYED) return walk_step(vrec, col, cur, l, w.key);
+    const int2 r = vrec[cur];
+    const uint32_t d = (uint32_t)r.y;
+    uint32_t k;
+    if (SM == SABA_SAMPLER_KEYED_MOD) {
+        k = (hash_w2((uint32_t)cur, l, w.key.hi) ^ w.key.lo) % d;
+    } else if (SM == SABA_SAMPLER_STREAM_MOD) {
+        uint32_t x = w.x;
+        x ^= x << 13;
+        x ^= x >> 17;
+        x ^= x << 5;
+        w.x = x;
+        k = x % d;
+    } else {
+        const uint32_t u = (w.key.hi ^ w.key.lo) ^ hash_w2((uint32_t)cur, l, 0u);
+        k = (uint32_t)(((uint64_t)u * d) >> 32);
+    }
+    return col[r.x + (int32_t)k];
+}
+
 }  // namespace saba

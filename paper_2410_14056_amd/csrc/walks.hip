@@ -12,6 +12,8 @@
 // order of any of these steps.
 #include <hip/hip_runtime.h>
 
+#include <hipcub/device/device_radix_sort.hpp>
+
 #include <algorithm>
 
 #include "saba_internal.hpp"
@@ -76,86 +78,183 @@ __global__ __launch_bounds__(kWalkBlock) void source_fill_kernel(const int64_t *
     }
 }
 
-// Alg. 2: one lane per walk, walks in the order the sources are given, one global
-// atomic per visit.  The rank of a walk among the walks of its source is taken from a
-// per-source counter; the set of (source, rank) pairs, and so the histograms, does
-// not depend on which walk receives which rank.
+// Branching statistics: the distinct vertices among each aligned group of 8 lanes, whose
+// walks have consecutive indices in the order the mode runs them.  Every lane of the wavefront
+// calls it; the first lane of a full group adds one to the block's LDS bin of its count.
+__device__ __forceinline__ void distinct8_count(int32_t cur, bool full, uint32_t *lhist) {
+    const int lane = __lane_id();
+    const int base = lane & ~7, p = lane & 7;
+    bool first = true;
+    for (int q = 0; q < 7; ++q) {
+        const int32_t v = __shfl(cur, base + q);
+        if (q < p && v == cur) first = false;
+    }
+    const unsigned long long fm = __ballot(first);
+    if (p == 0 && full) atomicAdd(lhist + __popcll((fm >> base) & 0xffull), 1u);
+}
+
+__device__ __forceinline__ void distinct8_flush(const uint32_t *lhist,
+                                                unsigned long long *__restrict__ out) {
+    __syncthreads();
+    if (threadIdx.x < 9 && lhist[threadIdx.x])
+        atomicAdd(out + threadIdx.x, (unsigned long long)lhist[threadIdx.x]);
+}
+
+// Rank of every walk among the walks of its start vertex, in list order: the walks sorted by
+// start vertex (a stable sort keeps list order inside a start vertex) give position p, and
+// rank = p - offs[s].
+__global__ __launch_bounds__(kWalkBlock) void list_rank_kernel(
+    const int32_t *__restrict__ sorted_src, const uint32_t *__restrict__ sorted_j, int64_t W,
+    const int64_t *__restrict__ offs, const int2 *__restrict__ vrec, int32_t n,
+    uint32_t *__restrict__ rank) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < W;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = sorted_src[p];
+        if (s < 0 || s >= n || vrec[s].y == 0) continue;  // flagged by the count kernel
+        rank[sorted_j[p]] = (uint32_t)(p - offs[s]);
+    }
+}
+
+__global__ __launch_bounds__(kWalkBlock) void iota_kernel(uint32_t *__restrict__ v, int64_t W) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < W;
+         j += (int64_t)gridDim.x * blockDim.x)
+        v[j] = (uint32_t)j;
+}
+
+// Alg. 2: one lane per walk, walks in the order the sources are given, one global atomic
+// per visit.  Walk j is the rank[j]-th walk of its start vertex in list order.
+template <int SM, bool CNT>
 __global__ __launch_bounds__(kWalkBlock) void walk_naive_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int32_t *__restrict__ src,
-    int64_t W, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int32_t n,
-    uint32_t *__restrict__ cursor, unsigned long long *__restrict__ endpoint,
-    unsigned long long *__restrict__ visits, int32_t *__restrict__ err) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= W) return;
-    const int32_t s = src[j];
-    if (s < 0 || s >= n || vrec[s].y == 0) {
-        atomicOr(err, 1);
-        return;
+    const uint32_t *__restrict__ rank, int64_t W, int32_t L, uint32_t seed, uint32_t G, uint32_t S,
+    int32_t n, unsigned long long *__restrict__ endpoint, unsigned long long *__restrict__ visits,
+    int32_t *__restrict__ err, unsigned long long *__restrict__ distinct) {
+    __shared__ uint32_t lhist[9];
+    if (CNT) {
+        if (threadIdx.x < 9) lhist[threadIdx.x] = 0;
+        __syncthreads();
     }
-    const uint32_t r = atomicAdd(cursor + s, 1u);
-    const WalkKey key = walk_key(seed, (uint32_t)s, 0u, 0u, r, G, S);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = j < W;
+    int32_t s = 0;
+    if (act) {
+        s = src[j];
+        if (s < 0 || s >= n || vrec[s].y == 0) {
+            atomicOr(err, 1);
+            act = false;
+        }
+    }
+    if (!CNT && !act) return;
+    Walker w{};
+    if (act) w = walker_init<SM>(walk_key(seed, (uint32_t)s, 0u, 0u, rank[j], G, S));
+    const bool full = (j & ~7ll) + 8 <= W;
     int32_t cur = s;
     for (int32_t l = 1; l <= L; ++l) {
-        cur = walk_step(vrec, col, cur, (uint32_t)l, key);
-        atomicAdd(visits + cur, 1ull);
+        if (act) {
+            cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, w);
+            atomicAdd(visits + cur, 1ull);
+        }
+        if (CNT) distinct8_count(cur, full, lhist);
     }
-    atomicAdd(endpoint + cur, 1ull);
+    if (act) atomicAdd(endpoint + cur, 1ull);
+    if (CNT) distinct8_flush(lhist, distinct);
 }
 
 // Alg. 3 for graphs too large for the bucketed count: bouquet order with equal visits
 // of adjacent lanes merged before the global atomics.
+template <int SM, bool CNT>
 __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_atomic_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
     const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int32_t L,
     uint32_t seed, uint32_t G, uint32_t S, unsigned long long *__restrict__ endpoint,
-    unsigned long long *__restrict__ visits) {
+    unsigned long long *__restrict__ visits, unsigned long long *__restrict__ distinct) {
+    __shared__ uint32_t lhist[9];
+    if (CNT) {
+        if (threadIdx.x < 9) lhist[threadIdx.x] = 0;
+        __syncthreads();
+    }
     // offs[n] counts only the walks whose start is a valid, non-isolated vertex
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = w < offs[n];
+    const int64_t valid = offs[n];
+    const bool active = w < valid;
+    const bool full = (w & ~7ll) + 8 <= valid;
     int32_t cur = 0;
-    WalkKey key{0u, 0u};
+    Walker wk{};
     if (active) {
         const int32_t s = bsrc[w];
         const uint64_t r = (uint64_t)(w - offs[s]);
-        key = walk_key(seed, (uint32_t)s, 0u, 0u, r, G, S);
+        wk = walker_init<SM>(walk_key(seed, (uint32_t)s, 0u, 0u, r, G, S));
         cur = s;
     }
     for (int32_t l = 1; l <= L; ++l) {
-        if (active) cur = walk_step(vrec, col, cur, (uint32_t)l, key);
+        if (active) cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, wk);
         wave_merged_add(visits, cur, active);
+        if (CNT) distinct8_count(cur, full, lhist);
     }
     wave_merged_add(endpoint, cur, active);
+    if (CNT) distinct8_flush(lhist, distinct);
 }
 
 // Alg. 3 with the bucketed count: walks w0 .. w0 + wc of the bucket order.  Walk
 // w0 + i writes its position l to vlog[(l - 1) * wc + i] and its end vertex to
 // elog[i]; the block counts its visits and ends per vertex bucket and writes the
 // counts bucket-major: cnt[b * gridDim.x + blockIdx.x].
+template <int SM, bool CNT>
 __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
     const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int64_t w0,
     int64_t wc, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int bsh, int32_t nbk,
     int32_t *__restrict__ vlog, int32_t *__restrict__ elog, long long *__restrict__ cnt_v,
-    long long *__restrict__ cnt_e) {
+    long long *__restrict__ cnt_e, unsigned long long *__restrict__ distinct) {
     extern __shared__ uint32_t lds_cnt[];
+    __shared__ uint32_t lhist[9];
     uint32_t *cv = lds_cnt, *ce = lds_cnt + nbk;
     for (int i = threadIdx.x; i < 2 * nbk; i += kWalkBlock) lds_cnt[i] = 0;
+    if (CNT && threadIdx.x < 9) lhist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t valid = min(wc, offs[n] - w0);
     for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid; tile += gridDim.x) {
         const int64_t i = tile * kWalkBlock + threadIdx.x;
-        if (i < valid) {
-            const int64_t w = w0 + i;
-            const int32_t s = bsrc[w];
-            const WalkKey key = walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S);
-            int32_t cur = s;
-            for (int32_t l = 1; l <= L; ++l) {
-                cur = walk_step(vrec, col, cur, (uint32_t)l, key);
-                __builtin_nontemporal_store(cur, vlog + (int64_t)(l - 1) * wc + i);
-                atomicAdd(cv + (cur >> bsh), 1u);
+        if (!CNT) {
+            if (i < valid) {
+                const int64_t w = w0 + i;
+                const int32_t s = bsrc[w];
+                Walker wk = walker_init<SM>(
+                    walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
+                int32_t cur = s;
+                for (int32_t l = 1; l <= L; ++l) {
+                    cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, wk);
+                    __builtin_nontemporal_store(cur, vlog + (int64_t)(l - 1) * wc + i);
+                    atomicAdd(cv + (cur >> bsh), 1u);
+                }
+                __builtin_nontemporal_store(cur, elog + i);
+                atomicAdd(ce + (cur >> bsh), 1u);
             }
-            __builtin_nontemporal_store(cur, elog + i);
-            atomicAdd(ce + (cur >> bsh), 1u);
+        } else {
+            // every lane steps (idle ones in place) so the 8-lane groups stay converged
+            const bool act = i < valid;
+            const bool full = (i & ~7ll) + 8 <= valid;
+            Walker wk{};
+            int32_t cur = 0;
+            if (act) {
+                const int64_t w = w0 + i;
+                const int32_t s = bsrc[w];
+                wk = walker_init<SM>(
+                    walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
+                cur = s;
+            }
+            for (int32_t l = 1; l <= L; ++l) {
+                if (act) {
+                    cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, wk);
+                    vlog[(int64_t)(l - 1) * wc + i] = cur;
+                    atomicAdd(cv + (cur >> bsh), 1u);
+                }
+                distinct8_count(cur, full, lhist);
+            }
+            if (act) {
+                elog[i] = cur;
+                atomicAdd(ce + (cur >> bsh), 1u);
+            }
         }
     }
     __syncthreads();
@@ -163,6 +262,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
         cnt_v[(int64_t)b * gridDim.x + blockIdx.x] = cv[b];
         cnt_e[(int64_t)b * gridDim.x + blockIdx.x] = ce[b];
     }
+    if (CNT) distinct8_flush(lhist, distinct);
 }
 
 // Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order:
@@ -329,6 +429,53 @@ static int bucket_count(int32_t *vlog, int32_t rows, int64_t wc, const int64_t *
     return SABA_OK;
 }
 
+// Launches of the kernel instantiations for sampler sm and branching statistics on/off.
+template <int SM>
+static void launch_naive_sm(bool cnt, unsigned blocks, hipStream_t s, const Graph *g,
+                            const saba_walk_params *p, const uint32_t *rank,
+                            unsigned long long *ep, unsigned long long *vi, int32_t *err,
+                            unsigned long long *dist) {
+    if (cnt)
+        walk_naive_kernel<SM, true><<<blocks, kWalkBlock, 0, s>>>(
+            g->vrec, g->col_idx, p->d_sources, rank, p->n_walks, p->length, p->seed, p->group,
+            p->spread, g->n, ep, vi, err, dist);
+    else
+        walk_naive_kernel<SM, false><<<blocks, kWalkBlock, 0, s>>>(
+            g->vrec, g->col_idx, p->d_sources, rank, p->n_walks, p->length, p->seed, p->group,
+            p->spread, g->n, ep, vi, err, dist);
+}
+
+template <int SM>
+static void launch_atomic_sm(bool cnt, unsigned blocks, hipStream_t s, const Graph *g,
+                             const saba_walk_params *p, const int32_t *bsrc, const int64_t *offs,
+                             unsigned long long *ep, unsigned long long *vi,
+                             unsigned long long *dist) {
+    if (cnt)
+        walk_bouquet_atomic_kernel<SM, true><<<blocks, kWalkBlock, 0, s>>>(
+            g->vrec, g->col_idx, bsrc, offs, g->n, p->length, p->seed, p->group, p->spread, ep,
+            vi, dist);
+    else
+        walk_bouquet_atomic_kernel<SM, false><<<blocks, kWalkBlock, 0, s>>>(
+            g->vrec, g->col_idx, bsrc, offs, g->n, p->length, p->seed, p->group, p->spread, ep,
+            vi, dist);
+}
+
+template <int SM>
+static void launch_log_sm(bool cnt, int nblk, size_t lds, hipStream_t s, const Graph *g,
+                          const saba_walk_params *p, const int32_t *bsrc, const int64_t *offs,
+                          int64_t w0, int64_t wc, int bsh, int32_t nbk, int32_t *vlog,
+                          int32_t *elog, long long *cnt_v, long long *cnt_e,
+                          unsigned long long *dist) {
+    if (cnt)
+        walk_bouquet_log_kernel<SM, true><<<nblk, kWalkBlock, lds, s>>>(
+            g->vrec, g->col_idx, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group,
+            p->spread, bsh, nbk, vlog, elog, cnt_v, cnt_e, dist);
+    else
+        walk_bouquet_log_kernel<SM, false><<<nblk, kWalkBlock, lds, s>>>(
+            g->vrec, g->col_idx, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group,
+            p->spread, bsh, nbk, vlog, elog, cnt_v, cnt_e, dist);
+}
+
 static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                       int64_t *d_visits, saba_stats *st, hipStream_t s) {
     const int64_t W = p->n_walks;
@@ -337,7 +484,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     if (W < 0 || L < 0 || p->group < 1 || p->spread > 31 ||
         (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) ||
         (W > 0 && !p->d_sources) || !d_endpoint || !d_visits ||
-        (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET)) {
+        (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET) || p->sampler < 0 ||
+        p->sampler > SABA_SAMPLER_LITERAL ||
+        (p->mode == SABA_WALK_NAIVE && W >= ((int64_t)1 << 31))) {
         set_error("invalid walk parameters");
         return SABA_E_INVALID;
     }
@@ -358,17 +507,62 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     SABA_HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * (size_t)n, s));
     auto *ep = reinterpret_cast<unsigned long long *>(d_endpoint);
     auto *vi = reinterpret_cast<unsigned long long *>(d_visits);
+    const bool cnt = p->d_distinct != nullptr;
+    auto *dist = reinterpret_cast<unsigned long long *>(p->d_distinct);
+    if (cnt) SABA_HIP_TRY(hipMemsetAsync(p->d_distinct, 0, sizeof(int64_t) * 9, s));
+    const int sm = p->sampler;
     bool counted_separately = false;
 
     if (W > 0 && p->mode == SABA_WALK_NAIVE) {
-        SABA_TRY(g->walk_scratch[0].ensure(sizeof(uint32_t) * (size_t)n));
-        uint32_t *cursor = g->walk_scratch[0].as<uint32_t>();
-        SABA_HIP_TRY(hipMemsetAsync(cursor, 0, sizeof(uint32_t) * (size_t)n, s));
+        // rank of each walk among the walks of its start vertex, in list order
+        SABA_TRY(g->walk_scratch[0].ensure(sizeof(int64_t) * (size_t)n));
+        SABA_TRY(g->walk_scratch[1].ensure(sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n)));
+        SABA_TRY(g->walk_scratch[2].ensure(sizeof(int32_t) * (size_t)W));
+        SABA_TRY(g->walk_scratch[4].ensure(sizeof(uint32_t) * 2 * (size_t)W));
+        SABA_TRY(g->walk_scratch[5].ensure(sizeof(uint32_t) * (size_t)W));
+        auto *counts = g->walk_scratch[0].as<unsigned long long>();
+        int64_t *offs = g->walk_scratch[1].as<int64_t>();
+        void *scan_tmp = offs + n + 1;
+        int32_t *sorted_src = g->walk_scratch[2].as<int32_t>();
+        uint32_t *iota = g->walk_scratch[4].as<uint32_t>(), *sorted_j = iota + W;
+        uint32_t *rank = g->walk_scratch[5].as<uint32_t>();
+        size_t sort_bytes = 0;
+        SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, p->d_sources,
+                                                        sorted_src, iota, sorted_j, (int)W, 0,
+                                                        32, s));
+        SABA_TRY(g->walk_scratch[6].ensure(std::max<size_t>(sort_bytes, 1)));
+        SABA_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int64_t) * (size_t)n, s));
+        const unsigned cblocks =
+            (unsigned)std::min<int64_t>((W + kWalkBlock - 1) / kWalkBlock, 1 << 16);
+        source_count_kernel<<<cblocks, kWalkBlock, 0, s>>>(p->d_sources, W, g->vrec, n, counts,
+                                                            err);
+        SABA_HIP_TRY(hipGetLastError());
+        SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
+        iota_kernel<<<cblocks, kWalkBlock, 0, s>>>(iota, W);
+        SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(g->walk_scratch[6].ptr, sort_bytes,
+                                                        p->d_sources, sorted_src, iota, sorted_j,
+                                                        (int)W, 0, 32, s));
+        list_rank_kernel<<<cblocks, kWalkBlock, 0, s>>>(sorted_src, sorted_j, W, offs, g->vrec, n,
+                                                         rank);
+        SABA_HIP_TRY(hipGetLastError());
         if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
-        unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
-        walk_naive_kernel<<<blocks, kWalkBlock, 0, s>>>(g->vrec, g->col_idx, p->d_sources, W, L,
-                                                        p->seed, p->group, p->spread, n, cursor,
-                                                        ep, vi, err);
+        const unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
+        switch (sm) {
+            case SABA_SAMPLER_KEYED:
+                launch_naive_sm<SABA_SAMPLER_KEYED>(cnt, blocks, s, g, p, rank, ep, vi, err, dist);
+                break;
+            case SABA_SAMPLER_KEYED_MOD:
+                launch_naive_sm<SABA_SAMPLER_KEYED_MOD>(cnt, blocks, s, g, p, rank, ep, vi, err,
+                                                        dist);
+                break;
+            case SABA_SAMPLER_STREAM_MOD:
+                launch_naive_sm<SABA_SAMPLER_STREAM_MOD>(cnt, blocks, s, g, p, rank, ep, vi, err,
+                                                         dist);
+                break;
+            default:
+                launch_naive_sm<SABA_SAMPLER_LITERAL>(cnt, blocks, s, g, p, rank, ep, vi, err,
+                                                      dist);
+        }
         SABA_HIP_TRY(hipGetLastError());
         if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
     } else if (W > 0) {
@@ -394,8 +588,23 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         if (nbk > kMaxBuckets) {
             if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
             unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
-            walk_bouquet_atomic_kernel<<<blocks, kWalkBlock, 0, s>>>(
-                g->vrec, g->col_idx, bsrc, offs, n, L, p->seed, p->group, p->spread, ep, vi);
+            switch (sm) {
+                case SABA_SAMPLER_KEYED:
+                    launch_atomic_sm<SABA_SAMPLER_KEYED>(cnt, blocks, s, g, p, bsrc, offs, ep, vi,
+                                                         dist);
+                    break;
+                case SABA_SAMPLER_KEYED_MOD:
+                    launch_atomic_sm<SABA_SAMPLER_KEYED_MOD>(cnt, blocks, s, g, p, bsrc, offs, ep,
+                                                             vi, dist);
+                    break;
+                case SABA_SAMPLER_STREAM_MOD:
+                    launch_atomic_sm<SABA_SAMPLER_STREAM_MOD>(cnt, blocks, s, g, p, bsrc, offs,
+                                                              ep, vi, dist);
+                    break;
+                default:
+                    launch_atomic_sm<SABA_SAMPLER_LITERAL>(cnt, blocks, s, g, p, bsrc, offs, ep,
+                                                           vi, dist);
+            }
             SABA_HIP_TRY(hipGetLastError());
             if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
         } else {
@@ -421,10 +630,30 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             for (int64_t w0 = 0; w0 < W; w0 += wc) {
                 const int64_t this_wc = std::min<int64_t>(wc, W - w0);
                 if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
-                walk_bouquet_log_kernel<<<nblk, kWalkBlock, sizeof(uint32_t) * 2 * nbk, s>>>(
-                    g->vrec, g->col_idx, bsrc, offs, n, w0, this_wc, L, p->seed, p->group,
-                    p->spread, bsh, nbk, vlog, elog, reinterpret_cast<long long *>(cnt_v),
-                    reinterpret_cast<long long *>(cnt_e));
+                const size_t lds = sizeof(uint32_t) * 2 * nbk;
+                auto *cv = reinterpret_cast<long long *>(cnt_v);
+                auto *ce = reinterpret_cast<long long *>(cnt_e);
+                switch (sm) {
+                    case SABA_SAMPLER_KEYED:
+                        launch_log_sm<SABA_SAMPLER_KEYED>(cnt, nblk, lds, s, g, p, bsrc, offs, w0,
+                                                          this_wc, bsh, nbk, vlog, elog, cv, ce,
+                                                          dist);
+                        break;
+                    case SABA_SAMPLER_KEYED_MOD:
+                        launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, nblk, lds, s, g, p, bsrc, offs,
+                                                              w0, this_wc, bsh, nbk, vlog, elog,
+                                                              cv, ce, dist);
+                        break;
+                    case SABA_SAMPLER_STREAM_MOD:
+                        launch_log_sm<SABA_SAMPLER_STREAM_MOD>(cnt, nblk, lds, s, g, p, bsrc,
+                                                               offs, w0, this_wc, bsh, nbk, vlog,
+                                                               elog, cv, ce, dist);
+                        break;
+                    default:
+                        launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, nblk, lds, s, g, p, bsrc, offs,
+                                                            w0, this_wc, bsh, nbk, vlog, elog, cv,
+                                                            ce, dist);
+                }
                 SABA_HIP_TRY(hipGetLastError());
                 if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
                 if (L > 0)

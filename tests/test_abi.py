@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_loads_and_reports_version():
     import paper_2410_14056_amd as saba
     lib = saba.load()
-    assert lib.saba_version() == 1
+    assert lib.saba_version() == 2
     for name in saba.EXPORTS:
         assert hasattr(lib, name)
     assert set(saba.EXPORTS) == set(declared())
@@ -56,8 +56,8 @@ def test_binding_fails_loudly_without_library(tmp_path):
 def test_structs_match_header_layout():
     import ctypes
     from paper_2410_14056_amd import _binding as b
-    # saba_walk_params: int64, int32, 3 x uint32, 2 x int32, pointer -> 40 bytes
-    assert ctypes.sizeof(b.WalkParams) == 40
+    # saba_walk_params: int64, int32, 3 x uint32, 2 x int32, pointer, 2 x int32, pointer -> 56
+    assert ctypes.sizeof(b.WalkParams) == 56
     # saba_aesc_params: 3 doubles, 3 uint32, 5 int32, int64 -> 64 bytes
     assert ctypes.sizeof(b.AescParams) == 64
     assert ctypes.sizeof(b.Stats) == 80
@@ -81,7 +81,8 @@ def test_server_structs_match_the_c_compiler(tmp_path):
         "saba_aesc_request": (b.AescRequest, ["graph", "params", "d_edges", "q", "d_sc"]),
         "saba_aesc_params": (b.AescParams, ["eps", "delta", "seed", "tau_cap", "mem_budget"]),
         "saba_stats": (b.Stats, ["walks", "warnings", "kernel_ms", "count_ms"]),
-        "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources"]),
+        "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources", "sampler",
+                                            "d_distinct"]),
         "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saba.h"', "int main(void) {"]
