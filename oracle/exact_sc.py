@@ -143,3 +143,14 @@ def truncated_resistance(row_ptr, col_idx, n, edges, taus):
         geo = np.array([sum(mk ** l for l in range(int(tau) + 1)) for mk in mu])
         out[i] = float(np.sum(c * c * geo))
     return out
+
+
+def spectral_lambda(row_ptr, col_idx, n):
+    """lambda = max(|lambda_2|, |lambda_n|) of N = D^{-1/2} A D^{-1/2} (the spectral input of
+    CalculateTau in Alg. 1), written out as the definition: a dense symmetric eigen-
+    decomposition of N (a connected graph has lambda_1 = 1).  Returns (lambda, eigenvalues
+    in ascending order)."""
+    _, A = _dense_laplacian(row_ptr, col_idx, n)
+    s = 1.0 / np.sqrt(A.sum(axis=1))
+    ev = np.linalg.eigvalsh(s[:, None] * A * s[None, :])
+    return float(max(abs(ev[-2]), abs(ev[0]))), ev
