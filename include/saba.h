@@ -119,7 +119,9 @@ typedef struct {
 typedef struct {
     double eps;            /* absolute error target (0 < eps) */
     double delta;          /* failure probability (0 < delta < 1) */
-    double lambda;         /* max(|lambda_2|, |lambda_n|) of D^-1/2 A D^-1/2, 0 < lambda < 1 */
+    double lambda;         /* max(|lambda_2|, |lambda_n|) of D^-1/2 A D^-1/2, 0 < lambda < 1;
+                              <= 0: computed on the device (saba_graph_lambda's lambda_bound,
+                              cached in the handle per graph) */
     uint32_t seed;         /* walk seed */
     uint32_t group;        /* G >= 1 walk key grouping (1 = independent walks) */
     uint32_t spread;       /* S, as in saba_walk_params */
@@ -148,6 +150,27 @@ typedef struct {
     int32_t batch_sources; /* cap on instances per batch (0: from mem_budget) */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
 } saba_batch_options;
+
+/* saba_graph_lambda arguments. */
+typedef struct {
+    int32_t graph;      /* graph of the handle */
+    int32_t max_iters;  /* Lanczos steps at most (0: 300) */
+    double tol;         /* stop when both extreme Ritz values move less than this over 10 steps
+                           (0: 1e-12) */
+    uint32_t seed;      /* start vector */
+    int32_t reserved;
+} saba_lambda_params;
+
+/* saba_graph_lambda result. */
+typedef struct {
+    double lambda;       /* max(|lambda2|, |lambdan|) */
+    double lambda_bound; /* max over the two extreme Ritz values of |theta| + its residual */
+    double lambda2;      /* largest Ritz value of N restricted to the complement of sqrt(d) */
+    double lambdan;      /* smallest Ritz value, the estimate of lambda_n */
+    double residual;     /* largest residual norm of the two extreme Ritz pairs */
+    int32_t iterations;  /* Lanczos steps taken */
+    int32_t converged;   /* 1 if the tolerance was met or an invariant subspace was found */
+} saba_lambda_result;
 
 /* Options of saba_server_create; none of them changes a result. */
 typedef struct {
@@ -229,6 +252,17 @@ int saba_graph_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
 int saba_graph_create_multi(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
                             int64_t nnz, int32_t ngraphs, const int32_t *vertex_offsets,
                             uint32_t flags, void *stream, saba_graph **out);
+
+/*
+ * The estimator's spectral input on the device (the lambda of CalculateTau, Alg. 1):
+ * max(|lambda_2|, |lambda_n|) of N = D^-1/2 A D^-1/2 for one connected graph of the handle,
+ * by a Lanczos iteration in FP64 on N with its top eigenvector sqrt(d) projected out.  Ritz
+ * values lie inside the spectrum, so lambda approaches the true value from below;
+ * lambda_bound adds each extreme pair's residual norm.  Deterministic for given arguments.
+ * Synchronises `stream`.  Errors: SABA_E_DISCONNECTED, SABA_E_INVALID.
+ */
+int saba_graph_lambda(saba_graph *g, const saba_lambda_params *p, saba_lambda_result *out,
+                      void *stream);
 
 /* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
 int saba_graph_destroy(saba_graph *g);

@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     aesc_batch,
     aesc_edge_stats,
     aesc_query,
+    graph_lambda,
     load,
     walks,
 )

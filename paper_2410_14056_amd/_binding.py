@@ -116,11 +116,28 @@ class ServerStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LambdaParams(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class LambdaResult(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lambda_bound", ctypes.c_double),
+                ("lambda2", ctypes.c_double), ("lambdan", ctypes.c_double),
+                ("residual", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
+
+
 # every symbol the header declares
 EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_create_multi",
            "saba_graph_destroy", "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
-           "saba_server_wait", "saba_server_stats", "saba_server_destroy"]
+           "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda"]
 
 _lib = None
 
@@ -151,6 +168,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_server_wait.argtypes = [P, ctypes.c_uint64, i32, ctypes.POINTER(ServerResult)]
     L.saba_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     L.saba_server_destroy.argtypes = [P]
+    L.saba_graph_lambda.argtypes = [P, ctypes.POINTER(LambdaParams), ctypes.POINTER(LambdaResult), P]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
     _lib = L
@@ -272,6 +290,16 @@ def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group
     _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
                              ctypes.byref(st), _stream_ptr(stream)))
     return WalkResult(endpoint, visits, st.as_dict(), dist)
+
+
+def graph_lambda(graph: SabaGraph, index: int = 0, max_iters: int = 0, tol: float = 0.0,
+                 seed: int = 1, stream=None) -> dict:
+    """saba_graph_lambda: lambda of graph `index` of the handle by Lanczos on the device."""
+    p = LambdaParams(int(index), int(max_iters), float(tol), seed & 0xFFFFFFFF, 0)
+    r = LambdaResult()
+    _check(load().saba_graph_lambda(graph.handle, ctypes.byref(p), ctypes.byref(r),
+                                    _stream_ptr(stream)))
+    return r.as_dict()
 
 
 def _aesc_params(eps, lam, seed, delta=0.01, group=1, spread=0, tau_cap=0, tilde_tau_max=-1,

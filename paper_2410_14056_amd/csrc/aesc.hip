@@ -894,7 +894,7 @@ int check_request(const Graph *g, int32_t graph, const saba_aesc_params &pr, int
         set_error("request names a graph the handle does not hold");
         return SABA_E_INVALID;
     }
-    if (!(p->eps > 0.0) || !(p->delta > 0.0 && p->delta < 1.0) || !(p->lambda >= 0.0) ||
+    if (!(p->eps > 0.0) || !(p->delta > 0.0 && p->delta < 1.0) || !(p->lambda > 0.0) ||
         p->group < 1 || p->spread > 31 ||
         (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) || q < -1 ||
         (q > 0 && !edges)) {
@@ -1156,6 +1156,9 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
                     saba_stats *st, hipStream_t s) {
     const int32_t *rp = g->h_row_ptr.data();
     const int32_t *ci = g->h_col_idx.data();
+    for (auto &r : reqs)
+        if (r.p.lambda <= 0.0 && r.graph >= 0 && r.graph < g->ngraphs && g->gconnected[r.graph])
+            SABA_TRY(resolve_lambda(g, r.graph, &r.p.lambda, s));
     for (auto &r : reqs) SABA_TRY(check_request(g, r.graph, r.p, r.q, r.edges));
 
     // parameter sets: requests with equal (graph, parameters) share their instances

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,9 @@ struct Graph {
     // reusable scratch of the synchronous calls
     DevBuf walk_scratch[8];
     Workspace est;
+    // lambda of each graph computed on the device for requests that leave it to the library
+    std::mutex lam_mu;
+    std::vector<double> glambda;
 };
 
 // Rows longer than this are "hub rows": the estimator finds their terms through a bitmap
@@ -91,6 +95,12 @@ struct Graph {
 constexpr int32_t kHubRow = 256;
 
 int check_graph(const saba_graph *g);
+
+// Lanczos estimate of lambda for graph `graph` of the handle, and the cached upper estimate
+// (lambda_bound, below 1) the estimator uses when a request passes lambda <= 0.
+int graph_lambda(Graph *g, int32_t graph, int32_t max_iters, double tol, uint32_t seed,
+                 saba_lambda_result *out, hipStream_t s);
+int resolve_lambda(Graph *g, int32_t graph, double *lam, hipStream_t s);
 inline Graph *G(saba_graph *g) { return reinterpret_cast<Graph *>(g); }
 inline const Graph *G(const saba_graph *g) { return reinterpret_cast<const Graph *>(g); }
 

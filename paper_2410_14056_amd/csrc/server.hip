@@ -510,7 +510,7 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
         return SABA_E_INVALID;
     }
     const auto t_entry = Clock::now();
-    const Graph *g = sv->g;
+    Graph *g = sv->g;
     {
         // refuse cheaply while the queue is full, before the pairs are validated
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -520,14 +520,24 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
             return SABA_E_BUSY;
         }
     }
-    SABA_TRY(check_request(g, rq->graph, rq->params, rq->q, rq->edges));
+    saba_aesc_params prm = rq->params;
+    if (prm.lambda <= 0.0 && rq->graph >= 0 && rq->graph < g->ngraphs &&
+        g->gconnected[rq->graph]) {
+        // lambda left to the library: computed once per graph (on a private stream) and cached
+        hipStream_t ls = nullptr;
+        SABA_HIP_TRY(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+        const int rc = resolve_lambda(g, rq->graph, &prm.lambda, ls);
+        (void)hipStreamDestroy(ls);
+        SABA_TRY(rc);
+    }
+    SABA_TRY(check_request(g, rq->graph, prm, rq->q, rq->edges));
     if (rq->q > sv->arena_edges) {
         set_error("the request has more pairs than the server's result arena holds");
         return SABA_E_INVALID;
     }
     auto r = std::make_shared<Req>();
     r->graph = rq->graph;
-    r->ps = make_pset(g, rq->graph, rq->params);
+    r->ps = make_pset(g, rq->graph, prm);
     r->sz = slot_size(g, rq->graph);
     r->q = rq->q;
     r->d_sc = rq->d_sc;

@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
                  "saba_graph_create_multi", "saba_graph_info", "saba_walks", "saba_aesc",
                  "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch",
                  "saba_server_create", "saba_server_submit", "saba_server_wait",
-                 "saba_server_stats", "saba_server_destroy"):
+                 "saba_server_stats", "saba_server_destroy", "saba_graph_lambda"):
         assert want in names
 
 
@@ -84,6 +84,9 @@ def test_server_structs_match_the_c_compiler(tmp_path):
         "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources", "sampler",
                                             "d_distinct"]),
         "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
+        "saba_lambda_params": (b.LambdaParams, ["graph", "max_iters", "tol", "seed"]),
+        "saba_lambda_result": (b.LambdaResult, ["lambda_bound", "residual", "iterations",
+                                                "converged"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saba.h"', "int main(void) {"]
     for cname, (_, fields) in checks.items():
