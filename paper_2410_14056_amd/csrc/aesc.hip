@@ -295,6 +295,7 @@ __device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, in
 // wavefronts.  Hub rows are not part of the groups' work: they go to the hub-row lists.
 constexpr int kPushGrid = 2048;
 constexpr int kHubGrid = 1024;  // blocks of the hub-row kernels
+constexpr int kPullWin = 4;     // 64-entry chunks per pass of the ordinary-row pull
 
 __global__ __launch_bounds__(1024) void group_scan_kernel(const BatchState *__restrict__ bs,
                                                           int32_t nb, int parity,
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
     const double *__restrict__ hcur_all, const uint32_t *__restrict__ bmcur_all,
     double *__restrict__ hnext_all, const int32_t *__restrict__ Fnext_all,
     Flags *__restrict__ fl) {
-    __shared__ double stage[kWavesPerBlock][64];
+    __shared__ double stage[kWavesPerBlock][64 * kPullWin];
     const int nxt = (level & 1) ^ 1;
     const int lane = __lane_id();
     double *lds = stage[threadIdx.x >> 6];
@@ -538,23 +539,33 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
         const WaveRows w = wave_rows(vrec, F, (gi - gc.gbase) * 64, fsz, true);
         if (lane == 0) visits += w.total;
         double acc = 0.0;  // the fold of this lane's own row
-        for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
-            const int32_t j = j0 + lane;
-            const bool inr = j < w.total;
-            const int32_t jc = inr ? j : w.total - 1;
-            const int o = wave_owner(w.pre, jc);
-            const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
-            double v = 0.0;
-            if (inr) {
-                const int32_t y = col[ost + (jc - opre)];
-                const int32_t yl = y - sl.goff;
-                if (bm[yl >> 5] & (1u << (yl & 31))) v = h[yl];
+        // kPullWin chunks of 64 entries per pass: their dependent loads (entry, support word,
+        // value) are issued together so that more of them are in flight per wavefront
+        for (int32_t j0 = 0; j0 < w.total; j0 += 64 * kPullWin) {
+            int32_t e[kPullWin], y[kPullWin];
+            uint32_t wd[kPullWin];
+            bool in[kPullWin];
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) {
+                const int32_t j = j0 + 64 * u + lane;
+                in[u] = j < w.total;
+                const int32_t jc = in[u] ? j : w.total - 1;
+                const int o = wave_owner(w.pre, jc);
+                const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
+                e[u] = ost + (jc - opre);
             }
-            lds[lane] = v;
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) y[u] = in[u] ? col[e[u]] - sl.goff : 0;
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) wd[u] = in[u] ? bm[y[u] >> 5] : 0u;
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u)
+                lds[64 * u + lane] = ((wd[u] >> (y[u] & 31)) & 1u) ? h[y[u]] : 0.0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int32_t k0 = max(w.pre, j0) - j0, k1 = min(w.pre + w.len, j0 + 64) - j0;
+            const int32_t k0 = max(w.pre, j0) - j0;
+            const int32_t k1 = min(w.pre + w.len, j0 + 64 * kPullWin) - j0;
             for (int32_t k = k0; k < k1; ++k) acc += lds[k];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
