@@ -41,12 +41,31 @@ AESC_STEP_BYTES = 192
 COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
 
-def kernel_source_sha() -> str:
+EST_COUNTERS = os.path.join(ROOT, "profiles", "mc_walk_kernel_chunglu1m_query1pct_counters.json")
+
+
+def kernel_source_sha(files=("saba_internal.hpp", "walks.hip")) -> str:
     h = hashlib.sha256()
-    for f in ("saba_internal.hpp", "walks.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2410_14056_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def estimator_traffic(walk_steps: int, launches: int):
+    """HBM bytes per launch of the walk-pair kernel from the committed counter runs, if they
+    were taken on the current estimator source with the same query; else None."""
+    try:
+        with open(EST_COUNTERS) as f:
+            c = json.load(f)
+    except OSError:
+        return None
+    if c.get("kernel_source_sha") != kernel_source_sha(("saba_internal.hpp", "estimator.hpp",
+                                                        "aesc.hip")):
+        return None
+    if c.get("walk_steps") != walk_steps or c.get("dispatches") != launches:
+        return None
+    return float(c["hbm_bytes_total"]) / launches
 
 
 def measured_traffic(walks: int, steps: int, chunks: int):
@@ -253,7 +272,8 @@ def bench_aesc(args, saba, torch, np):
         "max_tau": st["max_tau"], "max_ttau": st["max_ttau"],
         "roofline": {"bound": "hbm", "kernel": "mc_walk_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "kernel_ms": st["kernel_ms"],
+                     "traffic": estimator_traffic(st["walk_steps"], st["batches"]),
+                     "kernel_ms": st["kernel_ms"], "launches": st["batches"],
                      "bytes_per_step": AESC_STEP_BYTES},
     }
     if not args.no_cpu_baseline:
