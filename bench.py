@@ -247,10 +247,11 @@ def bench_aesc(args, saba, torch, np):
     q = np.ascontiguousarray(ce[np.sort(perm[:k])])
     qt = torch.from_numpy(q).cuda()
     warm = torch.from_numpy(np.ascontiguousarray(ce[np.sort(perm[k:k + 64])])).cuda()
-    saba.aesc_query(sg, warm, args.aesc_eps, lam, 1)
+    saba.aesc_query(sg, warm, args.aesc_eps, lam, 1, mem_budget=int(args.aesc_mem_gib * (1 << 30)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sc, st = saba.aesc_query(sg, qt, args.aesc_eps, lam, 1, time_kernels=True)
+    sc, st = saba.aesc_query(sg, qt, args.aesc_eps, lam, 1, time_kernels=True,
+                             mem_budget=int(args.aesc_mem_gib * (1 << 30)))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert bool(torch.isfinite(sc).all().item())
@@ -654,6 +655,8 @@ def main():
     ap.add_argument("--length", type=int, default=64)
     ap.add_argument("--aesc-frac", type=float, default=0.01)
     ap.add_argument("--aesc-eps", type=float, default=0.1)
+    ap.add_argument("--aesc-mem-gib", type=float, default=0.0,
+                    help="source scratch of the estimator (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -130,7 +130,7 @@ typedef struct {
     int32_t push_all;      /* nonzero: deterministic levels up to tau, no walks */
     int32_t batch_sources; /* sources per batch (0: chosen from mem_budget); no effect on results */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
-    int64_t mem_budget;    /* bytes of per-batch scratch (0: 8 GiB or 40% of free memory) */
+    int64_t mem_budget;    /* bytes of per-batch scratch (0: the smaller of 32 GiB and 40% of free memory) */
 } saba_aesc_params;
 
 /* One estimator request of saba_aesc_batch. */
@@ -146,7 +146,7 @@ typedef struct {
 
 /* Execution options of saba_aesc_batch; none of them changes a result. */
 typedef struct {
-    int64_t mem_budget;    /* bytes of per-batch scratch (0: 8 GiB or 40% of free memory) */
+    int64_t mem_budget;    /* bytes of per-batch scratch (0: the smaller of 32 GiB and 40% of free memory) */
     int32_t batch_sources; /* cap on instances per batch (0: from mem_budget) */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
 } saba_batch_options;
@@ -174,7 +174,7 @@ typedef struct {
 
 /* Options of saba_server_create; none of them changes a result. */
 typedef struct {
-    int64_t mem_budget;        /* bytes of source scratch over all lanes (0: 8 GiB or 40% of free
+    int64_t mem_budget;        /* bytes of source scratch over all lanes (0: the smaller of 32 GiB and 40% of free
                                   memory); each lane batches sources up to its equal share */
     int64_t max_queued_edges;  /* admission bound: query edges submitted and not finished; a
                                   request beyond it is refused with SABA_E_BUSY (0: 2^20) */

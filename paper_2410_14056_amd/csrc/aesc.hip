@@ -1308,7 +1308,7 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     SABA_HIP_TRY(hipMemGetInfo(&freeb, &totalb));
     const int64_t budget = opt.mem_budget > 0
                                ? opt.mem_budget
-                               : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
+                               : std::min<int64_t>(32ll << 30, (int64_t)(0.4 * (double)freeb));
     std::vector<SlotSize> ssz(P);
     for (int32_t k = 0; k < P; ++k) ssz[k] = slot_size(g, pgraph[k]);
     struct Batch {

@@ -431,7 +431,7 @@ extern "C" int saba_server_create(saba_graph *gh, const saba_server_options *opt
     sv->nlanes = o.lanes > 0 ? o.lanes : 2;
     const int64_t budget = o.mem_budget > 0
                                ? o.mem_budget
-                               : std::min<int64_t>(8ll << 30, (int64_t)(0.4 * (double)freeb));
+                               : std::min<int64_t>(32ll << 30, (int64_t)(0.4 * (double)freeb));
     sv->lane_budget = budget / sv->nlanes;
     sv->max_queued_edges = o.max_queued_edges > 0 ? o.max_queued_edges : (1ll << 20);
     sv->arena_edges = o.arena_edges > 0 ? o.arena_edges : (1ll << 22);
