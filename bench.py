@@ -115,6 +115,11 @@ def bench_walks(args, saba, torch, np):
     ep = torch.empty(g.n, dtype=torch.int64, device="cuda")
     vi = torch.empty(g.n, dtype=torch.int64, device="cuda")
 
+    tuned = None
+    if mode == saba.SABA_WALK_BOUQUET:
+        # one-time set-up outside the timed steps: pick the execution knobs on this workload
+        tuned = saba.autotune_walks(sg, src, L, seed, group=args.group, spread=args.spread)
+
     def step():
         return saba.walks(sg, src, L, seed, group=args.group, spread=args.spread, mode=mode,
                           time_kernels=True, endpoint=ep, visits=vi)
@@ -150,6 +155,7 @@ def bench_walks(args, saba, torch, np):
             "n": g.n, "nnz": g.nnz, "walks": W, "length": L,
             "sources": "uniform non-isolated, seed 1",
             "mode": args.mode, "group": args.group, "spread": args.spread,
+            "tuned": tuned,
         },
         "roofline": {
             "bound": "hbm",

@@ -172,6 +172,16 @@ typedef struct {
     int32_t converged;   /* 1 if the tolerance was met or an invariant subspace was found */
 } saba_lambda_result;
 
+/* Execution knobs of a handle.  None of them changes a result: walks, counts and estimates are
+ * the same under every setting (the tests compare them bit for bit). */
+typedef struct {
+    int32_t walks_per_lane;  /* walks stepped side by side per lane in the bouquet walk kernel:
+                                1, 2 or 4 (0: 1) */
+    int32_t walk_blocks;     /* blocks of the persistent bouquet walk kernel (0: 8192) */
+    int32_t est_walk_blocks; /* blocks of the estimator's walk-pair kernel (0: 2048) */
+    int32_t est_push_blocks; /* blocks of the estimator's frontier kernels (0: 2048) */
+} saba_exec_config;
+
 /* Options of saba_server_create; none of them changes a result. */
 typedef struct {
     int64_t mem_budget;        /* bytes of source scratch over all lanes (0: the smaller of 32 GiB and 40% of free
@@ -263,6 +273,20 @@ int saba_graph_create_multi(const int32_t *row_ptr, const int32_t *col_idx, int3
  */
 int saba_graph_lambda(saba_graph *g, const saba_lambda_params *p, saba_lambda_result *out,
                       void *stream);
+
+/* Read or replace the execution knobs of a handle (SABA_E_INVALID for values out of range). */
+int saba_graph_get_config(const saba_graph *g, saba_exec_config *out);
+int saba_graph_set_config(saba_graph *g, const saba_exec_config *cfg);
+
+/*
+ * Autotuner of the bouquet walk kernel: runs the walk workload `sample` (bouquet mode) under
+ * each candidate (walks per lane 1, 2, 4; 1024, 2048, 4096 or 8192 persistent blocks), times
+ * the whole call (walks and counting passes) with HIP events, keeps the fastest in the handle
+ * and returns it in *best
+ * (may be NULL).  The sample's outputs are written to scratch the call allocates.
+ */
+int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec_config *best,
+                        void *stream);
 
 /* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
 int saba_graph_destroy(saba_graph *g);

@@ -19,6 +19,9 @@ from ._binding import (  # noqa: F401
     aesc_batch,
     aesc_edge_stats,
     aesc_query,
+    autotune_walks,
+    get_config,
+    set_config,
     graph_lambda,
     load,
     walks,

@@ -133,11 +133,20 @@ class LambdaResult(ctypes.Structure):
         return d
 
 
+class ExecConfig(ctypes.Structure):
+    _fields_ = [("walks_per_lane", ctypes.c_int32), ("walk_blocks", ctypes.c_int32),
+                ("est_walk_blocks", ctypes.c_int32), ("est_push_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every symbol the header declares
 EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_create_multi",
            "saba_graph_destroy", "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
-           "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda"]
+           "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
+           "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks"]
 
 _lib = None
 
@@ -169,6 +178,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     L.saba_server_destroy.argtypes = [P]
     L.saba_graph_lambda.argtypes = [P, ctypes.POINTER(LambdaParams), ctypes.POINTER(LambdaResult), P]
+    L.saba_graph_get_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
+    L.saba_graph_set_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
+    L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
     _lib = L
@@ -290,6 +302,34 @@ def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group
     _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
                              ctypes.byref(st), _stream_ptr(stream)))
     return WalkResult(endpoint, visits, st.as_dict(), dist)
+
+
+def get_config(graph: SabaGraph) -> dict:
+    c = ExecConfig()
+    _check(load().saba_graph_get_config(graph.handle, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def set_config(graph: SabaGraph, walks_per_lane: int = 0, walk_blocks: int = 0,
+               est_walk_blocks: int = 0, est_push_blocks: int = 0):
+    """saba_graph_set_config: execution knobs of the handle (0 = default); never changes a
+    result."""
+    c = ExecConfig(int(walks_per_lane), int(walk_blocks), int(est_walk_blocks),
+                   int(est_push_blocks))
+    _check(load().saba_graph_set_config(graph.handle, ctypes.byref(c)))
+
+
+def autotune_walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int,
+                   group: int = 1, spread: int = 0, stream=None) -> dict:
+    """saba_autotune_walks: times the bouquet walk kernel on this sample under each candidate
+    setting, keeps the fastest in the handle and returns it."""
+    assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
+    p = WalkParams(sources.numel(), int(length), seed & 0xFFFFFFFF, int(group), int(spread),
+                   SABA_WALK_BOUQUET, 1, sources.data_ptr(), 0, 0, None)
+    c = ExecConfig()
+    _check(load().saba_autotune_walks(graph.handle, ctypes.byref(p), ctypes.byref(c),
+                                      _stream_ptr(stream)))
+    return c.as_dict()
 
 
 def graph_lambda(graph: SabaGraph, index: int = 0, max_iters: int = 0, tol: float = 0.0,

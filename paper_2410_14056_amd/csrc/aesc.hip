@@ -752,7 +752,8 @@ __global__ __launch_bounds__(kBlock) void nreq_kernel(
 // fixed wavefront-strided order; the loop control depends only on the wavefront index, so the
 // wavefront stays converged around its reductions.
 __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const Slot *__restrict__ slots,
+    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int4 *__restrict__ nbr,
+    const Slot *__restrict__ slots,
     const PSet *__restrict__ psets, const BatchState *__restrict__ bs, int32_t nb,
     const int64_t *__restrict__ eb, int64_t ie0, const int64_t *__restrict__ coff, int64_t nle,
     const int32_t *__restrict__ tau, const long long *__restrict__ nreq,
@@ -786,12 +787,14 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
         long long hits = 0;
         if (active) {
             const int32_t sloc = sl.v - sl.goff, tloc = t - sl.goff;
-            const WalkKey key = walk_key(ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side,
-                                         (uint64_t)k, ps.G, ps.S);
-            int32_t cur = side ? t : sl.v;
+            Walker wk = walker_init<SABA_SAMPLER_KEYED>(walk_key(
+                ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side, (uint64_t)k, ps.G, ps.S));
+            WalkPos p = walk_pos(vrec, side ? t : sl.v);
             for (int32_t l = 1; l <= L; ++l) {
-                cur = walk_step_local(vrec, col, cur, (uint32_t)l, key, sl.goff);
-                const int32_t xl = cur - sl.goff;
+                // the hash sees the graph's own vertex ids
+                p = walker_step_nbr<SABA_SAMPLER_KEYED>(nbr, p, (uint32_t)(p.v - sl.goff),
+                                                        (uint32_t)l, wk);
+                const int32_t xl = p.v - sl.goff;
                 if (bm[xl >> 5] & (1u << (xl & 31))) {  // h_ttau is zero off its support
                     acc += h[xl];
                     hits += 1;
@@ -1049,6 +1052,9 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     int2 *hubs = E[B_HUBS].as<int2>();
     hubcap = std::max<int64_t>(hubcap, 1);
     Flags *fl = ea.fl;
+    // execution knobs of the handle (none changes a result)
+    const unsigned push_blocks = g->cfg.est_push_blocks > 0 ? g->cfg.est_push_blocks : kPushGrid;
+    const unsigned walk_blocks = g->cfg.est_walk_blocks > 0 ? g->cfg.est_walk_blocks : kWalkGrid;
     ws.clean = false;  // until the batch has cleared everything it touched
 
     SABA_HIP_TRY(hipMemcpyAsync(d_slots, hslots.data(), sizeof(Slot) * nb, hipMemcpyHostToDevice,
@@ -1078,14 +1084,14 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
         SABA_HIP_TRY(hipStreamSynchronize(s));
         if (!any) break;
         group_scan_kernel<<<1, 1024, 0, s>>>(bs, nb, cur, gofs_cur);
-        expand_kernel<<<kPushGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, nb,
+        expand_kernel<<<push_blocks, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs, nb,
                                                    level, gofs_cur, Fcur, bmnext, slotbm, fl);
         expand_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->slotv, d_slots, bs,
                                                       level, hubs, hubcap, bmnext, slotbm, fl);
         compact_frontier_kernel<<<(unsigned)nb, kBlock, 0, s>>>(g->hubbm, d_slots, bs, level,
                                                                 bmnext, Fnext, hubs, hubcap, fl);
         group_scan_kernel<<<1, 1024, 0, s>>>(bs, nb, cur ^ 1, gofs_nxt);
-        pull_kernel<<<kPushGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, nb, level,
+        pull_kernel<<<push_blocks, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, nb, level,
                                                  gofs_nxt, hcur, bmcur, hnext, Fnext, fl);
         pull_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hubs,
                                                     hubcap, hcur, slotbm, hnext, fl);
@@ -1112,8 +1118,8 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     if (T > 0) {
         const bool timing = tm && tm->on;
         if (timing) SABA_HIP_TRY(hipEventRecord(tm->a, s));
-        mc_walk_kernel<<<grid_for(T, kWavesPerBlock, kWalkGrid), kBlock, 0, s>>>(
-            g->vrec, g->col_idx, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq,
+        mc_walk_kernel<<<grid_for(T, kWavesPerBlock, walk_blocks), kBlock, 0, s>>>(
+            g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq,
             hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl);
         SABA_HIP_TRY(hipGetLastError());
         if (timing) {

@@ -158,6 +158,17 @@ __global__ void build_slotv_kernel(const int2 *__restrict__ vrec, const int32_t 
         slotv[e] = vrec[col[e]].y > kHubRow ? rev[e] : -1;
 }
 
+// Walk entries: nbr[e] = (col[e], row start of col[e], degree of col[e], 0).
+__global__ void build_nbr_kernel(const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+                                 int64_t nnz, int4 *__restrict__ nbr) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t y = col[e];
+        const int2 r = vrec[y];
+        nbr[e] = make_int4(y, r.x, r.y, 0);
+    }
+}
+
 static int validate_host(const int32_t *rp, const int32_t *ci, int32_t n, int64_t nnz,
                          const std::vector<int32_t> &goff) {
     if (rp[0] != 0 || (int64_t)rp[n] != nnz) {
@@ -255,6 +266,7 @@ static void destroy_graph(Graph *g) {
     if (g->row_of) (void)hipFree(g->row_of);
     if (g->slotv) (void)hipFree(g->slotv);
     if (g->hubbm) (void)hipFree(g->hubbm);
+    if (g->nbr) (void)hipFree(g->nbr);
     for (auto &b : g->walk_scratch) b.release();
     g->est.release();
     delete g;
@@ -357,6 +369,7 @@ static int create_impl(const int32_t *row_ptr, const int32_t *col_idx, int32_t n
         hipMalloc(&g->vrec, sizeof(int2) * std::max<int32_t>(n, 1)) != hipSuccess ||
         hipMalloc(&g->rev, nb) != hipSuccess || hipMalloc(&g->row_of, nb) != hipSuccess ||
         hipMalloc(&g->slotv, nb) != hipSuccess ||
+        hipMalloc(&g->nbr, sizeof(int4) * std::max<int64_t>(nnz, 1)) != hipSuccess ||
         hipMalloc(&g->canon, sizeof(int32_t) * std::max<size_t>(canon.size(), 1)) != hipSuccess) {
         (void)hipGetLastError();
         set_error("device allocation for the graph failed");
@@ -382,6 +395,7 @@ static int create_impl(const int32_t *row_ptr, const int32_t *col_idx, int32_t n
         unsigned blocks = (unsigned)std::min<int64_t>((nnz + 255) / 256, 1 << 20);
         build_rev_kernel<<<blocks, 256, 0, s>>>(g->row_ptr, g->col_idx, g->row_of, nnz, g->rev);
         build_slotv_kernel<<<blocks, 256, 0, s>>>(g->vrec, g->col_idx, g->rev, nnz, g->slotv);
+        build_nbr_kernel<<<blocks, 256, 0, s>>>(g->vrec, g->col_idx, nnz, g->nbr);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("graph set-up kernels failed");
@@ -438,5 +452,31 @@ extern "C" int saba_graph_info(const saba_graph *gh, saba_graph_info_t *out) {
     out->connected = g->connected;
     out->bipartite = g->bipartite;
     out->ngraphs = g->ngraphs;
+    return SABA_OK;
+}
+
+extern "C" int saba_graph_get_config(const saba_graph *gh, saba_exec_config *out) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!out) {
+        set_error("out is NULL");
+        return SABA_E_INVALID;
+    }
+    *out = G(gh)->cfg;
+    return SABA_OK;
+}
+
+extern "C" int saba_graph_set_config(saba_graph *gh, const saba_exec_config *cfg) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!cfg || !(cfg->walks_per_lane == 0 || cfg->walks_per_lane == 1 ||
+                  cfg->walks_per_lane == 2 || cfg->walks_per_lane == 4) ||
+        cfg->walk_blocks < 0 || cfg->walk_blocks > (1 << 16) || cfg->est_walk_blocks < 0 ||
+        cfg->est_walk_blocks > (1 << 16) || cfg->est_push_blocks < 0 ||
+        cfg->est_push_blocks > (1 << 16)) {
+        set_error("invalid execution configuration");
+        return SABA_E_INVALID;
+    }
+    G(gh)->cfg = *cfg;
     return SABA_OK;
 }

@@ -82,9 +82,15 @@ struct Graph {
     int32_t *row_of = nullptr;  // source vertex of each CSR entry
     int32_t *slotv = nullptr;   // rev[e] if the row of col[e] is longer than kHubRow, else -1
     uint32_t *hubbm = nullptr;  // bit v set if the row of v is longer than kHubRow (n/32 + 2 words)
+    // Walk entries, one aligned 16-byte record per CSR position e: (col[e], row start of
+    // col[e], degree of col[e], 0).  A walk step reads one record at a random position and
+    // gets its next vertex together with what the following step needs, so a step costs one
+    // random sector instead of two (the vertex record, then the adjacency entry).
+    int4 *nbr = nullptr;
     // reusable scratch of the synchronous calls
     DevBuf walk_scratch[8];
     Workspace est;
+    saba_exec_config cfg{};  // execution knobs (0 = default)
     // lambda of each graph computed on the device for requests that leave it to the library
     std::mutex lam_mu;
     std::vector<double> glambda;
@@ -210,27 +216,48 @@ __device__ __forceinline__ Walker walker_init(WalkKey key) {
 // Eq. (3) stream (Marsaglia's xorshift32, shifts 13 / 17 / 5, then modulo) or Eq. (5) read
 // literally (unkeyed step hash XOR the walk's fixed seed, multiply-high).
 template <int SM>
-__device__ __forceinline__ int32_t walker_step(const int2 *__restrict__ vrec,
-                                               const int32_t *__restrict__ col, int32_t cur,
-                                               uint32_t l, Walker &w) {
-    if (SM == SABA_SAMPLER_KEYED) return walk_step(vrec, col, cur, l, w.key);
-    const int2 r = vrec[cur];
-    const uint32_t d = (uint32_t)r.y;
-    uint32_t k;
-    if (SM == SABA_SAMPLER_KEYED_MOD) {
-        k = (hash_w2((uint32_t)cur, l, w.key.hi) ^ w.key.lo) % d;
-    } else if (SM == SABA_SAMPLER_STREAM_MOD) {
+__device__ __forceinline__ uint32_t walker_choice(uint32_t cur, uint32_t d, uint32_t l,
+                                                  Walker &w) {
+    if (SM == SABA_SAMPLER_KEYED_MOD) return (hash_w2(cur, l, w.key.hi) ^ w.key.lo) % d;
+    if (SM == SABA_SAMPLER_STREAM_MOD) {
         uint32_t x = w.x;
         x ^= x << 13;
         x ^= x >> 17;
         x ^= x << 5;
         w.x = x;
-        k = x % d;
-    } else {
-        const uint32_t u = (w.key.hi ^ w.key.lo) ^ hash_w2((uint32_t)cur, l, 0u);
-        k = (uint32_t)(((uint64_t)u * d) >> 32);
+        return x % d;
     }
-    return col[r.x + (int32_t)k];
+    const uint32_t u = SM == SABA_SAMPLER_LITERAL
+                           ? (w.key.hi ^ w.key.lo) ^ hash_w2(cur, l, 0u)
+                           : hash_w2(cur, l, w.key.hi) ^ w.key.lo;
+    return (uint32_t)(((uint64_t)u * d) >> 32);
+}
+
+template <int SM>
+__device__ __forceinline__ int32_t walker_step(const int2 *__restrict__ vrec,
+                                               const int32_t *__restrict__ col, int32_t cur,
+                                               uint32_t l, Walker &w) {
+    const int2 r = vrec[cur];
+    return col[r.x + (int32_t)walker_choice<SM>((uint32_t)cur, (uint32_t)r.y, l, w)];
+}
+
+// A walk's position for the walk-entry layout: vertex, its row start and degree.
+struct WalkPos {
+    int32_t v, rs, d;
+};
+
+__device__ __forceinline__ WalkPos walk_pos(const int2 *__restrict__ vrec, int32_t v) {
+    const int2 r = vrec[v];
+    return WalkPos{v, r.x, r.y};
+}
+
+// One step on the walk entries (the same choice as walker_step); `hv` is the vertex id the
+// hash sees (the graph-local id on a multi-graph handle).
+template <int SM>
+__device__ __forceinline__ WalkPos walker_step_nbr(const int4 *__restrict__ nbr, WalkPos p,
+                                                   uint32_t hv, uint32_t l, Walker &w) {
+    const int4 f = nbr[p.rs + (int32_t)walker_choice<SM>(hv, (uint32_t)p.d, l, w)];
+    return WalkPos{f.x, f.y, f.z};
 }
 
 }  // namespace saba

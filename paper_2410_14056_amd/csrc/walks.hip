@@ -25,7 +25,7 @@ constexpr int kMaxBucketShift = 14;      // LDS histogram of up to 16384 bins (6
 constexpr int kMaxBuckets = 2048;        // LDS bucket counters in the walk and scatter kernels
 constexpr int64_t kLogCap = 1ll << 29;   // visit-log entries per chunk of walks
 constexpr int64_t kHistSlice = 1 << 18;  // log entries per histogram block
-constexpr int kPersistBlocks = 2048;
+constexpr int kPersistBlocks = 8192;
 
 // Counts of equal keys held by adjacent active lanes are merged, so one wavefront
 // issues one atomic per run of equal vertices instead of one per lane.
@@ -195,13 +195,13 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_atomic_kernel(
     if (CNT) distinct8_flush(lhist, distinct);
 }
 
-// Alg. 3 with the bucketed count: walks w0 .. w0 + wc of the bucket order.  Walk
-// w0 + i writes its position l to vlog[(l - 1) * wc + i] and its end vertex to
-// elog[i]; the block counts its visits and ends per vertex bucket and writes the
-// counts bucket-major: cnt[b * gridDim.x + blockIdx.x].
-template <int SM, bool CNT>
+// Alg. 3 with the bucketed count: walks w0 .. w0 + wc of the bucket order, stepping on the
+// 16-byte walk entries (one random read per step).  Walk w0 + i writes its position l to
+// vlog[(l - 1) * wc + i] and its end vertex to elog[i]; the block counts its visits and ends
+// per vertex bucket and writes the counts bucket-major: cnt[b * gridDim.x + blockIdx.x].
+template <int SM, bool CNT, int WPL>
 __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
+    const int2 *__restrict__ vrec, const int4 *__restrict__ nbr,
     const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int64_t w0,
     int64_t wc, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int bsh, int32_t nbk,
     int32_t *__restrict__ vlog, int32_t *__restrict__ elog, long long *__restrict__ cnt_v,
@@ -213,47 +213,72 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
     if (CNT && threadIdx.x < 9) lhist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t valid = min(wc, offs[n] - w0);
-    for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid; tile += gridDim.x) {
+    // The block runs the 256-walk tiles blockIdx.x, blockIdx.x + gridDim.x, ... (the tiles the
+    // scatter pass assigns to it); with WPL walks per lane it takes WPL of its tiles at a time
+    // and steps their walks side by side, so WPL independent reads are in flight per lane.
+    for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid;
+         tile += (int64_t)(CNT ? 1 : WPL) * gridDim.x) {
         const int64_t i = tile * kWalkBlock + threadIdx.x;
         if (!CNT) {
-            if (i < valid) {
-                const int64_t w = w0 + i;
-                const int32_t s = bsrc[w];
-                Walker wk = walker_init<SM>(
-                    walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
-                int32_t cur = s;
-                for (int32_t l = 1; l <= L; ++l) {
-                    cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, wk);
-                    __builtin_nontemporal_store(cur, vlog + (int64_t)(l - 1) * wc + i);
-                    atomicAdd(cv + (cur >> bsh), 1u);
+            int64_t ii[WPL];
+            bool act[WPL];
+            Walker wk[WPL];
+            WalkPos p[WPL];
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) {
+                ii[k] = (tile + (int64_t)k * gridDim.x) * kWalkBlock + threadIdx.x;
+                act[k] = ii[k] < valid;
+                p[k] = WalkPos{0, 0, 0};
+                if (act[k]) {
+                    const int64_t w = w0 + ii[k];
+                    const int32_t s = bsrc[w];
+                    wk[k] = walker_init<SM>(
+                        walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
+                    p[k] = walk_pos(vrec, s);
                 }
-                __builtin_nontemporal_store(cur, elog + i);
-                atomicAdd(ce + (cur >> bsh), 1u);
             }
+            for (int32_t l = 1; l <= L; ++l) {
+#pragma unroll
+                for (int k = 0; k < WPL; ++k)
+                    if (act[k]) p[k] = walker_step_nbr<SM>(nbr, p[k], (uint32_t)p[k].v, (uint32_t)l,
+                                                           wk[k]);
+#pragma unroll
+                for (int k = 0; k < WPL; ++k)
+                    if (act[k]) {
+                        __builtin_nontemporal_store(p[k].v, vlog + (int64_t)(l - 1) * wc + ii[k]);
+                        atomicAdd(cv + (p[k].v >> bsh), 1u);
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < WPL; ++k)
+                if (act[k]) {
+                    __builtin_nontemporal_store(p[k].v, elog + ii[k]);
+                    atomicAdd(ce + (p[k].v >> bsh), 1u);
+                }
         } else {
             // every lane steps (idle ones in place) so the 8-lane groups stay converged
             const bool act = i < valid;
             const bool full = (i & ~7ll) + 8 <= valid;
             Walker wk{};
-            int32_t cur = 0;
+            WalkPos p{0, 0, 0};
             if (act) {
                 const int64_t w = w0 + i;
                 const int32_t s = bsrc[w];
                 wk = walker_init<SM>(
                     walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
-                cur = s;
+                p = walk_pos(vrec, s);
             }
             for (int32_t l = 1; l <= L; ++l) {
                 if (act) {
-                    cur = walker_step<SM>(vrec, col, cur, (uint32_t)l, wk);
-                    vlog[(int64_t)(l - 1) * wc + i] = cur;
-                    atomicAdd(cv + (cur >> bsh), 1u);
+                    p = walker_step_nbr<SM>(nbr, p, (uint32_t)p.v, (uint32_t)l, wk);
+                    vlog[(int64_t)(l - 1) * wc + i] = p.v;
+                    atomicAdd(cv + (p.v >> bsh), 1u);
                 }
-                distinct8_count(cur, full, lhist);
+                distinct8_count(p.v, full, lhist);
             }
             if (act) {
-                elog[i] = cur;
-                atomicAdd(ce + (cur >> bsh), 1u);
+                elog[i] = p.v;
+                atomicAdd(ce + (p.v >> bsh), 1u);
             }
         }
     }
@@ -461,19 +486,24 @@ static void launch_atomic_sm(bool cnt, unsigned blocks, hipStream_t s, const Gra
 }
 
 template <int SM>
-static void launch_log_sm(bool cnt, int nblk, size_t lds, hipStream_t s, const Graph *g,
-                          const saba_walk_params *p, const int32_t *bsrc, const int64_t *offs,
-                          int64_t w0, int64_t wc, int bsh, int32_t nbk, int32_t *vlog,
-                          int32_t *elog, long long *cnt_v, long long *cnt_e,
+static void launch_log_sm(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s,
+                          const Graph *g, const saba_walk_params *p, const int32_t *bsrc,
+                          const int64_t *offs, int64_t w0, int64_t wc, int bsh, int32_t nbk,
+                          int32_t *vlog, int32_t *elog, long long *cnt_v, long long *cnt_e,
                           unsigned long long *dist) {
+#define SABA_LOG_LAUNCH(C, W)                                                                   \
+    walk_bouquet_log_kernel<SM, C, W><<<nblk, kWalkBlock, lds, s>>>(                             \
+        g->vrec, g->nbr, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group, p->spread, bsh, \
+        nbk, vlog, elog, cnt_v, cnt_e, dist)
     if (cnt)
-        walk_bouquet_log_kernel<SM, true><<<nblk, kWalkBlock, lds, s>>>(
-            g->vrec, g->col_idx, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group,
-            p->spread, bsh, nbk, vlog, elog, cnt_v, cnt_e, dist);
+        SABA_LOG_LAUNCH(true, 1);
+    else if (wpl >= 4)
+        SABA_LOG_LAUNCH(false, 4);
+    else if (wpl == 2)
+        SABA_LOG_LAUNCH(false, 2);
     else
-        walk_bouquet_log_kernel<SM, false><<<nblk, kWalkBlock, lds, s>>>(
-            g->vrec, g->col_idx, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group,
-            p->spread, bsh, nbk, vlog, elog, cnt_v, cnt_e, dist);
+        SABA_LOG_LAUNCH(false, 1);
+#undef SABA_LOG_LAUNCH
 }
 
 static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
@@ -612,7 +642,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             // chunks of walks whose visit log fits kLogCap entries
             int64_t wc = std::max<int64_t>(kWalkBlock, kLogCap / std::max<int32_t>(L, 1));
             wc = std::min<int64_t>(W, wc / kWalkBlock * kWalkBlock);
-            const int nblk = (int)std::min<int64_t>(kPersistBlocks, (wc + kWalkBlock - 1) / kWalkBlock);
+            const int want_blocks = g->cfg.walk_blocks > 0 ? g->cfg.walk_blocks : kPersistBlocks;
+            const int wpl = g->cfg.walks_per_lane > 0 ? g->cfg.walks_per_lane : 1;
+            const int nblk = (int)std::min<int64_t>(want_blocks, (wc + kWalkBlock - 1) / kWalkBlock);
             const int64_t ncnt = (int64_t)nbk * nblk;
             const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
             SABA_TRY(g->walk_scratch[4].ensure(sizeof(int32_t) * (size_t)(logn + wc)));
@@ -635,22 +667,22 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                 auto *ce = reinterpret_cast<long long *>(cnt_e);
                 switch (sm) {
                     case SABA_SAMPLER_KEYED:
-                        launch_log_sm<SABA_SAMPLER_KEYED>(cnt, nblk, lds, s, g, p, bsrc, offs, w0,
+                        launch_log_sm<SABA_SAMPLER_KEYED>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, w0,
                                                           this_wc, bsh, nbk, vlog, elog, cv, ce,
                                                           dist);
                         break;
                     case SABA_SAMPLER_KEYED_MOD:
-                        launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, nblk, lds, s, g, p, bsrc, offs,
+                        launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
                                                               w0, this_wc, bsh, nbk, vlog, elog,
                                                               cv, ce, dist);
                         break;
                     case SABA_SAMPLER_STREAM_MOD:
-                        launch_log_sm<SABA_SAMPLER_STREAM_MOD>(cnt, nblk, lds, s, g, p, bsrc,
+                        launch_log_sm<SABA_SAMPLER_STREAM_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc,
                                                                offs, w0, this_wc, bsh, nbk, vlog,
                                                                elog, cv, ce, dist);
                         break;
                     default:
-                        launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, nblk, lds, s, g, p, bsrc, offs,
+                        launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
                                                             w0, this_wc, bsh, nbk, vlog, elog, cv,
                                                             ce, dist);
                 }
@@ -715,4 +747,55 @@ extern "C" int saba_walks(saba_graph *gh, const saba_walk_params *p, int64_t *d_
         return SABA_E_INVALID;
     }
     return walks_impl(G(gh), p, d_endpoint, d_visits, st, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int saba_autotune_walks(saba_graph *gh, const saba_walk_params *sample,
+                                   saba_exec_config *best, void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!sample) {
+        set_error("sample is NULL");
+        return SABA_E_INVALID;
+    }
+    Graph *g = G(gh);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf out;
+    SABA_TRY(out.ensure(sizeof(int64_t) * 2 * (size_t)std::max<int32_t>(g->n, 1)));
+    struct Guard {
+        DevBuf *b;
+        ~Guard() { b->release(); }
+    } guard{&out};
+    int64_t *ep = out.as<int64_t>(), *vi = ep + std::max<int32_t>(g->n, 1);
+    saba_walk_params p = *sample;
+    p.mode = SABA_WALK_BOUQUET;
+    p.time_kernels = 1;
+    p.d_distinct = nullptr;
+    const saba_exec_config saved = g->cfg;
+    saba_exec_config pick = saved;
+    double best_ms = 1e300;
+    const int wpls[] = {1, 2, 4};
+    const int blocks[] = {1024, 2048, 4096, 8192};
+    for (int wpl : wpls)
+        for (int nb : blocks) {
+            g->cfg = saved;
+            g->cfg.walks_per_lane = wpl;
+            g->cfg.walk_blocks = nb;
+            double ms = 0.0;
+            for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                saba_stats st{};
+                const int rc = walks_impl(g, &p, ep, vi, &st, s);
+                if (rc != SABA_OK) {
+                    g->cfg = saved;
+                    return rc;
+                }
+                if (rep > 0) ms += st.total_ms;  // the whole call: walks and counting passes
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                pick = g->cfg;
+            }
+        }
+    g->cfg = pick;
+    if (best) *best = pick;
+    return SABA_OK;
 }

@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
                  "saba_graph_create_multi", "saba_graph_info", "saba_walks", "saba_aesc",
                  "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch",
                  "saba_server_create", "saba_server_submit", "saba_server_wait",
-                 "saba_server_stats", "saba_server_destroy", "saba_graph_lambda"):
+                 "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
+                 "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks"):
         assert want in names
 
 
@@ -85,6 +86,8 @@ def test_server_structs_match_the_c_compiler(tmp_path):
                                             "d_distinct"]),
         "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
         "saba_lambda_params": (b.LambdaParams, ["graph", "max_iters", "tol", "seed"]),
+        "saba_exec_config": (b.ExecConfig, ["walks_per_lane", "walk_blocks", "est_walk_blocks",
+                                            "est_push_blocks"]),
         "saba_lambda_result": (b.LambdaResult, ["lambda_bound", "residual", "iterations",
                                                 "converged"]),
     }

@@ -1,0 +1,58 @@
+"""Execution knobs and the walk autotuner: every setting gives bit-identical walks and
+estimates (they only change how the work is spread over the GPU)."""
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def saba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_14056_amd as saba
+    saba.load()
+    return saba
+
+
+def test_walk_knobs_do_not_change_results(saba, orc):
+    import torch
+    g = graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 2)
+    sg = saba.SabaGraph.from_graph(g)
+    src = graphgen.uniform_sources(g, 200001, 3)  # several tiles per block, ragged
+    t = torch.from_numpy(src).cuda()
+    ep_o, vi_o = orc.walks_histogram(g, src, 13, 9, G=8, S=24)
+    for wpl in (1, 2, 4):
+        for blocks in (7, 64, 1024, 4096):
+            saba.set_config(sg, walks_per_lane=wpl, walk_blocks=blocks)
+            r = saba.walks(sg, t, 13, 9, group=8, spread=24)
+            assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), (wpl, blocks)
+            assert np.array_equal(r.visits.cpu().numpy(), vi_o), (wpl, blocks)
+    best = saba.autotune_walks(sg, t, 13, 9)
+    assert best["walks_per_lane"] in (1, 2, 4) and best["walk_blocks"] in (1024, 2048, 4096, 8192)
+    assert saba.get_config(sg) == best
+    r = saba.walks(sg, t, 13, 9, group=8, spread=24)
+    assert np.array_equal(r.visits.cpu().numpy(), vi_o)
+
+
+def test_estimator_knobs_do_not_change_results(saba):
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(3000, 8, 2.3, 5))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    ref, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
+    for wb, pb in ((1, 1), (3, 17), (512, 4096), (8192, 64)):
+        saba.set_config(sg, est_walk_blocks=wb, est_push_blocks=pb)
+        sc, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
+        assert torch.equal(sc, ref), (wb, pb)
+
+
+def test_config_rejects_bad_values(saba):
+    sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
+    for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20}):
+        with pytest.raises(saba.SabaError) as ei:
+            saba.set_config(sg, **kw)
+        assert ei.value.name == "SABA_E_INVALID"
