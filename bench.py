@@ -30,14 +30,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and AESC edges/s at ε=0.1 (1 GPU); p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-# walk kernel: two random 64 B sectors per step (vertex record, adjacency entry) plus the
-# 4 B coalesced visit-log store
-WALK_KERNEL_BYTES_PER_STEP = 132
+# walk kernel: one random 64 B sector per step (the 16-byte walk entry of the next vertex) plus
+# the 4 B coalesced visit-log store
+WALK_KERNEL_BYTES_PER_STEP = 68
 # whole walk call, counted as the survey's unit: vertex record, adjacency entry and a random
 # visit-counter update per step
 WALK_STEP_BYTES = 192
-# estimator walk kernel: vertex record, adjacency entry, support-map lookup per step
-AESC_STEP_BYTES = 192
+# estimator walk kernel: the walk entry of the next vertex and its support-bitmap word, one
+# random 64 B sector each, per step
+AESC_STEP_BYTES = 128
 COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
 
@@ -137,6 +138,8 @@ def bench_walks(args, saba, torch, np):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert int(vi.sum().item()) == W * L and int(ep.sum().item()) == W
+    # measured ceiling of dependent random 16-byte reads (one per walk step), outside the timing
+    probe = saba.probe_random_reads(26, 256) if mode == saba.SABA_WALK_BOUQUET else None
     k_ms = float(np.mean(kms))
     call_ms = float(np.mean(tms))
     log_cap = 1 << 29  # visit-log entries per chunk (library constant)
@@ -169,6 +172,12 @@ def bench_walks(args, saba, torch, np):
             "launches_per_step": chunks,
             "bytes_per_step": kbytes,
             "steps_per_launch": per_launch_steps,
+            "random_read_ceiling": None if probe is None else {
+                "reads_per_s": probe["reads_per_s"],
+                "kernel_steps_per_s": per_launch_steps / (k_ms / chunks * 1e-3),
+                "frac": per_launch_steps / (k_ms / chunks * 1e-3) / probe["reads_per_s"],
+                "probe": "saba_probe_random_reads: 2^26 records of 16 B (1 GiB), 8192 x 256 lanes, "
+                         "256 dependent reads each"},
             "call": {"ms": call_ms, "count_ms": float(np.mean(cms)),
                      "achieved_at_192B_per_step": WALK_STEP_BYTES * W * L / (call_ms * 1e-3) / 1e9},
         },

@@ -288,6 +288,16 @@ int saba_graph_set_config(saba_graph *g, const saba_exec_config *cfg);
 int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec_config *best,
                         void *stream);
 
+/*
+ * Diagnostic: dependent random 16-byte reads per second on this GPU, the access pattern of a
+ * walk step (every lane of 8192 x 256 follows its own chain of `steps` reads at hashed positions
+ * of a buffer of 2^log2_records aligned 16-byte records, 10 <= log2_records <= 30).  It gives
+ * the measured random-access ceiling the walk kernels are compared with.  *ms (may be NULL)
+ * receives the timed launch.  Allocates and frees its buffer; synchronises `stream`.
+ */
+int saba_probe_random_reads(int32_t log2_records, int32_t steps, double *reads_per_s, double *ms,
+                            void *stream);
+
 /* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
 int saba_graph_destroy(saba_graph *g);
 

@@ -146,7 +146,8 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_graph_destroy", "saba_graph_info", "saba_walks", "saba_aesc", "saba_aesc_query",
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
-           "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks"]
+           "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
+           "saba_probe_random_reads"]
 
 _lib = None
 
@@ -181,6 +182,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_graph_get_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_graph_set_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
+    L.saba_probe_random_reads.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), P]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "saba_last_error" else ctypes.c_int
     _lib = L
@@ -302,6 +305,15 @@ def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group
     _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
                              ctypes.byref(st), _stream_ptr(stream)))
     return WalkResult(endpoint, visits, st.as_dict(), dist)
+
+
+def probe_random_reads(log2_records: int = 26, steps: int = 256, stream=None) -> dict:
+    """saba_probe_random_reads: dependent random 16-byte reads per second."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(load().saba_probe_random_reads(int(log2_records), int(steps), ctypes.byref(rate),
+                                          ctypes.byref(ms), _stream_ptr(stream)))
+    return {"reads_per_s": rate.value, "ms": ms.value, "log2_records": log2_records,
+            "steps": steps}
 
 
 def get_config(graph: SabaGraph) -> dict:

@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
                  "saba_aesc_query", "saba_aesc_edge_stats", "saba_aesc_batch",
                  "saba_server_create", "saba_server_submit", "saba_server_wait",
                  "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
-                 "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks"):
+                 "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
+                 "saba_probe_random_reads"):
         assert want in names
 
 
