@@ -505,11 +505,11 @@ def bench_serve(args, saba, torch, np):
         return saba.SabaServer(mg, lanes=args.serve_lanes, mem_budget=budget,
                                max_batch_sources=args.serve_max_batch, **kw)
 
-    def stream(seed):
+    def stream(seed, qmax=4096):
         rng = np.random.default_rng(seed)
         while True:
             k = int(rng.integers(len(graphs)))
-            q = int(rng.integers(1, 4097))
+            q = int(rng.integers(1, qmax + 1))
             m = ces[k].shape[0]
             pick = rng.choice(m, q, replace=False) if q < m else np.arange(m)
             yield k, np.ascontiguousarray(ces[k][pick]), float(rng.choice([0.1, 0.2, 0.3]))
@@ -551,6 +551,42 @@ def bench_serve(args, saba, torch, np):
                     "refused": rejected, "failed": sum(1 for d in done if d["status"] != 0)})
         return out
 
+    def compare(gen, count, label):
+        progress(f"serve workload: plain calls against the server ({label} requests)")
+        reqs = [next(gen) for _ in range(count)]
+        handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
+        dev = [torch.from_numpy(e).cuda() for _, e, _ in reqs]
+        # the plain path keeps each graph's scratch between calls: size it once, untimed, with a
+        # request of the largest size on every graph (the server allocates its own at creation)
+        for k, h in enumerate(handles):
+            m = ces[k].shape[0]
+            warm = torch.from_numpy(np.ascontiguousarray(ces[k][:min(m, 4096)])).cuda()
+            saba.aesc_query(h, warm, 0.3, lams[k], 1, mem_budget=budget)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [saba.aesc_query(handles[k], d, eps, lams[k], 1, mem_budget=budget)[0]
+                 for (k, _, eps), d in zip(reqs, dev)]
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        del handles
+        keep = {}
+        with server() as srv:
+            col = _Collector(srv)
+            t0 = time.perf_counter()
+            tickets = []
+            for r in reqs:
+                tickets.append(submit(srv, r))
+                col.q.put((tickets[-1], len(r[1]), keep))
+            col.finish()
+            t_served = time.perf_counter() - t0
+        same = all(bool(torch.equal(p, keep[t])) for p, t in zip(plain, tickets))
+        assert same, "served results differ from the plain per-request results"
+        nedge = sum(len(e) for _, e, _ in reqs)
+        return {"requests": len(reqs), "edges": nedge, "plain_s": t_plain,
+                "plain_edges_per_s": nedge / t_plain, "served_s": t_served,
+                "served_edges_per_s": nedge / t_served, "speedup": t_plain / t_served,
+                "identical": same}
+
     # warm the lanes' scratch on the largest graph
     with server() as srv:
         t = srv.submit(15, ces[15][:256], 0.1, lams[15], 1)
@@ -575,42 +611,10 @@ def bench_serve(args, saba, torch, np):
         res["sustained"] = open_loop(srv, rate, args.serve_sustain_seconds, 12, "sustained")
         res["sustained"]["server"] = srv.stats()
 
-    # plain one-request-per-call path against the server on the same requests
-    progress("serve workload: plain calls against the server")
-    gen = stream(13)
-    reqs = [next(gen) for _ in range(args.serve_compare)]
-    handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
-    dev = [torch.from_numpy(e).cuda() for _, e, _ in reqs]
-    # the plain path keeps each graph's scratch between calls: size it once, untimed, with a
-    # request of the largest size on every graph (the server allocates its own at creation)
-    for k, h in enumerate(handles):
-        m = ces[k].shape[0]
-        warm = torch.from_numpy(np.ascontiguousarray(ces[k][:min(m, 4096)])).cuda()
-        saba.aesc_query(h, warm, 0.3, lams[k], 1, mem_budget=budget)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain = [saba.aesc_query(handles[k], d, eps, lams[k], 1, mem_budget=budget)[0]
-             for (k, _, eps), d in zip(reqs, dev)]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    del handles
-    keep = {}
-    with server() as srv:
-        col = _Collector(srv)
-        t0 = time.perf_counter()
-        tickets = []
-        for r in reqs:
-            tickets.append(submit(srv, r))
-            col.q.put((tickets[-1], len(r[1]), keep))
-        col.finish()
-        t_served = time.perf_counter() - t0
-    same = all(bool(torch.equal(p, keep[t])) for p, t in zip(plain, tickets))
-    assert same, "served results differ from the plain per-request results"
-    nedge = sum(len(e) for _, e, _ in reqs)
-    res["plain_vs_served"] = {"requests": len(reqs), "edges": nedge, "plain_s": t_plain,
-                              "plain_edges_per_s": nedge / t_plain, "served_s": t_served,
-                              "served_edges_per_s": nedge / t_served,
-                              "speedup": t_plain / t_served, "identical": same}
+    # plain one-request-per-call path against the server on the same requests: requests of
+    # the workload's size, and small requests (1-64 edges), where per-call work dominates
+    res["plain_vs_served"] = compare(stream(13), args.serve_compare, "workload-sized")
+    res["plain_vs_served_small"] = compare(stream(14, qmax=64), 256, "small")
     return res
 
 
