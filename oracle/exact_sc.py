@@ -154,3 +154,37 @@ def spectral_lambda(row_ptr, col_idx, n):
     s = 1.0 / np.sqrt(A.sum(axis=1))
     ev = np.linalg.eigvalsh(s[:, None] * A * s[None, :])
     return float(max(abs(ev[-2]), abs(ev[0]))), ev
+
+
+def top_eigenpairs(row_ptr, col_idx, n, omega):
+    """The omega eigenpairs of N = D^{-1/2} A D^{-1/2} of largest |eigenvalue| other than the
+    trivial one (eigenvalue 1, vector sqrt(d)/sqrt(2m)), by a dense symmetric eigen-
+    decomposition; and lambda_rest, the largest |eigenvalue| of the others.  Returns
+    (values[omega], vectors[n, omega], lambda_rest)."""
+    _, A = _dense_laplacian(row_ptr, col_idx, n)
+    s = 1.0 / np.sqrt(A.sum(axis=1))
+    mu, U = np.linalg.eigh(s[:, None] * A * s[None, :])
+    keep = np.arange(n - 1)  # eigh sorts ascending: the trivial eigenvalue 1 is the last
+    order = keep[np.argsort(-np.abs(mu[keep]), kind="stable")]
+    top, rest = order[:omega], order[omega:]
+    lam_rest = float(np.max(np.abs(mu[rest]))) if len(rest) else 0.0
+    return mu[top], U[:, top], lam_rest
+
+
+def eigen_tail_correction(row_ptr, col_idx, n, edges, taus, values, vectors):
+    """The part of the truncation remainder r - r_tau that the given eigenpairs carry:
+    sum_k c_k mu_k^(tau+1) / (1 - mu_k), c_k = (u_k(s)/sqrt(d_s) - u_k(t)/sqrt(d_t))^2,
+    the geometric tail of the spectral series of the truncated resistance (one tau per
+    edge; the power by repeated multiplication)."""
+    d = np.diff(np.asarray(row_ptr)).astype(np.float64)
+    out = np.zeros(len(edges))
+    for i, ((a, b), tau) in enumerate(zip(edges, taus)):
+        acc = 0.0
+        for k, mk in enumerate(values):
+            c = vectors[a, k] / np.sqrt(d[a]) - vectors[b, k] / np.sqrt(d[b])
+            p = mk
+            for _ in range(int(tau)):
+                p = p * mk
+            acc += c * c * p / (1.0 - mk)
+        out[i] = acc
+    return out
