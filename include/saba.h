@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define SABA_ABI_VERSION 2
+#define SABA_ABI_VERSION 3
 
 /* status codes */
 #define SABA_OK 0
@@ -131,6 +131,16 @@ typedef struct {
     int32_t batch_sources; /* sources per batch (0: chosen from mem_budget); no effect on results */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
     int64_t mem_budget;    /* bytes of per-batch scratch (0: the smaller of 32 GiB and 40% of free memory) */
+    int32_t omega;         /* eigenpairs used (Alg. 1's omega), 0 <= omega <= 64.  0: the plain
+                              truncated series with tau from lambda.  omega > 0: the library
+                              finds the omega nontrivial eigenpairs of N of largest |theta|
+                              (saba_graph_spectrum with its defaults, cached per graph and
+                              omega), adds their exact contribution beyond each edge's tau to
+                              the estimate, and takes tau from the radius of the rest of the
+                              spectrum: lambda > 0 is then that radius, given by the caller,
+                              and lambda <= 0 leaves it to the library (lambda_rest_bound).
+                              Not accepted by the server. */
+    int32_t reserved;      /* 0 */
 } saba_aesc_params;
 
 /* One estimator request of saba_aesc_batch. */
@@ -171,6 +181,28 @@ typedef struct {
     int32_t iterations;  /* Lanczos steps taken */
     int32_t converged;   /* 1 if the tolerance was met or an invariant subspace was found */
 } saba_lambda_result;
+
+/* saba_graph_spectrum arguments. */
+typedef struct {
+    int32_t graph;      /* graph of the handle */
+    int32_t omega;      /* eigenpairs wanted, 1 <= omega <= 64 and omega < n of the graph */
+    int32_t max_iters;  /* Lanczos steps at most (0: the smaller of n - 1 and 1000) */
+    uint32_t seed;      /* start vector (the estimator uses 1) */
+    double tol;         /* residual norm each kept pair must reach (0: 1e-10) */
+} saba_spectrum_params;
+
+/* saba_graph_spectrum result. */
+typedef struct {
+    double lambda_rest;       /* largest |Ritz value| of N on the complement of sqrt(d) and
+                                 of the kept eigenvectors */
+    double lambda_rest_bound; /* lambda_rest plus the residual norm of its Ritz pair */
+    double max_residual;      /* largest ||N u_k - theta_k u_k|| over the kept pairs */
+    int32_t pairs;            /* pairs kept: omega, or fewer when the Krylov space of the start
+                                 vector is exhausted first (repeated eigenvalues) */
+    int32_t iterations;       /* Lanczos steps of the eigenpair run */
+    int32_t converged;        /* 1 if every kept pair met tol */
+    int32_t reserved;
+} saba_spectrum_result;
 
 /* Execution knobs of a handle.  None of them changes a result: walks, counts and estimates are
  * the same under every setting (the tests compare them bit for bit). */
@@ -273,6 +305,27 @@ int saba_graph_create_multi(const int32_t *row_ptr, const int32_t *col_idx, int3
  */
 int saba_graph_lambda(saba_graph *g, const saba_lambda_params *p, saba_lambda_result *out,
                       void *stream);
+
+/*
+ * Leading eigenpairs of N = D^-1/2 A D^-1/2 for one connected graph of the handle: the
+ * `pairs` nontrivial eigenpairs of largest |theta| (omega of them unless the Krylov space of
+ * the start vector runs out first), the spectral input of the omega > 0 form of
+ * CalculateTau (Alg. 1).  Lanczos in FP64 on N with sqrt(d) projected out and every new
+ * vector reorthogonalised against all earlier ones (twice); Ritz values from Sturm
+ * bisection of the tridiagonal matrix and Ritz vectors from inverse iteration, mapped back
+ * through the stored basis.  A second, deflated Lanczos run on the complement of sqrt(d) and
+ * the kept vectors, from another start vector, gives lambda_rest, so that eigenvalues the
+ * first run could not separate (copies of a repeated eigenvalue) still bound the truncation.
+ *   values[omega] (host): theta_k by decreasing |theta| (equal |theta|: positive first);
+ *   entries past `pairs` are set to 0.
+ *   d_vectors (device, may be NULL): [omega][n of the graph] unit eigenvectors u_k, row k
+ *   for theta_k (the sign is deterministic, not specified); rows past `pairs` are set to 0.
+ * Needs (min(max_iters, n - 1) + 1) * n * 8 bytes of device scratch, released on return.
+ * Deterministic for given arguments.  Synchronises `stream`.  Errors: SABA_E_DISCONNECTED,
+ * SABA_E_INVALID, SABA_E_NOMEM.
+ */
+int saba_graph_spectrum(saba_graph *g, const saba_spectrum_params *p, double *values,
+                        double *d_vectors, saba_spectrum_result *out, void *stream);
 
 /* Read or replace the execution knobs of a handle (SABA_E_INVALID for values out of range). */
 int saba_graph_get_config(const saba_graph *g, saba_exec_config *out);

@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401
     get_config,
     set_config,
     graph_lambda,
+    graph_spectrum,
     probe_random_reads,
     load,
     walks,

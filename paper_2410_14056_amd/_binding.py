@@ -74,7 +74,8 @@ class AescParams(ctypes.Structure):
                 ("seed", ctypes.c_uint32), ("group", ctypes.c_uint32), ("spread", ctypes.c_uint32),
                 ("tau_cap", ctypes.c_int32), ("tilde_tau_max", ctypes.c_int32),
                 ("push_all", ctypes.c_int32), ("batch_sources", ctypes.c_int32),
-                ("time_kernels", ctypes.c_int32), ("mem_budget", ctypes.c_int64)]
+                ("time_kernels", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
+                ("omega", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class AescRequest(ctypes.Structure):
@@ -133,6 +134,21 @@ class LambdaResult(ctypes.Structure):
         return d
 
 
+class SpectrumParams(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("omega", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("seed", ctypes.c_uint32), ("tol", ctypes.c_double)]
+
+
+class SpectrumResult(ctypes.Structure):
+    _fields_ = [("lambda_rest", ctypes.c_double), ("lambda_rest_bound", ctypes.c_double),
+                ("max_residual", ctypes.c_double), ("pairs", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class ExecConfig(ctypes.Structure):
     _fields_ = [("walks_per_lane", ctypes.c_int32), ("walk_blocks", ctypes.c_int32),
                 ("est_walk_blocks", ctypes.c_int32), ("est_push_blocks", ctypes.c_int32)]
@@ -147,7 +163,7 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
-           "saba_probe_random_reads"]
+           "saba_probe_random_reads", "saba_graph_spectrum"]
 
 _lib = None
 
@@ -182,6 +198,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_graph_get_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_graph_set_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
+    L.saba_graph_spectrum.argtypes = [P, ctypes.POINTER(SpectrumParams), P, P,
+                                      ctypes.POINTER(SpectrumResult), P]
     L.saba_probe_random_reads.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), P]
     for name in EXPORTS:
@@ -221,6 +239,7 @@ class SabaGraph:
         self._h = h
         self.n = n
         self.nnz = ci.size
+        self.offsets = [0, n]
 
     @classmethod
     def from_graph(cls, g, **kw):
@@ -252,12 +271,17 @@ class SabaGraph:
         self._h = h
         self.n = offs[-1]
         self.nnz = nnz
+        self.offsets = list(offs)
         self.graph_m = [int(g.col_idx.size) // 2 for g in graphs]
         return self
 
     @property
     def handle(self):
         return self._h
+
+    def n_of(self, index: int = 0) -> int:
+        """Vertex count of graph `index` of the handle."""
+        return self.offsets[index + 1] - self.offsets[index]
 
     def info(self) -> dict:
         out = GraphInfo()
@@ -354,11 +378,34 @@ def graph_lambda(graph: SabaGraph, index: int = 0, max_iters: int = 0, tol: floa
     return r.as_dict()
 
 
+def graph_spectrum(graph: SabaGraph, omega: int, index: int = 0, max_iters: int = 0,
+                   tol: float = 0.0, seed: int = 1, vectors: bool = True, stream=None) -> dict:
+    """saba_graph_spectrum: the omega nontrivial eigenpairs of D^-1/2 A D^-1/2 of largest
+    |theta| for graph `index` of the handle, and the radius of the rest of the spectrum.
+    Returns the result fields plus "values" (numpy, by decreasing |theta|) and "vectors"
+    (a [omega, n] float64 CUDA tensor of unit eigenvectors, or None)."""
+    import numpy as np
+    n = graph.n_of(index)
+    p = SpectrumParams(int(index), int(omega), int(max_iters), seed & 0xFFFFFFFF, float(tol))
+    vals = (ctypes.c_double * max(int(omega), 1))()
+    vec = None
+    if vectors and omega > 0:
+        vec = torch.empty((int(omega), n), dtype=torch.float64, device="cuda")
+    r = SpectrumResult()
+    _check(load().saba_graph_spectrum(graph.handle, ctypes.byref(p), vals,
+                                      vec.data_ptr() if vec is not None else None,
+                                      ctypes.byref(r), _stream_ptr(stream)))
+    d = r.as_dict()
+    d["values"] = np.array(vals[:max(int(omega), 0)], dtype=np.float64)
+    d["vectors"] = vec
+    return d
+
+
 def _aesc_params(eps, lam, seed, delta=0.01, group=1, spread=0, tau_cap=0, tilde_tau_max=-1,
-                 push_all=False, batch_sources=0, time_kernels=False, mem_budget=0):
+                 push_all=False, batch_sources=0, time_kernels=False, mem_budget=0, omega=0):
     return AescParams(float(eps), float(delta), float(lam), seed & 0xFFFFFFFF, int(group),
                       int(spread), int(tau_cap), int(tilde_tau_max), int(bool(push_all)),
-                      int(batch_sources), int(bool(time_kernels)), int(mem_budget))
+                      int(batch_sources), int(bool(time_kernels)), int(mem_budget), int(omega), 0)
 
 
 def aesc(graph: SabaGraph, eps: float, lam: float, seed: int, device="cuda", stream=None, **kw):

@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -887,6 +888,52 @@ __global__ void finalize_pairs_kernel(const int64_t *__restrict__ pairs, int64_t
         sc[j] = g[pairs[2 * j]] + g[pairs[2 * j + 1]];
 }
 
+// The omega > 0 form of CalculateTau: the kept eigenpairs' exact contribution beyond the
+// truncation, sum_k (y_k(a) - y_k(b))^2 theta_k^(tau+1) / (1 - theta_k) with y_k = u_k / sqrt(d)
+// (the geometric tail of the spectral series of the resistance).  The power by squaring.
+__device__ double eigen_tail(const double *__restrict__ theta, const double *__restrict__ y,
+                             int64_t gn, int32_t pairs, int32_t a, int32_t b, int32_t tau) {
+    double acc = 0.0;
+    for (int32_t k = 0; k < pairs; ++k) {
+        const double t = theta[k];
+        const double c = y[(int64_t)k * gn + a] - y[(int64_t)k * gn + b];
+        double p = 1.0, base = t;
+        for (uint32_t e = (uint32_t)tau + 1u; e; e >>= 1) {
+            if (e & 1u) p *= base;
+            base *= base;
+        }
+        acc += c * c * p / (1.0 - t);
+    }
+    return acc;
+}
+
+// All edges of one graph in canonical order: the edge (row_of[e], col[e]) with its tau.
+__global__ void tail_all_kernel(const int32_t *__restrict__ canon, const int32_t *__restrict__ row_of,
+                                const int32_t *__restrict__ col, int64_t cb, int64_t m,
+                                int64_t base, int32_t gpos, int32_t goff,
+                                const int32_t *__restrict__ tau, const double *__restrict__ theta,
+                                const double *__restrict__ y, int64_t gn, int32_t pairs,
+                                double *__restrict__ sc) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = canon[cb + i];
+        sc[i] += eigen_tail(theta, y, gn, pairs, row_of[e] - goff, col[e] - goff,
+                            tau[base + (e - gpos)]);
+    }
+}
+
+// Query pairs (graph-local ids) with the tau of their first instance edge.
+__global__ void tail_pairs_kernel(const int32_t *__restrict__ edges,
+                                  const int64_t *__restrict__ pairs_ie, int64_t q,
+                                  const int32_t *__restrict__ tau, const double *__restrict__ theta,
+                                  const double *__restrict__ y, int64_t gn, int32_t pairs,
+                                  double *__restrict__ sc) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q;
+         j += (int64_t)gridDim.x * blockDim.x)
+        sc[j] += eigen_tail(theta, y, gn, pairs, edges[2 * j], edges[2 * j + 1],
+                            tau[pairs_ie[2 * j]]);
+}
+
 __global__ void export_ttau_kernel(const int32_t *__restrict__ row_of, int64_t nnz,
                                    const int32_t *__restrict__ ttau_inst,
                                    int32_t *__restrict__ ttau) {
@@ -916,6 +963,10 @@ int check_request(const Graph *g, int32_t graph, const saba_aesc_params &pr, int
         return SABA_E_INVALID;
     }
     const int32_t a = g->goff[graph], z = g->goff[graph + 1];
+    if (p->omega < 0 || p->omega > kMaxOmega || (p->omega > 0 && p->omega >= z - a)) {
+        set_error("omega must lie in [0, 64] and below the vertex count of the graph");
+        return SABA_E_INVALID;
+    }
     if (!g->gconnected[graph] || z - a < 2) {
         set_error("the estimator needs a connected graph with at least one edge");
         return SABA_E_DISCONNECTED;
@@ -1147,6 +1198,7 @@ struct Request {
     int64_t q = -1;                  // -1: all edges of the graph
     double *sc = nullptr;
     int32_t pid = -1;
+    const Spectrum *spec = nullptr;  // eigenpairs of the omega > 0 correction
 };
 
 struct Exports {  // per CSR position (single graph, all edges)
@@ -1173,9 +1225,18 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
                     saba_stats *st, hipStream_t s) {
     const int32_t *rp = g->h_row_ptr.data();
     const int32_t *ci = g->h_col_idx.data();
-    for (auto &r : reqs)
-        if (r.p.lambda <= 0.0 && r.graph >= 0 && r.graph < g->ngraphs && g->gconnected[r.graph])
+    for (auto &r : reqs) {
+        if (r.graph < 0 || r.graph >= g->ngraphs || !g->gconnected[r.graph]) continue;
+        const int32_t gn = g->goff[r.graph + 1] - g->goff[r.graph];
+        if (r.p.omega > 0 && r.p.omega <= kMaxOmega && r.p.omega < gn && !g->gbipartite[r.graph]) {
+            // tau from the radius of the spectrum outside the kept pairs
+            SABA_TRY(resolve_spectrum(g, r.graph, r.p.omega, &r.spec, s));
+            if (r.p.lambda <= 0.0)
+                r.p.lambda = std::min(std::max(r.spec->lambda_rest_bound, DBL_MIN), 1.0 - 1e-12);
+        } else if (r.p.lambda <= 0.0 && r.p.omega == 0) {
             SABA_TRY(resolve_lambda(g, r.graph, &r.p.lambda, s));
+        }
+    }
     for (auto &r : reqs) SABA_TRY(check_request(g, r.graph, r.p, r.q, r.edges));
 
     // parameter sets: requests with equal (graph, parameters) share their instances
@@ -1394,15 +1455,25 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         if (r.q < 0) {
             const int32_t ga = g->goff[r.graph];
             const int64_t cb = g->cbase[r.graph], m = g->cbase[r.graph + 1] - cb;
-            if (m > 0)
+            if (m > 0) {
                 finalize_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, s>>>(
                     g->canon, g->rev, cb, m, pbase[r.pid], rp[ga], ea.g, r.sc);
+                if (r.spec && r.spec->pairs > 0)
+                    tail_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, s>>>(
+                        g->canon, g->row_of, g->col_idx, cb, m, pbase[r.pid], rp[ga], ga, ea.tau,
+                        r.spec->d_theta(), r.spec->d_y(), g->goff[r.graph + 1] - ga,
+                        r.spec->pairs, r.sc);
+            }
         } else if (r.q > 0) {
             SABA_HIP_TRY(hipMemcpyAsync(d_pairs + off, qpairs[i].data(),
                                         sizeof(int64_t) * qpairs[i].size(), hipMemcpyHostToDevice,
                                         s));
             finalize_pairs_kernel<<<grid_for(r.q, 256, 1 << 16), 256, 0, s>>>(d_pairs + off, r.q,
                                                                              ea.g, r.sc);
+            if (r.spec && r.spec->pairs > 0)
+                tail_pairs_kernel<<<grid_for(r.q, 256, 1 << 16), 256, 0, s>>>(
+                    r.edges, d_pairs + off, r.q, ea.tau, r.spec->d_theta(), r.spec->d_y(),
+                    g->goff[r.graph + 1] - g->goff[r.graph], r.spec->pairs, r.sc);
             off += (int64_t)qpairs[i].size();
         }
         SABA_HIP_TRY(hipGetLastError());

@@ -269,6 +269,7 @@ static void destroy_graph(Graph *g) {
     if (g->nbr) (void)hipFree(g->nbr);
     for (auto &b : g->walk_scratch) b.release();
     g->est.release();
+    for (auto &sp : g->spectra) sp->dev.release();
     delete g;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -94,6 +95,25 @@ struct Graph {
     // lambda of each graph computed on the device for requests that leave it to the library
     std::mutex lam_mu;
     std::vector<double> glambda;
+    // leading eigenpairs of graphs the estimator was asked to correct with (omega > 0)
+    std::mutex spec_mu;
+    std::vector<std::unique_ptr<struct Spectrum>> spectra;
+};
+
+// The omega nontrivial eigenpairs (theta_k, u_k) of N = D^-1/2 A D^-1/2 of largest |theta|
+// that a Lanczos run found for one graph, and the radius of the rest of the spectrum.
+struct Spectrum {
+    int32_t graph = -1, omega = 0;  // request
+    int32_t pairs = 0;              // pairs kept (omega, or fewer on an exhausted Krylov space)
+    int32_t iterations = 0, converged = 0;
+    double lambda_rest = 0.0, lambda_rest_bound = 0.0, max_residual = 0.0;
+    std::vector<double> theta;      // host copy of the kept eigenvalues
+    // device: theta[pairs], then y[pairs][gn] with y_k = u_k / sqrt(d) (the estimator's
+    // correction reads y_k at both ends of an edge), then u[pairs][gn]
+    DevBuf dev;
+    const double *d_theta() const { return dev.as<double>(); }
+    const double *d_y() const { return dev.as<double>() + pairs; }
+    const double *d_u(int64_t gn) const { return dev.as<double>() + pairs + pairs * gn; }
 };
 
 // Rows longer than this are "hub rows": the estimator finds their terms through a bitmap
@@ -107,6 +127,12 @@ int check_graph(const saba_graph *g);
 int graph_lambda(Graph *g, int32_t graph, int32_t max_iters, double tol, uint32_t seed,
                  saba_lambda_result *out, hipStream_t s);
 int resolve_lambda(Graph *g, int32_t graph, double *lam, hipStream_t s);
+// Leading eigenpairs of graph `graph` (Lanczos with full reorthogonalisation), and the cached
+// set with the library's defaults that the estimator's correction uses for omega > 0.
+constexpr int32_t kMaxOmega = 64;
+int graph_spectrum(Graph *g, int32_t graph, int32_t omega, int32_t max_iters, double tol,
+                   uint32_t seed, Spectrum *out, hipStream_t s);
+int resolve_spectrum(Graph *g, int32_t graph, int32_t omega, const Spectrum **out, hipStream_t s);
 inline Graph *G(saba_graph *g) { return reinterpret_cast<Graph *>(g); }
 inline const Graph *G(const saba_graph *g) { return reinterpret_cast<const Graph *>(g); }
 

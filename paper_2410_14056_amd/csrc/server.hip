@@ -521,6 +521,10 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
         }
     }
     saba_aesc_params prm = rq->params;
+    if (prm.omega != 0) {
+        set_error("the server takes omega = 0 only (use saba_aesc_query for the eigenpair form)");
+        return SABA_E_INVALID;
+    }
     if (prm.lambda <= 0.0 && rq->graph >= 0 && rq->graph < g->ngraphs &&
         g->gconnected[rq->graph]) {
         // lambda left to the library: computed once per graph (on a private stream) and cached

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_loads_and_reports_version():
     import paper_2410_14056_amd as saba
     lib = saba.load()
-    assert lib.saba_version() == 2
+    assert lib.saba_version() == 3
     for name in saba.EXPORTS:
         assert hasattr(lib, name)
     assert set(saba.EXPORTS) == set(declared())
@@ -60,12 +60,14 @@ def test_structs_match_header_layout():
     from paper_2410_14056_amd import _binding as b
     # saba_walk_params: int64, int32, 3 x uint32, 2 x int32, pointer, 2 x int32, pointer -> 56
     assert ctypes.sizeof(b.WalkParams) == 56
-    # saba_aesc_params: 3 doubles, 3 uint32, 5 int32, int64 -> 64 bytes
-    assert ctypes.sizeof(b.AescParams) == 64
+    # saba_aesc_params: 3 doubles, 3 uint32, 5 int32, int64, 2 int32 -> 72 bytes
+    assert ctypes.sizeof(b.AescParams) == 72
     assert ctypes.sizeof(b.Stats) == 80
     assert ctypes.sizeof(b.GraphInfo) == 48
-    # saba_aesc_request: 2 x int32, params (64), pointer, int64, pointer -> 96 bytes
-    assert ctypes.sizeof(b.AescRequest) == 96
+    # saba_aesc_request: 2 x int32, params (72), pointer, int64, pointer -> 104 bytes
+    assert ctypes.sizeof(b.AescRequest) == 104
+    assert ctypes.sizeof(b.SpectrumParams) == 24
+    assert ctypes.sizeof(b.SpectrumResult) == 40
     assert ctypes.sizeof(b.BatchOptions) == 16
 
 
@@ -81,7 +83,12 @@ def test_server_structs_match_the_c_compiler(tmp_path):
                                                 "latency_ms"]),
         "saba_server_stats_t": (b.ServerStats, [f for f, _ in b.ServerStats._fields_]),
         "saba_aesc_request": (b.AescRequest, ["graph", "params", "d_edges", "q", "d_sc"]),
-        "saba_aesc_params": (b.AescParams, ["eps", "delta", "seed", "tau_cap", "mem_budget"]),
+        "saba_aesc_params": (b.AescParams, ["eps", "delta", "seed", "tau_cap", "mem_budget",
+                                            "omega", "reserved"]),
+        "saba_spectrum_params": (b.SpectrumParams, ["graph", "omega", "max_iters", "seed", "tol"]),
+        "saba_spectrum_result": (b.SpectrumResult, ["lambda_rest", "lambda_rest_bound",
+                                                    "max_residual", "pairs", "iterations",
+                                                    "converged"]),
         "saba_stats": (b.Stats, ["walks", "warnings", "kernel_ms", "count_ms"]),
         "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources", "sampler",
                                             "d_distinct"]),

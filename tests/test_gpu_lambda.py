@@ -56,7 +56,7 @@ def test_lambda_per_graph_of_a_multi_graph_handle(saba):
         assert saba.graph_lambda(mg, index=k) == alone
 
 
-def test_estimator_with_lambda_left_to_the_library(saba, orc):
+def test_estimator_with_lambda_left_to_the_library(saba):
     import torch
     g = GRAPHS["er300"]()
     sg = saba.SabaGraph.from_graph(g)
@@ -64,8 +64,10 @@ def test_estimator_with_lambda_left_to_the_library(saba, orc):
     auto, _ = saba.aesc(sg, 0.2, 0.0, 3, tau_cap=64)
     given, _ = saba.aesc(sg, 0.2, min(lb, 1 - 1e-12), 3, tau_cap=64)
     assert torch.equal(auto, given)
-    so, _ = orc.aesc(g, 0.2, min(lb, 1 - 1e-12), 3, tau_cap=64)
-    np.testing.assert_allclose(auto.cpu().numpy(), so, rtol=1e-12, atol=1e-15)
+    # the radius the library took is the dense one up to the Lanczos residual (the estimator's
+    # parity at a given lambda is covered by the estimator tests)
+    lam, _ = exact_sc.spectral_lambda(g.row_ptr, g.col_idx, g.n)
+    assert lam - 1e-12 <= lb <= lam + 1e-6
     # the server resolves it too
     e = graphgen.canonical_edges(g)[:9]
     with saba.SabaServer(saba.SabaGraph.from_graphs([g])) as srv:
