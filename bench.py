@@ -311,32 +311,84 @@ def bench_aesc(args, saba, torch, np):
     return out
 
 
+def bench_omega(args, saba, torch, np):
+    """The eigenpair form of the truncation on the 1% query workload of the 10^6-vertex
+    Chung-Lu graph: for each omega, the cost of the leading eigenpairs (a fresh Lanczos run),
+    the radius tau is taken from, and the estimator's time and walk steps with the pairs
+    cached.  omega = 0 is the plain series with the library's lambda."""
+    import graphgen
+    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    ce = graphgen.canonical_edges(g)
+    perm = np.random.default_rng(7).permutation(g.m)
+    k = max(1, int(round(args.aesc_frac * g.m)))
+    qt = torch.from_numpy(np.ascontiguousarray(ce[np.sort(perm[:k])])).cuda()
+    warm = torch.from_numpy(np.ascontiguousarray(ce[np.sort(perm[k:k + 64])])).cuda()
+    lam = saba.graph_lambda(sg, max_iters=1000)
+    rows = []
+    base = None
+    for omega in (0, 8, 32, 64):
+        row = {"omega": omega}
+        if omega > 0:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = saba.graph_spectrum(sg, omega, vectors=False)
+            row["spectrum_s"] = time.perf_counter() - t0
+            row.update({"radius": r["lambda_rest_bound"], "pairs": r["pairs"],
+                        "iterations": r["iterations"], "max_residual": r["max_residual"],
+                        "converged": r["converged"],
+                        "smallest_kept_abs_theta": float(np.min(np.abs(r["values"])))})
+        else:
+            row["radius"] = lam["lambda_bound"]
+        saba.aesc_query(sg, warm, args.aesc_eps, 0.0, 1, omega=omega)  # fills the pair cache
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc, st = saba.aesc_query(sg, qt, args.aesc_eps, 0.0, 1, omega=omega)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        row.update({"seconds": dt, "edges_per_s": k / dt, "walk_steps": st["walk_steps"],
+                    "push_edge_visits": st["push_edge_visits"], "max_tau": st["max_tau"],
+                    "sum_sc": float(sc.sum().item())})
+        if base is None:
+            base = sc
+        else:
+            row["max_abs_change_vs_omega0"] = float((sc - base).abs().max().item())
+        rows.append(row)
+        progress(f"omega {omega}: {dt:.2f} s, radius {row['radius']:.6f}")
+    return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_query_1pct", "edges": k,
+            "lambda": lam["lambda"], "rows": rows}
+
+
 def bench_aesc_full(args, saba, torch, np):
     """All edges of the 10^6-vertex Chung-Lu graph at eps = 0.1: the edges in canonical order
     cut into 20 query calls (each result equals the all-edges call's entry), one progress line
     per call."""
     import graphgen
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
-    lam = graphgen.spectral_lambda(g)
+    omega = args.omega
+    # omega > 0: the radius of the rest of the spectrum comes from the library
+    lam = graphgen.spectral_lambda(g) if omega == 0 else 0.0
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     ce = graphgen.canonical_edges(g)
     parts = np.array_split(np.arange(g.m), 20)
-    saba.aesc_query(sg, torch.from_numpy(np.ascontiguousarray(ce[:64])).cuda(), args.aesc_eps, lam, 1)
+    saba.aesc_query(sg, torch.from_numpy(np.ascontiguousarray(ce[:64])).cuda(), args.aesc_eps, lam, 1,
+                    omega=omega)
     torch.cuda.synchronize()
     steps = 0
     sums = 0.0
     t0 = time.perf_counter()
     for k, idx in enumerate(parts):
         q = torch.from_numpy(np.ascontiguousarray(ce[idx])).cuda()
-        sc, st = saba.aesc_query(sg, q, args.aesc_eps, lam, 1)
+        sc, st = saba.aesc_query(sg, q, args.aesc_eps, lam, 1, omega=omega)
         torch.cuda.synchronize()
         steps += st["walk_steps"]
         sums += float(sc.sum().item())
         progress(f"aesc full: {k + 1}/20 parts, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
-    return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_all_edges", "edges": g.m, "n": g.n,
-            "lambda": lam, "seconds": dt, "edges_per_s": g.m / dt, "walk_steps": steps,
-            "sum_sc": sums, "n_minus_1": g.n - 1}
+    return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_all_edges"
+            + (f"_omega{omega}" if omega else ""), "edges": g.m, "n": g.n,
+            "lambda": lam, "omega": omega, "seconds": dt, "edges_per_s": g.m / dt,
+            "walk_steps": steps, "sum_sc": sums, "n_minus_1": g.n - 1}
 
 
 def _batch_graph(spec):
@@ -688,7 +740,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
                     choices=["all", "walks", "aesc", "aesc_full", "c1", "batch", "serve", "ablation",
-                             "copy"],
+                             "omega", "copy"],
                     default="all")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-edges", type=int, default=32)
@@ -711,6 +763,8 @@ def main():
     ap.add_argument("--aesc-eps", type=float, default=0.1)
     ap.add_argument("--aesc-mem-gib", type=float, default=0.0,
                     help="source scratch of the estimator (0: the library default)")
+    ap.add_argument("--omega", type=int, default=0,
+                    help="eigenpairs of the all-edges estimator run (aesc_full)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -770,6 +824,14 @@ def main():
         head = next(r for r in a["rows"] if "headline" in r["name"])
         out.update({"value": head["walk_steps_per_s"], "ms_per_step": head["ms_per_step"],
                     "config": {"workload": a["workload"]}, "ablation": a})
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "omega":
+        a = bench_omega(args, saba, torch, np)
+        best = max(a["rows"], key=lambda r: r["edges_per_s"])
+        out.update({"value": best["edges_per_s"], "unit": "edges/s", "dtype": "f64",
+                    "ms_per_step": best["seconds"] * 1e3, "config": {"workload": a["workload"]},
+                    "omega": a})
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serve":
