@@ -194,3 +194,25 @@ def test_chung_lu_query_matches_oracle(saba, orc):
     sq, _ = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.2, lam, 11)
     so, _ = orc.aesc(g, 0.2, lam, seed=11, query=q)
     np.testing.assert_allclose(sq.cpu().numpy(), so, rtol=RTOL, atol=1e-15)
+
+
+def test_config3_sampled_edges_match_oracle(saba, orc):
+    """The 10^6-vertex Chung-Lu graph at eps = 0.1 in the benchmark's launch configuration (the
+    1% query with the default source scratch): 24 of its edges, computed by the oracle on their
+    own, equal the GPU's entries (a query's entries do not depend on the other pairs)."""
+    import os
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+    lam = graphgen.spectral_lambda(g)
+    ce = graphgen.canonical_edges(g)
+    perm = np.random.default_rng(7).permutation(g.m)
+    k = int(round(0.01 * g.m))
+    q = np.ascontiguousarray(ce[np.sort(perm[:k])])
+    print(f"config3 sampled parity n={g.n} m={g.m} q={k}", flush=True)
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    sq, st = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.1, lam, 1)
+    pick = np.sort(np.random.default_rng(3).choice(k, 24, replace=False))
+    so, _ = orc.aesc(g, 0.1, lam, seed=1, query=q[pick], nthreads=min(16, os.cpu_count() or 1))
+    np.testing.assert_allclose(sq.cpu().numpy()[pick], so, rtol=RTOL, atol=1e-15)
+    assert st["sources"] > 0 and st["walk_steps"] > 0
+
