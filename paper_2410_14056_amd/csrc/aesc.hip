@@ -274,6 +274,17 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
+// XCD-aware block order.  The dispatcher deals the blocks of a launch round-robin over the
+// 8 XCDs, so blocks with equal blockIdx.x mod 8 share one L2.  Numbering those blocks
+// consecutively (a permutation of the block ids when the grid is a multiple of 8) makes the
+// waves of one XCD take consecutive work items, which belong to the same source.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t i = blockIdx.x, nb = gridDim.x;
+    if (nb % kXcds) return i;
+    return (i % kXcds) * (nb / kXcds) + i / kXcds;
+}
+
 __device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, int64_t len,
                                                int64_t key) {
     // largest i in [0, len) with a[i] <= key (a non-decreasing, a[0] <= key)
@@ -343,7 +354,7 @@ __device__ __forceinline__ void wave_groups(const int64_t *__restrict__ gofs, in
                                             int64_t &first, int64_t &stride, int64_t &total) {
     total = uniform64(gofs[nb]);
     stride = (int64_t)gridDim.x * kWavesPerBlock;
-    first = uniform64((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    first = uniform64(xcd_block() * kWavesPerBlock + (threadIdx.x >> 6));
 }
 
 // Push the current support one hop: set the bit of every neighbour in the next level's
@@ -414,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void expand_hub_kernel(
     const int2 *hubs = hubs_all + cur * hubcap;
     const int32_t nh = fl->nhub[cur];
     unsigned long long visits = 0;
-    for (int32_t k = blockIdx.x; k < nh; k += gridDim.x) {
+    for (int32_t k = (int32_t)xcd_block(); k < nh; k += gridDim.x) {
         const int2 hb = hubs[k];
         if (!bs[hb.x].active) continue;  // the list was made before this level's stop test
         const Slot sl = slots[hb.x];
@@ -602,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void pull_hub_kernel(
     const int32_t nh = __builtin_amdgcn_readfirstlane(fl->nhub[nxt]);
     const int32_t nwaves = (int32_t)gridDim.x * kWavesPerBlock;
     unsigned long long visits = 0;
-    for (int32_t k = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * kWavesPerBlock +
+    for (int32_t k = __builtin_amdgcn_readfirstlane((int32_t)(xcd_block() * kWavesPerBlock +
                                                               (threadIdx.x >> 6)));
          k < nh; k += nwaves) {
         const int2 hb = hubs[k];
@@ -765,8 +776,7 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const int lane = __lane_id();
     const int64_t T = coff[nle];
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); c < T;
-         c += nwaves) {
+    for (int64_t c = xcd_block() * kWavesPerBlock + (threadIdx.x >> 6); c < T; c += nwaves) {
         const int64_t le = upper_index(coff, nle + 1, c);
         const int64_t b = upper_index(eb, nb + 1, le);
         const Slot sl = slots[b];
@@ -793,11 +803,11 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
             WalkPos p = walk_pos(vrec, side ? t : sl.v);
             for (int32_t l = 1; l <= L; ++l) {
                 // the hash sees the graph's own vertex ids
-                p = walker_step_nbr<SABA_SAMPLER_KEYED>(nbr, p, (uint32_t)(p.v - sl.goff),
-                                                        (uint32_t)l, wk);
+                p = walker_step_nbr_nt<SABA_SAMPLER_KEYED>(nbr, p, (uint32_t)(p.v - sl.goff),
+                                                           (uint32_t)l, wk);
                 const int32_t xl = p.v - sl.goff;
                 if (bm[xl >> 5] & (1u << (xl & 31))) {  // h_ttau is zero off its support
-                    acc += h[xl];
+                    acc += h[xl];  // cached: the hubs' values are read again and again
                     hits += 1;
                 }
             }

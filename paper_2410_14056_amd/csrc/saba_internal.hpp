@@ -286,4 +286,16 @@ __device__ __forceinline__ WalkPos walker_step_nbr(const int4 *__restrict__ nbr,
     return WalkPos{f.x, f.y, f.z};
 }
 
+// The same step with the entry read marked non-temporal, so that the random entry stream does
+// not push data with reuse (a source's support bitmap) out of the caches.
+typedef int32_t nbr_vec4 __attribute__((ext_vector_type(4)));
+template <int SM>
+__device__ __forceinline__ WalkPos walker_step_nbr_nt(const int4 *__restrict__ nbr, WalkPos p,
+                                                      uint32_t hv, uint32_t l, Walker &w) {
+    const nbr_vec4 f = __builtin_nontemporal_load(
+        reinterpret_cast<const nbr_vec4 *>(nbr) + p.rs +
+        (int32_t)walker_choice<SM>(hv, (uint32_t)p.d, l, w));
+    return WalkPos{f.x, f.y, f.z};
+}
+
 }  // namespace saba
