@@ -30,14 +30,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and AESC edges/s at ε=0.1 (1 GPU); p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-# walk kernel: one random 64 B sector per step (the 16-byte walk entry of the next vertex) plus
-# the 4 B coalesced visit-log store
-WALK_KERNEL_BYTES_PER_STEP = 68
+# walk kernel: one random 128 B line per step (the 16-byte walk entry of the next vertex) plus
+# the 4 B coalesced visit-log store.  gfx950's L2 fetches whole 128 B lines from memory for
+# every read: the request-size counters (TCC_EA0_RDREQ_{32B,64B,128B}) show only 128 B read
+# requests, for a plain copy and for the random walk-entry reads alike.
+WALK_KERNEL_BYTES_PER_STEP = 132
+# the same step counted in 64 B sectors (the HBM3E burst), for comparison
+WALK_KERNEL_BYTES_PER_STEP_64B = 68
 # whole walk call, counted as the survey's unit: vertex record, adjacency entry and a random
 # visit-counter update per step
 WALK_STEP_BYTES = 192
-# estimator walk kernel: the walk entry of the next vertex and its support-bitmap word, one
-# random 64 B sector each, per step
+# estimator walk kernel: the 128 B line of the walk entry of the next vertex per step (the
+# support bitmaps, and the h values of frequently hit vertices, are meant to stay cached)
 AESC_STEP_BYTES = 128
 COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
@@ -171,6 +175,8 @@ def bench_walks(args, saba, torch, np):
             "kernel_ms_per_launch": k_ms / chunks,
             "launches_per_step": chunks,
             "bytes_per_step": kbytes,
+            "frac_at_64B_sectors": (WALK_KERNEL_BYTES_PER_STEP_64B * per_launch_steps /
+                                    (k_ms / chunks * 1e-3) / 1e9 / HBM_PEAK_GBS) if bouquet else None,
             "steps_per_launch": per_launch_steps,
             "random_read_ceiling": None if probe is None else {
                 "reads_per_s": probe["reads_per_s"],
