@@ -68,6 +68,13 @@ extern "C" {
                                      Murmur2(cur|l, 0), k = floor(u d / 2^32); each walk is
                                      decided by a few top bits of its seed (negative ablation) */
 
+/* Where saba_walks takes the start vertices from. */
+#define SABA_SOURCES_EXPLICIT 0 /* walk j starts at d_sources[j] */
+#define SABA_SOURCES_UNIFORM 1  /* walk j starts at pool[floor(h_j * |pool| / 2^32)], pool = the
+                                   non-isolated vertices in ascending order and
+                                   h_j = Murmur2(LE32(j mod 2^32) | LE32(j / 2^32), seed):
+                                   uniform sources drawn on the device */
+
 typedef struct saba_graph saba_graph;
 
 typedef struct {
@@ -104,9 +111,10 @@ typedef struct {
     uint32_t spread;         /* S: bit offset of the lane index inside key_lo; G << S <= 2^32 */
     int32_t mode;            /* SABA_WALK_NAIVE or SABA_WALK_BOUQUET */
     int32_t time_kernels;    /* nonzero: fill saba_stats kernel_ms / total_ms (synchronises) */
-    const int32_t *d_sources; /* [n_walks] start vertex of each walk (device) */
+    const int32_t *d_sources; /* [n_walks] start vertex of each walk (device); read only with
+                                SABA_SOURCES_EXPLICIT */
     int32_t sampler;         /* SABA_SAMPLER_* (0: keyed Eq. (5)) */
-    int32_t reserved;
+    int32_t source_mode;     /* SABA_SOURCES_EXPLICIT (0) or SABA_SOURCES_UNIFORM */
     int64_t *d_distinct;     /* NULL, or [9] int64 (device): branching statistics (the Table 5
                                 experiment).  The walks are cut into consecutive vectors of 8
                                 in the order the mode runs them (naive: the order of
@@ -360,11 +368,12 @@ int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
 /*
  * Random-walk generation (Alg. 2 / Alg. 3, neighbour choice of Eq. (5), bouquet
  * arrangement of Sec. 3.3), the synthetic benchmark of Sec. 5.4.
- *   Walk j starts at d_sources[j] (which must not be isolated).  The walks that
- *   start at a vertex s are numbered r = 0, 1, ... in the order of d_sources and
- *   walk r of s draws its choices from the key of address (s, 0, 0) and index r
- *   under (seed, G, S) with the chosen sampler, so the histograms depend only on
- *   the multiset of sources.
+ *   Walk j starts at d_sources[j] (which must not be isolated), or, with
+ *   SABA_SOURCES_UNIFORM, at the j-th hashed draw from the non-isolated vertices
+ *   (SABA_E_INVALID if the graph has none).  The walks that start at a vertex s are
+ *   numbered r = 0, 1, ... in the order of j and walk r of s draws its choices from
+ *   the key of address (s, 0, 0) and index r under (seed, G, S) with the chosen
+ *   sampler, so the histograms depend only on the multiset of sources.
  *   d_endpoint[n] (int64): walks ending at each vertex after L steps.
  *   d_visits[n] (int64): visits at positions 1..L.
  *   Both outputs are overwritten (the library clears them on `stream`).

@@ -55,6 +55,8 @@ def lib():
         L.orc_walks_histogram.restype = i32
         L.orc_distinct8.argtypes = [P, P, i32, P, i64, i32, u32, u32, u32, i32, i32, P]
         L.orc_distinct8.restype = i32
+        L.orc_uniform_sources.argtypes = [P, i32, i64, u32, P]
+        L.orc_uniform_sources.restype = i32
         L.orc_xorshift32.argtypes = [u32]
         L.orc_xorshift32.restype = u32
         L.orc_aesc.argtypes = [P, P, i32, f64, f64, f64, u32, u32, u32, i32, i32, i32, P, i64, P,
@@ -126,6 +128,15 @@ def walks_histogram(g, sources, L, seed, G=1, S=0, nthreads=0, sampler=SAMPLER_K
     if rc != 0:
         raise ValueError(f"orc_walks_histogram failed ({rc})")
     return ep, vi
+
+
+def uniform_sources(g, n_walks, seed):
+    """Hashed uniform start vertices over the non-isolated vertices (int32[n_walks])."""
+    out = np.zeros(int(n_walks), dtype=np.int32)
+    rc = lib().orc_uniform_sources(_p(g.row_ptr), g.n, int(n_walks), seed & 0xFFFFFFFF, _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_uniform_sources failed ({rc})")
+    return out
 
 
 def distinct8(g, sources, L, seed, G=1, S=0, sampler=SAMPLER_KEYED, order=1):

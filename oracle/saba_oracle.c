@@ -95,6 +95,35 @@ void orc_hash2_batch(const uint32_t *a, const uint32_t *b, int64_t n, uint32_t s
     }
 }
 
+/* Uniform start vertices (the benchmark's "uniform random sources", drawn by the hash so that
+ * both sides can reproduce them): the pool is the vertices with at least one edge, in
+ * ascending order; walk j starts at pool[floor(h * |pool| / 2^32)] with h the Murmur2 of the
+ * 64-bit walk number j as two little-endian words (low word first) under the walk seed.
+ * Returns -1 if the pool is empty and n_walks > 0. */
+int32_t orc_uniform_sources(const int32_t *row_ptr, int32_t n, int64_t n_walks, uint32_t seed,
+                            int32_t *out)
+{
+    int64_t np = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] > row_ptr[v]) ++np;
+    if (np == 0) return n_walks > 0 ? -1 : 0;
+    int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
+    if (!pool) return -2;
+    int64_t k = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] > row_ptr[v]) pool[k++] = v;
+    for (int64_t j = 0; j < n_walks; ++j) {
+        uint32_t w[2];
+        w[0] = (uint32_t)((uint64_t)j & 0xffffffffu);
+        w[1] = (uint32_t)((uint64_t)j >> 32);
+        const uint64_t h = orc_hash_words(w, 2, seed);
+        /* floor(h * np / 2^32) with h < 2^32 and np < 2^31: below np, no overflow */
+        out[j] = pool[(int64_t)((h * (uint64_t)np) >> 32)];
+    }
+    free(pool);
+    return 0;
+}
+
 /* Eq. (5): scale the hashed value to [0, d) without a modulo. */
 uint32_t orc_choice(uint32_t u, uint32_t d)
 {

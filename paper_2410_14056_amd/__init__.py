@@ -9,6 +9,8 @@ from ._binding import (  # noqa: F401
     SABA_SAMPLER_KEYED_MOD,
     SABA_SAMPLER_LITERAL,
     SABA_SAMPLER_STREAM_MOD,
+    SABA_SOURCES_EXPLICIT,
+    SABA_SOURCES_UNIFORM,
     SABA_WALK_BOUQUET,
     SABA_WALK_NAIVE,
     SabaError,

@@ -24,6 +24,7 @@ SABA_SAMPLER_KEYED = 0
 SABA_SAMPLER_KEYED_MOD = 1
 SABA_SAMPLER_STREAM_MOD = 2
 SABA_SAMPLER_LITERAL = 3
+SABA_SOURCES_EXPLICIT, SABA_SOURCES_UNIFORM = 0, 1
 
 _ERRORS = {
     -1: "SABA_E_INVALID", -2: "SABA_E_NOMEM", -3: "SABA_E_HIP", -4: "SABA_E_GRAPH",
@@ -65,7 +66,7 @@ class WalkParams(ctypes.Structure):
     _fields_ = [("n_walks", ctypes.c_int64), ("length", ctypes.c_int32), ("seed", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("spread", ctypes.c_uint32), ("mode", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("d_sources", ctypes.c_void_p),
-                ("sampler", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sampler", ctypes.c_int32), ("source_mode", ctypes.c_int32),
                 ("d_distinct", ctypes.c_void_p)]
 
 
@@ -308,22 +309,27 @@ class WalkResult:
     distinct: torch.Tensor | None = None
 
 
-def walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int, group: int = 1,
+def walks(graph: SabaGraph, sources: torch.Tensor | None, length: int, seed: int, group: int = 1,
           spread: int = 0, mode: int = SABA_WALK_BOUQUET, time_kernels: bool = False,
           endpoint: torch.Tensor | None = None, visits: torch.Tensor | None = None,
           stream=None, sampler: int = SABA_SAMPLER_KEYED,
-          distinct: bool = False) -> WalkResult:
+          distinct: bool = False, n_walks: int | None = None) -> WalkResult:
     """saba_walks: endpoint / visit histograms of the walks started at `sources` (int32,
-    device); with distinct=True also the branching statistics (int64 [9])."""
-    assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
-    dev = sources.device
+    device), or, with sources=None, of n_walks walks from uniform sources the library draws
+    (SABA_SOURCES_UNIFORM); with distinct=True also the branching statistics (int64 [9])."""
+    if sources is None:
+        assert n_walks is not None and n_walks >= 0
+        nw, sptr, smode, dev = int(n_walks), None, SABA_SOURCES_UNIFORM, torch.device("cuda")
+    else:
+        assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
+        nw, sptr, smode, dev = sources.numel(), sources.data_ptr(), SABA_SOURCES_EXPLICIT, sources.device
     if endpoint is None:
         endpoint = torch.empty(graph.n, dtype=torch.int64, device=dev)
     if visits is None:
         visits = torch.empty(graph.n, dtype=torch.int64, device=dev)
     dist = torch.empty(9, dtype=torch.int64, device=dev) if distinct else None
-    p = WalkParams(sources.numel(), int(length), seed & 0xFFFFFFFF, int(group), int(spread),
-                   int(mode), int(bool(time_kernels)), sources.data_ptr(), int(sampler), 0,
+    p = WalkParams(nw, int(length), seed & 0xFFFFFFFF, int(group), int(spread),
+                   int(mode), int(bool(time_kernels)), sptr, int(sampler), smode,
                    None if dist is None else dist.data_ptr())
     st = Stats()
     _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),

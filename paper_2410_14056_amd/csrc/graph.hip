@@ -267,6 +267,7 @@ static void destroy_graph(Graph *g) {
     if (g->slotv) (void)hipFree(g->slotv);
     if (g->hubbm) (void)hipFree(g->hubbm);
     if (g->nbr) (void)hipFree(g->nbr);
+    if (g->pool) (void)hipFree(g->pool);
     for (auto &b : g->walk_scratch) b.release();
     g->est.release();
     for (auto &sp : g->spectra) sp->dev.release();

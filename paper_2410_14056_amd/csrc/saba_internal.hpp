@@ -95,6 +95,11 @@ struct Graph {
     // lambda of each graph computed on the device for requests that leave it to the library
     std::mutex lam_mu;
     std::vector<double> glambda;
+    // the non-isolated vertices in ascending order (device), built on first use by the uniform
+    // source mode of the walks
+    std::mutex pool_mu;
+    int32_t *pool = nullptr;
+    int64_t npool = -1;
     // leading eigenpairs of graphs the estimator was asked to correct with (omega > 0)
     std::mutex spec_mu;
     std::vector<std::unique_ptr<struct Spectrum>> spectra;

@@ -506,6 +506,35 @@ static void launch_log_sm(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s
 #undef SABA_LOG_LAUNCH
 }
 
+// Uniform sources: walk j starts at pool[floor(h_j npool / 2^32)] with
+// h_j = Murmur2(LE32(j mod 2^32) | LE32(j / 2^32), seed).
+__global__ void uniform_sources_kernel(const int32_t *__restrict__ pool, int64_t npool,
+                                       uint32_t seed, int64_t W, int32_t *__restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < W;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = hash_w2((uint32_t)j, (uint32_t)((uint64_t)j >> 32), seed);
+        out[j] = pool[(int64_t)(((uint64_t)h * (uint64_t)npool) >> 32)];
+    }
+}
+
+// The pool of the uniform source mode, built once per handle from the host copy of the CSR.
+static int ensure_pool(Graph *g, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    if (g->npool >= 0) return SABA_OK;
+    std::vector<int32_t> pool;
+    const int32_t *rp = g->h_row_ptr.data();
+    for (int32_t v = 0; v < g->n; ++v)
+        if (rp[v + 1] > rp[v]) pool.push_back(v);
+    if (!pool.empty()) {
+        SABA_HIP_TRY(hipMalloc(&g->pool, sizeof(int32_t) * pool.size()));
+        SABA_HIP_TRY(hipMemcpyAsync(g->pool, pool.data(), sizeof(int32_t) * pool.size(),
+                                    hipMemcpyHostToDevice, s));
+        SABA_HIP_TRY(hipStreamSynchronize(s));
+    }
+    g->npool = (int64_t)pool.size();
+    return SABA_OK;
+}
+
 static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                       int64_t *d_visits, saba_stats *st, hipStream_t s) {
     const int64_t W = p->n_walks;
@@ -513,7 +542,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     const int32_t L = p->length;
     if (W < 0 || L < 0 || p->group < 1 || p->spread > 31 ||
         (p->group > 1 && ((uint64_t)(p->group - 1) << p->spread) > 0xFFFFFFFFull) ||
-        (W > 0 && !p->d_sources) || !d_endpoint || !d_visits ||
+        (p->source_mode != SABA_SOURCES_EXPLICIT && p->source_mode != SABA_SOURCES_UNIFORM) ||
+        (W > 0 && p->source_mode == SABA_SOURCES_EXPLICIT && !p->d_sources) || !d_endpoint ||
+        !d_visits ||
         (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET) || p->sampler < 0 ||
         p->sampler > SABA_SAMPLER_LITERAL ||
         (p->mode == SABA_WALK_NAIVE && W >= ((int64_t)1 << 31))) {
@@ -529,6 +560,24 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     if (timing)
         for (auto &e : ev.e) SABA_HIP_TRY(hipEventCreate(&e));
     if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[0], s));
+
+    saba_walk_params drawn;
+    if (W > 0 && p->source_mode == SABA_SOURCES_UNIFORM) {
+        SABA_TRY(ensure_pool(g, s));
+        if (g->npool == 0) {
+            set_error("uniform sources need a vertex with an edge");
+            return SABA_E_INVALID;
+        }
+        SABA_TRY(g->walk_scratch[7].ensure(sizeof(int32_t) * (size_t)W));
+        int32_t *src = g->walk_scratch[7].as<int32_t>();
+        uniform_sources_kernel<<<(unsigned)std::min<int64_t>((W + 255) / 256, 1 << 16), 256, 0, s>>>(
+            g->pool, g->npool, p->seed, W, src);
+        SABA_HIP_TRY(hipGetLastError());
+        drawn = *p;
+        drawn.d_sources = src;
+        drawn.source_mode = SABA_SOURCES_EXPLICIT;
+        p = &drawn;
+    }
 
     SABA_TRY(g->walk_scratch[3].ensure(sizeof(int32_t)));
     int32_t *err = g->walk_scratch[3].as<int32_t>();

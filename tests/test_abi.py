@@ -91,7 +91,7 @@ def test_server_structs_match_the_c_compiler(tmp_path):
                                                     "converged"]),
         "saba_stats": (b.Stats, ["walks", "warnings", "kernel_ms", "count_ms"]),
         "saba_walk_params": (b.WalkParams, ["n_walks", "length", "mode", "d_sources", "sampler",
-                                            "d_distinct"]),
+                                            "source_mode", "d_distinct"]),
         "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
         "saba_lambda_params": (b.LambdaParams, ["graph", "max_iters", "tol", "seed"]),
         "saba_exec_config": (b.ExecConfig, ["walks_per_lane", "walk_blocks", "est_walk_blocks",

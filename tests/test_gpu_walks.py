@@ -47,6 +47,44 @@ def test_walks_match_oracle(saba, orc, gname, L, G, S):
         assert np.array_equal(vi, vi_o), mode
 
 
+@pytest.mark.parametrize("gname", ["er", "rmat12"])
+@pytest.mark.parametrize("G,S", [(1, 0), (64, 20)])
+def test_uniform_sources_on_the_device_match_oracle(saba, orc, gname, G, S):
+    """SABA_SOURCES_UNIFORM: the library draws the start vertices itself; the histograms equal
+    the oracle's for the oracle's own draw (rmat12 has isolated vertices, which are skipped)."""
+    g = GRAPHS[gname]()
+    sg = saba.SabaGraph.from_graph(g)
+    W, L, seed = 100003, 9, 21
+    print(f"uniform sources graph={gname} W={W} G={G}", flush=True)
+    ep_o, vi_o = orc.walks_histogram(g, orc.uniform_sources(g, W, seed), L, seed=seed, G=G, S=S)
+    for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+        r = saba.walks(sg, None, L, seed, group=G, spread=S, mode=mode, n_walks=W)
+        assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), mode
+        assert np.array_equal(r.visits.cpu().numpy(), vi_o), mode
+    r = saba.walks(sg, None, 0, seed, n_walks=W)  # L = 0: the start vertices themselves
+    assert np.array_equal(r.endpoint.cpu().numpy(),
+                          np.bincount(orc.uniform_sources(g, W, seed), minlength=g.n))
+
+
+def test_uniform_sources_errors(saba):
+    import ctypes
+    from paper_2410_14056_amd import _binding as b
+    empty = saba.SabaGraph.from_graph(graphgen.from_edges([], 3))
+    r = saba.walks(empty, None, 4, 1, n_walks=0)
+    assert r.endpoint.sum().item() == 0
+    with pytest.raises(saba.SabaError) as ei:
+        saba.walks(empty, None, 4, 1, n_walks=5)
+    assert ei.value.name == "SABA_E_INVALID"
+    import torch
+    sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
+    ep = torch.empty(sg.n, dtype=torch.int64, device="cuda")
+    vi = torch.empty(sg.n, dtype=torch.int64, device="cuda")
+    p = b.WalkParams(10, 3, 1, 1, 0, saba.SABA_WALK_BOUQUET, 0, None, 0, 2, None)  # mode 2
+    rc = b.load().saba_walks(sg.handle, ctypes.byref(p), b._ptr(ep), b._ptr(vi), None,
+                             b._stream_ptr())
+    assert rc == -1  # SABA_E_INVALID
+
+
 def test_walks_empty_and_invalid(saba):
     import torch
     g = graphgen.from_edges([(0, 1), (1, 2)], 4)  # vertex 3 isolated
