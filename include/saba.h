@@ -350,6 +350,17 @@ int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec
                         void *stream);
 
 /*
+ * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
+ * which may be NULL) under each candidate grid (1024, 2048, 4096 or 8192 blocks for the
+ * walk-pair kernel x 1024, 2048 or 4096 blocks for the frontier-group kernels), times whole
+ * calls with HIP events, keeps the fastest in the handle and returns it in *best (may be
+ * NULL).  The knobs do not change results; the sample's outputs hold its results on return.
+ * Errors: those of saba_aesc_batch, SABA_E_INVALID for an empty sample.
+ */
+int saba_autotune_aesc(saba_graph *g, const saba_aesc_request *sample, int32_t nreq,
+                       const saba_batch_options *opt, saba_exec_config *best, void *stream);
+
+/*
  * Diagnostic: dependent random 16-byte reads per second on this GPU, the access pattern of a
  * walk step (every lane of 8192 x 256 follows its own chain of `steps` reads at hashed positions
  * of a buffer of 2^log2_records aligned 16-byte records, 10 <= log2_records <= 30).  It gives

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     aesc_batch,
     aesc_edge_stats,
     aesc_query,
+    autotune_aesc,
     autotune_walks,
     get_config,
     set_config,

@@ -164,7 +164,7 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
-           "saba_probe_random_reads", "saba_graph_spectrum"]
+           "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc"]
 
 _lib = None
 
@@ -199,6 +199,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_graph_get_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_graph_set_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
+    L.saba_autotune_aesc.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions),
+                                     ctypes.POINTER(ExecConfig), P]
     L.saba_graph_spectrum.argtypes = [P, ctypes.POINTER(SpectrumParams), P, P,
                                       ctypes.POINTER(SpectrumResult), P]
     L.saba_probe_random_reads.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double),
@@ -468,6 +470,30 @@ def aesc_batch(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: i
     m (edge count of the graph, needed for all-edges requests) and the estimator keywords of
     aesc().  Returns (list of result tensors, stats)."""
     lib = load()
+    arr, outs, keep = _batch_requests(requests, device)
+    opt = BatchOptions(int(mem_budget), int(batch_sources), int(bool(time_kernels)))
+    st = Stats()
+    _check(lib.saba_aesc_batch(graph.handle, ctypes.cast(arr, ctypes.c_void_p), len(requests),
+                               ctypes.byref(opt), ctypes.byref(st), _stream_ptr(stream)))
+    return outs, st.as_dict()
+
+
+def autotune_aesc(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: int = 0,
+                  device="cuda", stream=None) -> dict:
+    """saba_autotune_aesc: times the estimator on the sample `requests` (as for aesc_batch)
+    under each candidate grid, keeps the fastest in the handle and returns it."""
+    arr, outs, keep = _batch_requests(requests, device)
+    opt = BatchOptions(int(mem_budget), int(batch_sources), 1)
+    c = ExecConfig()
+    _check(load().saba_autotune_aesc(graph.handle, ctypes.cast(arr, ctypes.c_void_p),
+                                     len(requests), ctypes.byref(opt), ctypes.byref(c),
+                                     _stream_ptr(stream)))
+    return c.as_dict()
+
+
+def _batch_requests(requests, device):
+    """The AescRequest array of aesc_batch's request dicts, the result tensors and the edge
+    tensors that must stay alive during the call."""
     arr = (AescRequest * max(1, len(requests)))()
     outs = []
     keep = []
@@ -491,11 +517,7 @@ def aesc_batch(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: i
         arr[i].q = q
         arr[i].d_sc = out.data_ptr() if out.numel() else None
         outs.append(out)
-    opt = BatchOptions(int(mem_budget), int(batch_sources), int(bool(time_kernels)))
-    st = Stats()
-    _check(lib.saba_aesc_batch(graph.handle, ctypes.cast(arr, ctypes.c_void_p), len(requests),
-                               ctypes.byref(opt), ctypes.byref(st), _stream_ptr(stream)))
-    return outs, st.as_dict()
+    return arr, outs, keep
 
 
 class SabaServer:

@@ -1641,3 +1641,46 @@ extern "C" int saba_aesc_batch(saba_graph *gh, const saba_aesc_request *reqs, in
     }
     return aesc_run(G(gh), rs, o, nullptr, st, static_cast<hipStream_t>(stream));
 }
+
+extern "C" int saba_autotune_aesc(saba_graph *gh, const saba_aesc_request *sample, int32_t nreq,
+                                  const saba_batch_options *opt, saba_exec_config *best,
+                                  void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (nreq < 1 || !sample) {
+        set_error("the autotuner needs a sample of at least one request");
+        return SABA_E_INVALID;
+    }
+    Graph *g = G(gh);
+    saba_batch_options o{};
+    if (opt) o = *opt;
+    o.time_kernels = 1;
+    const saba_exec_config saved = g->cfg;
+    saba_exec_config pick = saved;
+    double best_ms = 1e300;
+    const int walk_blocks[] = {1024, 2048, 4096, 8192};
+    const int push_blocks[] = {1024, 2048, 4096};
+    for (int wb : walk_blocks)
+        for (int pb : push_blocks) {
+            g->cfg = saved;
+            g->cfg.est_walk_blocks = wb;
+            g->cfg.est_push_blocks = pb;
+            double ms = 0.0;
+            for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                saba_stats st{};
+                const int rc = saba_aesc_batch(gh, sample, nreq, &o, &st, stream);
+                if (rc != SABA_OK) {
+                    g->cfg = saved;
+                    return rc;
+                }
+                if (rep > 0) ms += st.total_ms;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                pick = g->cfg;
+            }
+        }
+    g->cfg = pick;
+    if (best) *best = pick;
+    return SABA_OK;
+}

@@ -50,6 +50,28 @@ def test_estimator_knobs_do_not_change_results(saba):
         assert torch.equal(sc, ref), (wb, pb)
 
 
+def test_estimator_autotuner(saba):
+    """saba_autotune_aesc picks a candidate grid, keeps it in the handle, and the sample's
+    outputs and later results equal the untuned ones."""
+    import torch
+    gs = [graphgen.largest_component(graphgen.er_gnm(800, 3200, 2)),
+          graphgen.largest_component(graphgen.chung_lu(2000, 8, 2.3, 3))]
+    mg = saba.SabaGraph.from_graphs(gs)
+    lams = [graphgen.spectral_lambda(g) for g in gs]
+    reqs = [dict(graph=k, eps=0.25, lam=lams[k], seed=5, m=g.m) for k, g in enumerate(gs)]
+    ref, _ = saba.aesc_batch(mg, reqs)
+    best = saba.autotune_aesc(mg, reqs)
+    assert best["est_walk_blocks"] in (1024, 2048, 4096, 8192)
+    assert best["est_push_blocks"] in (1024, 2048, 4096)
+    assert saba.get_config(mg) == best
+    out, _ = saba.aesc_batch(mg, reqs)
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+    with pytest.raises(saba.SabaError) as ei:
+        saba.autotune_aesc(mg, [])
+    assert ei.value.name == "SABA_E_INVALID"
+
+
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
     for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20}):
