@@ -218,7 +218,7 @@ typedef struct {
     int32_t walks_per_lane;  /* walks stepped side by side per lane in the bouquet walk kernel:
                                 1, 2 or 4 (0: 1) */
     int32_t walk_blocks;     /* blocks of the persistent bouquet walk kernel (0: 8192) */
-    int32_t est_walk_blocks; /* blocks of the estimator's walk-pair kernel (0: 2048) */
+    int32_t est_walk_blocks; /* blocks of the estimator's walk-pair kernel (0: 1024) */
     int32_t est_push_blocks; /* blocks of the estimator's frontier kernels (0: 2048) */
 } saba_exec_config;
 
@@ -351,8 +351,8 @@ int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec
 
 /*
  * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
- * which may be NULL) under each candidate grid (1024, 2048, 4096 or 8192 blocks for the
- * walk-pair kernel x 1024, 2048 or 4096 blocks for the frontier-group kernels), times whole
+ * which may be NULL) under each candidate grid (512, 1024, 2048 or 4096 blocks for the
+ * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels), times whole
  * calls with HIP events, keeps the fastest in the handle and returns it in *best (may be
  * NULL).  The knobs do not change results; the sample's outputs hold its results on return.
  * Errors: those of saba_aesc_batch, SABA_E_INVALID for an empty sample.

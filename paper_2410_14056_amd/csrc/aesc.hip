@@ -49,7 +49,7 @@ namespace saba {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kChunk = 64;  // walks per wavefront chunk
-constexpr int kWalkGrid = 2048;
+constexpr int kWalkGrid = 1024;
 
 struct BatchState {  // one per slot; [2] entries are indexed by level parity
     int32_t active;
@@ -1658,8 +1658,8 @@ extern "C" int saba_autotune_aesc(saba_graph *gh, const saba_aesc_request *sampl
     const saba_exec_config saved = g->cfg;
     saba_exec_config pick = saved;
     double best_ms = 1e300;
-    const int walk_blocks[] = {1024, 2048, 4096, 8192};
-    const int push_blocks[] = {1024, 2048, 4096};
+    const int walk_blocks[] = {512, 1024, 2048, 4096};
+    const int push_blocks[] = {1024, 2048, 4096, 8192};
     for (int wb : walk_blocks)
         for (int pb : push_blocks) {
             g->cfg = saved;

@@ -61,8 +61,8 @@ def test_estimator_autotuner(saba):
     reqs = [dict(graph=k, eps=0.25, lam=lams[k], seed=5, m=g.m) for k, g in enumerate(gs)]
     ref, _ = saba.aesc_batch(mg, reqs)
     best = saba.autotune_aesc(mg, reqs)
-    assert best["est_walk_blocks"] in (1024, 2048, 4096, 8192)
-    assert best["est_push_blocks"] in (1024, 2048, 4096)
+    assert best["est_walk_blocks"] in (512, 1024, 2048, 4096)
+    assert best["est_push_blocks"] in (1024, 2048, 4096, 8192)
     assert saba.get_config(mg) == best
     out, _ = saba.aesc_batch(mg, reqs)
     for a, b in zip(out, ref):
