@@ -420,8 +420,9 @@ int saba_aesc_query(saba_graph *g, const saba_aesc_params *p, const int32_t *d_e
  *   d_nreq[nnz] int64: walk pairs; d_D[nnz] double: deterministic part
  *   sum_{l <= min(ttau, tau)} (h_l(s) - h_l(t)); d_MC[nnz] double: sum over pairs of the
  *   walk statistic; d_vis0 / d_vis1[nnz] int64: walk positions of the walks from s / t
- *   that land where h_ttau is nonzero; d_g[nnz] double: directed estimate g(s, t).
- *   d_sc[m] as in saba_aesc (may be NULL).
+ *   that land where h_ttau is nonzero; d_g[nnz] double: directed estimate g(s, t) of the
+ *   truncated series (without the eigenpair tail of omega > 0).
+ *   d_sc[m] as in saba_aesc (may be NULL); it includes the tail when omega > 0.
  */
 int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc, int32_t *d_tau,
                          int32_t *d_ttau, int64_t *d_nreq, double *d_D, double *d_MC,
