@@ -370,8 +370,26 @@ def bench_omega(args, saba, torch, np):
             row["max_abs_change_vs_omega0"] = float((sc - base).abs().max().item())
         rows.append(row)
         progress(f"omega {omega}: {dt:.2f} s, radius {row['radius']:.6f}")
+    # the paper's grouping (SABA, G = 64, S = 20) on the same query: the walks of a group
+    # share their path until their choices split, so a wavefront's reads coalesce; the eps
+    # guarantee is then empirical
+    grouped = []
+    for omega in (0, 64):
+        saba.aesc_query(sg, warm, args.aesc_eps, 0.0, 1, omega=omega, group=64, spread=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc, st = saba.aesc_query(sg, qt, args.aesc_eps, 0.0, 1, omega=omega, group=64, spread=20,
+                                 time_kernels=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        grouped.append({"omega": omega, "group": 64, "spread": 20, "seconds": dt,
+                        "edges_per_s": k / dt, "walk_steps": st["walk_steps"],
+                        "walk_kernel_ms": st["kernel_ms"],
+                        "max_abs_change_vs_omega0_G1": float((sc - base).abs().max().item()),
+                        "mean_abs_change_vs_omega0_G1": float((sc - base).abs().mean().item())})
+        progress(f"omega {omega}, G 64: {dt:.2f} s")
     return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_query_1pct", "edges": k,
-            "lambda": lam["lambda"], "rows": rows}
+            "lambda": lam["lambda"], "rows": rows, "grouped": grouped}
 
 
 def bench_aesc_full(args, saba, torch, np):
