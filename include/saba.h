@@ -370,6 +370,14 @@ int saba_autotune_aesc(saba_graph *g, const saba_aesc_request *sample, int32_t n
 int saba_probe_random_reads(int32_t log2_records, int32_t steps, double *reads_per_s, double *ms,
                             void *stream);
 
+/*
+ * Failure injection, for callers that test their own error handling: with n > 0, the n-th
+ * scratch allocation the library makes from now on fails with SABA_E_NOMEM, as a real
+ * out-of-memory would (n = 0 disarms it).  Process-wide.  A call that fails this way leaves
+ * every handle usable: the next call on it computes the same results as if nothing had failed.
+ */
+int saba_debug_fail_allocation(int32_t n);
+
 /* Free every resource of a handle.  NULL is accepted.  Synchronises the device. */
 int saba_graph_destroy(saba_graph *g);
 

@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401
     aesc_query,
     autotune_aesc,
     autotune_walks,
+    fail_allocation,
     get_config,
     set_config,
     graph_lambda,

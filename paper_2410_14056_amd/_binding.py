@@ -164,7 +164,8 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_aesc_edge_stats", "saba_aesc_batch", "saba_server_create", "saba_server_submit",
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
-           "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc"]
+           "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc",
+           "saba_debug_fail_allocation"]
 
 _lib = None
 
@@ -201,6 +202,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
     L.saba_autotune_aesc.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions),
                                      ctypes.POINTER(ExecConfig), P]
+    L.saba_debug_fail_allocation.argtypes = [i32]
     L.saba_graph_spectrum.argtypes = [P, ctypes.POINTER(SpectrumParams), P, P,
                                       ctypes.POINTER(SpectrumResult), P]
     L.saba_probe_random_reads.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double),
@@ -407,6 +409,11 @@ def graph_spectrum(graph: SabaGraph, omega: int, index: int = 0, max_iters: int 
     d["values"] = np.array(vals[:max(int(omega), 0)], dtype=np.float64)
     d["vectors"] = vec
     return d
+
+
+def fail_allocation(n: int):
+    """saba_debug_fail_allocation: the n-th scratch allocation from now on fails (0 disarms)."""
+    _check(load().saba_debug_fail_allocation(int(n)))
 
 
 def _aesc_params(eps, lam, seed, delta=0.01, group=1, spread=0, tau_cap=0, tilde_tau_max=-1,

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -17,10 +18,21 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
+// Failure injection for tests of the error paths: when positive, the allocation that brings
+// the count down to zero fails as an out-of-memory would.
+static std::atomic<int64_t> g_fail_alloc{0};
+
 int DevBuf::ensure(size_t want) {
     if (want <= bytes && ptr) return SABA_OK;
     const size_t grown = bytes + bytes / 4;
     release();
+    int64_t c = g_fail_alloc.load(std::memory_order_relaxed);
+    while (c > 0 && !g_fail_alloc.compare_exchange_weak(c, c - 1, std::memory_order_relaxed)) {
+    }
+    if (c == 1) {
+        set_error("injected allocation failure");
+        return SABA_E_NOMEM;
+    }
     size_t sz = std::max<size_t>(std::max(want, grown), 256);
     hipError_t e = hipMalloc(&ptr, sz);
     if (e != hipSuccess) {
@@ -279,6 +291,16 @@ static void destroy_graph(Graph *g) {
 using namespace saba;
 
 extern "C" int saba_version(void) { return SABA_ABI_VERSION; }
+
+extern "C" int saba_debug_fail_allocation(int32_t n) {
+    clear_error();
+    if (n < 0) {
+        set_error("n must be >= 0");
+        return SABA_E_INVALID;
+    }
+    g_fail_alloc.store(n, std::memory_order_relaxed);
+    return SABA_OK;
+}
 
 extern "C" const char *saba_last_error(void) { return g_last_error.c_str(); }
 

@@ -72,6 +72,26 @@ def test_estimator_autotuner(saba):
     assert ei.value.name == "SABA_E_INVALID"
 
 
+def test_results_do_not_depend_on_the_stream(saba):
+    """Walks and estimates issued on a side stream (default priority) equal those on the
+    current stream, bit for bit."""
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(3000, 8, 2.3, 7))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    src = torch.from_numpy(graphgen.uniform_sources(g, 50000, 2)).cuda()
+    r0 = saba.walks(sg, src, 11, 3)
+    a0, _ = saba.aesc(sg, 0.25, lam, 3)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r1 = saba.walks(sg, src, 11, 3, stream=side)
+        a1, _ = saba.aesc(sg, 0.25, lam, 3, stream=side)
+    side.synchronize()
+    assert torch.equal(r0.endpoint, r1.endpoint) and torch.equal(r0.visits, r1.visits)
+    assert torch.equal(a0, a1)
+
+
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
     for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20}):

@@ -126,3 +126,23 @@ def test_distinct8_special_cases(orc):
     assert h[1] == 8 and h.sum() == 8
     # walks of L = 0 have no positions to count
     assert orc.distinct8(g, np.zeros(64, dtype=np.int32), 0, 1).sum() == 0
+
+
+@pytest.mark.parametrize("beta", [4, 16, 100])
+def test_distinct_count_follows_the_expected_distinct_items(orc, beta):
+    """Sec. 5.5 (limitations): alpha independent choices among beta neighbours hold
+    beta (1 - (1 - 1/beta)^alpha) distinct vertices on average.  The branching counter at the
+    first step of independent walks (alpha = 8, one vector per 8 walks of a star's centre)
+    follows it within a CLT bound; grouped walks (G = 64) fall far below it."""
+    g = graphgen.from_edges([(0, i) for i in range(1, beta + 1)], beta + 1)
+    W = 8 * 20000
+    src = np.zeros(W, dtype=np.int32)
+    h = orc.distinct8(g, src, 1, 13, order=1)
+    k = np.arange(9)
+    n = h.sum()
+    mean = (h * k).sum() / n
+    sd = np.sqrt((h * (k - mean) ** 2).sum() / n)
+    expect = beta * (1 - (1 - 1 / beta) ** 8)
+    assert abs(mean - expect) < 5 * sd / np.sqrt(n), (mean, expect)
+    hg = orc.distinct8(g, src, 1, 13, G=64, S=20, order=1)
+    assert (hg * k).sum() / hg.sum() < 0.5 * expect + 0.5
