@@ -147,7 +147,11 @@ typedef struct {
                               the estimate, and takes tau from the radius of the rest of the
                               spectrum: lambda > 0 is then that radius, given by the caller,
                               and lambda <= 0 leaves it to the library (lambda_rest_bound).
-                              Not accepted by the server. */
+                              The pairs stay cached in the handle until it is destroyed
+                              (16 omega n bytes per graph and omega; the first request of
+                              a (graph, omega) also needs the Lanczos basis for the
+                              duration of the call, as saba_graph_spectrum).  Not accepted
+                              by the server. */
     int32_t reserved;      /* 0 */
 } saba_aesc_params;
 
