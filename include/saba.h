@@ -150,8 +150,7 @@ typedef struct {
                               The pairs stay cached in the handle until it is destroyed
                               (16 omega n bytes per graph and omega; the first request of
                               a (graph, omega) also needs the Lanczos basis for the
-                              duration of the call, as saba_graph_spectrum).  Not accepted
-                              by the server. */
+                              duration of the call, as saba_graph_spectrum). */
     int32_t reserved;      /* 0 */
 } saba_aesc_params;
 

@@ -898,25 +898,6 @@ __global__ void finalize_pairs_kernel(const int64_t *__restrict__ pairs, int64_t
         sc[j] = g[pairs[2 * j]] + g[pairs[2 * j + 1]];
 }
 
-// The omega > 0 form of CalculateTau: the kept eigenpairs' exact contribution beyond the
-// truncation, sum_k (y_k(a) - y_k(b))^2 theta_k^(tau+1) / (1 - theta_k) with y_k = u_k / sqrt(d)
-// (the geometric tail of the spectral series of the resistance).  The power by squaring.
-__device__ double eigen_tail(const double *__restrict__ theta, const double *__restrict__ y,
-                             int64_t gn, int32_t pairs, int32_t a, int32_t b, int32_t tau) {
-    double acc = 0.0;
-    for (int32_t k = 0; k < pairs; ++k) {
-        const double t = theta[k];
-        const double c = y[(int64_t)k * gn + a] - y[(int64_t)k * gn + b];
-        double p = 1.0, base = t;
-        for (uint32_t e = (uint32_t)tau + 1u; e; e >>= 1) {
-            if (e & 1u) p *= base;
-            base *= base;
-        }
-        acc += c * c * p / (1.0 - t);
-    }
-    return acc;
-}
-
 // All edges of one graph in canonical order: the edge (row_of[e], col[e]) with its tau.
 __global__ void tail_all_kernel(const int32_t *__restrict__ canon, const int32_t *__restrict__ row_of,
                                 const int32_t *__restrict__ col, int64_t cb, int64_t m,

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -51,11 +52,31 @@ __global__ void scatter_kernel(const int64_t *__restrict__ map, int64_t n,
         arena[map[2 * i + 1]] = g[map[2 * i]];
 }
 
-__global__ void finalize_arena_kernel(const double *__restrict__ a, int64_t q,
+// SC of pair j from its two directed estimates, plus (omega > 0) the eigenpair tail the
+// batches left at a[2q + j]; the same additions in the same order as the synchronous calls.
+__global__ void finalize_arena_kernel(const double *__restrict__ a, int64_t q, int has_tail,
                                       double *__restrict__ sc) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q;
-         j += (int64_t)gridDim.x * blockDim.x)
-        sc[j] = a[2 * j] + a[2 * j + 1];
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double v = a[2 * j] + a[2 * j + 1];
+        if (has_tail) v += a[2 * q + j];
+        sc[j] = v;
+    }
+}
+
+// Eigenpair tails (omega > 0) of the pairs whose first directed edge ran in this batch:
+// entry i = (instance edge, arena position, u | v graph-local, theta, y, n of the graph,
+// kept pairs); tau is the batch's tau of that instance edge (symmetric in the pair).
+__global__ void tail_scatter_kernel(const int64_t *__restrict__ tm, int64_t n,
+                                    const int32_t *__restrict__ tau, double *__restrict__ arena) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t *m = tm + 7 * i;
+        const int32_t u = (int32_t)(m[2] >> 32), v = (int32_t)(m[2] & 0xffffffffll);
+        arena[m[1]] = eigen_tail(reinterpret_cast<const double *>(m[3]),
+                                 reinterpret_cast<const double *>(m[4]), m[5], (int32_t)m[6], u,
+                                 v, tau[m[0]]);
+    }
 }
 
 struct Req;
@@ -77,6 +98,8 @@ struct Req {
     int64_t ninst = 0;
     int64_t remaining = 0;
     int64_t arena_off = -1;
+    int64_t arena_len = 0;             // 2q, or 3q with the eigenpair tails (omega > 0)
+    const Spectrum *spec = nullptr;    // kept eigenpairs of the omega > 0 correction
     int32_t status = SABA_OK;
     std::string err;
     int32_t batches = 0;
@@ -124,6 +147,7 @@ struct Lane {
     hipStream_t s = nullptr;
     Workspace ws;
     DevBuf map;
+    DevBuf tmap;  // tail entries of a batch (omega > 0 requests)
     std::thread th;
 };
 
@@ -156,7 +180,7 @@ struct Server {
 void Server::admit_locked() {
     while (!arrivals.empty()) {
         const std::shared_ptr<Req> &r = arrivals.front();
-        const int64_t off = arena.alloc(2 * r->q);
+        const int64_t off = arena.alloc(r->arena_len);
         if (off < 0) break;  // in order: later arrivals wait for the arena too
         r->arena_off = off;
         r->t_admit = Clock::now();
@@ -187,7 +211,7 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
     std::vector<PSet> ps;
     std::vector<Slot> slots(nb);
     std::vector<int64_t> eb(nb + 1);
-    std::vector<int64_t> map;
+    std::vector<int64_t> map, tmap;
     int64_t ne = 0, ho = 0, bo = 0, so = 0, hubs = 0, maxgn = 1;
     for (int32_t b = 0; b < nb; ++b) {
         const Inst &x = batch[b];
@@ -221,6 +245,19 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
         for (size_t k = 0; k < x.want.size(); k += 2) {
             map.push_back(ne + x.want[k]);
             map.push_back(r.arena_off + x.want[k + 1]);
+            if (r.spec && r.spec->pairs > 0 && (x.want[k + 1] & 1) == 0) {
+                // the pair's first directed edge carries its tail
+                const int64_t j = x.want[k + 1] >> 1;
+                const int32_t u = x.v - sl.goff;
+                const int32_t v = g->h_col_idx[rp[x.v] + x.want[k]] - sl.goff;
+                tmap.push_back(ne + x.want[k]);
+                tmap.push_back(r.arena_off + 2 * r.q + j);
+                tmap.push_back(((int64_t)u << 32) | (int64_t)(uint32_t)v);
+                tmap.push_back((int64_t)reinterpret_cast<uintptr_t>(r.spec->d_theta()));
+                tmap.push_back((int64_t)reinterpret_cast<uintptr_t>(r.spec->d_y()));
+                tmap.push_back(sl.gn);
+                tmap.push_back(r.spec->pairs);
+            }
         }
         ne += rp[x.v + 1] - rp[x.v];
     }
@@ -245,6 +282,15 @@ int Server::exec_batch(Lane &ln, std::vector<Inst> &batch, int64_t *steps) {
     if (nmap > 0) {
         scatter_kernel<<<grid_for(nmap, 256, 1 << 14), 256, 0, s>>>(
             ln.map.as<int64_t>(), nmap, ea.g, arena_buf.as<double>());
+        SABA_HIP_TRY(hipGetLastError());
+    }
+    const int64_t ntail = (int64_t)tmap.size() / 7;
+    if (ntail > 0) {
+        SABA_TRY(ln.tmap.ensure(sizeof(int64_t) * tmap.size()));
+        SABA_HIP_TRY(hipMemcpyAsync(ln.tmap.ptr, tmap.data(), sizeof(int64_t) * tmap.size(),
+                                    hipMemcpyHostToDevice, s));
+        tail_scatter_kernel<<<grid_for(ntail, 256, 1 << 14), 256, 0, s>>>(
+            ln.tmap.as<int64_t>(), ntail, ea.tau, arena_buf.as<double>());
         SABA_HIP_TRY(hipGetLastError());
     }
     Flags hf;
@@ -279,7 +325,8 @@ void Server::complete(Lane &ln, std::vector<Inst> &batch, int64_t id, int rc,
     for (auto &r : fin) {
         if (r->status != SABA_OK || r->q == 0) continue;
         finalize_arena_kernel<<<grid_for(r->q, 256, 1 << 14), 256, 0, ln.s>>>(
-            arena_buf.as<double>() + r->arena_off, r->q, r->d_sc);
+            arena_buf.as<double>() + r->arena_off, r->q, r->arena_len > 2 * r->q ? 1 : 0,
+            r->d_sc);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(ln.s);
@@ -297,7 +344,7 @@ void Server::complete(Lane &ln, std::vector<Inst> &batch, int64_t id, int rc,
             }
             r->done = true;
             r->t_done = now;
-            arena.release(r->arena_off, 2 * r->q);
+            arena.release(r->arena_off, r->arena_len);
             st.queued_edges -= r->q;
             st.queued_requests -= 1;
             if (r->status == SABA_OK)
@@ -398,6 +445,7 @@ void shutdown(Server *sv) {
         if (ln->s) (void)hipStreamSynchronize(ln->s);
         ln->ws.release();
         ln->map.release();
+        ln->tmap.release();
         if (ln->s) (void)hipStreamDestroy(ln->s);
         ln->s = nullptr;
     }
@@ -521,21 +569,27 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
         }
     }
     saba_aesc_params prm = rq->params;
-    if (prm.omega != 0) {
-        set_error("the server takes omega = 0 only (use saba_aesc_query for the eigenpair form)");
-        return SABA_E_INVALID;
-    }
-    if (prm.lambda <= 0.0 && rq->graph >= 0 && rq->graph < g->ngraphs &&
-        g->gconnected[rq->graph]) {
-        // lambda left to the library: computed once per graph (on a private stream) and cached
-        hipStream_t ls = nullptr;
-        SABA_HIP_TRY(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
-        const int rc = resolve_lambda(g, rq->graph, &prm.lambda, ls);
-        (void)hipStreamDestroy(ls);
-        SABA_TRY(rc);
+    const Spectrum *spec = nullptr;
+    if (rq->graph >= 0 && rq->graph < g->ngraphs && g->gconnected[rq->graph]) {
+        const int32_t gn = g->goff[rq->graph + 1] - g->goff[rq->graph];
+        const bool eig = prm.omega > 0 && prm.omega <= kMaxOmega && prm.omega < gn &&
+                         !g->gbipartite[rq->graph];
+        if (eig || (prm.omega == 0 && prm.lambda <= 0.0)) {
+            // the spectral input, computed once per graph (and omega) on a private stream and
+            // cached: the kept eigenpairs and the radius of the rest, or lambda
+            hipStream_t ls = nullptr;
+            SABA_HIP_TRY(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+            const int rc = eig ? resolve_spectrum(g, rq->graph, prm.omega, &spec, ls)
+                               : resolve_lambda(g, rq->graph, &prm.lambda, ls);
+            (void)hipStreamDestroy(ls);
+            SABA_TRY(rc);
+            if (eig && prm.lambda <= 0.0)
+                prm.lambda = std::min(std::max(spec->lambda_rest_bound, DBL_MIN), 1.0 - 1e-12);
+        }
     }
     SABA_TRY(check_request(g, rq->graph, prm, rq->q, rq->edges));
-    if (rq->q > sv->arena_edges) {
+    const int64_t arena_len = (spec && spec->pairs > 0 ? 3 : 2) * rq->q;
+    if (arena_len > 2 * sv->arena_edges) {
         set_error("the request has more pairs than the server's result arena holds");
         return SABA_E_INVALID;
     }
@@ -545,6 +599,8 @@ extern "C" int saba_server_submit(saba_server *sh, const saba_server_request *rq
     r->sz = slot_size(g, rq->graph);
     r->q = rq->q;
     r->d_sc = rq->d_sc;
+    r->spec = spec;
+    r->arena_len = arena_len;
     // NWalks <= c * tau_cap^2 (q = L hmax / d_s <= L <= tau_cap): rule out an overflow of the
     // walk counts here, so that no batch can fail on behalf of another request
     if (!(r->ps.c * (double)r->ps.tau_cap * (double)r->ps.tau_cap < 4.0e18)) {

@@ -85,6 +85,36 @@ def test_served_results_equal_alone(saba, orc, graphs):
     np.testing.assert_allclose(expect[reqs.index(r0)], so, rtol=1e-12, atol=1e-15)
 
 
+def test_served_eigenpair_requests_equal_alone(saba, graphs):
+    """omega > 0 requests (the eigenpair form, radius left to the library) mixed with plain ones:
+    each served result equals the same request alone on a handle holding only its graph."""
+    import torch
+    gs, lams = graphs
+    mg = saba.SabaGraph.from_graphs(gs)
+    reqs = _requests(gs, lams, 12, 7)
+    for i, r in enumerate(reqs):
+        r["omega"] = 3 if i % 2 == 0 else 0
+    expect = []
+    for r in reqs:
+        sg = saba.SabaGraph.from_graph(gs[r["graph"]])
+        lam = 0.0 if r["omega"] else lams[r["graph"]]
+        sc, _ = saba.aesc_query(sg, torch.from_numpy(r["edges"]).cuda(), r["eps"], lam, r["seed"],
+                                tau_cap=r["tau_cap"], omega=r["omega"])
+        expect.append(sc.cpu().numpy())
+    with saba.SabaServer(mg, lanes=2, max_batch_sources=5) as srv:
+        tickets = [srv.submit(r["graph"], r["edges"], r["eps"],
+                              0.0 if r["omega"] else lams[r["graph"]], r["seed"],
+                              tau_cap=r["tau_cap"], omega=r["omega"]) for r in reqs]
+        for t, r, e in zip(tickets, reqs, expect):
+            sc, res = srv.wait(t)
+            assert res["status"] == 0
+            assert np.array_equal(sc.cpu().numpy(), e), r["omega"]
+    # the correction is there: the same request without it differs
+    r = next(x for x in reqs if x["omega"])
+    plain = _alone(saba, gs, lams, r)
+    assert not np.array_equal(plain, expect[reqs.index(r)])
+
+
 def test_staggered_arrivals_and_lanes(saba, graphs):
     """Requests submitted while others run, waited for out of order, on three lanes with tiny
     batches, plus duplicate pairs in one request: still identical to running alone."""

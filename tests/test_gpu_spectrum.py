@@ -232,7 +232,7 @@ def test_omega_errors(saba):
     e = graphgen.canonical_edges(g)[:4]
     with saba.SabaServer(saba.SabaGraph.from_graphs([g])) as srv:
         with pytest.raises(saba.SabaError) as ei:
-            srv.submit(0, e, 0.2, 0.5, 3, omega=2)
+            srv.submit(0, e, 0.2, 0.5, 3, omega=65)
         assert ei.value.name == "SABA_E_INVALID"
 
 
