@@ -636,11 +636,12 @@ def bench_serve(args, saba, torch, np):
             pick = rng.choice(m, q, replace=False) if q < m else np.arange(m)
             yield k, np.ascontiguousarray(ces[k][pick]), float(rng.choice([0.1, 0.2, 0.3]))
 
-    def submit(srv, req):
+    def submit(srv, req, omega=0):
         k, e, eps = req
-        return srv.submit(k, e, eps, lams[k], 1)
+        # omega > 0: the radius of the rest of the spectrum is left to the library
+        return srv.submit(k, e, eps, 0.0 if omega else lams[k], 1, omega=omega)
 
-    def open_loop(srv, rate, seconds, seed, label):
+    def open_loop(srv, rate, seconds, seed, label, omega=0):
         rng = np.random.default_rng(seed + 100)
         gen = stream(seed)
         col = _Collector(srv)
@@ -655,7 +656,7 @@ def bench_serve(args, saba, torch, np):
             req = next(gen)
             offered += 1
             try:
-                col.q.put((submit(srv, req), len(req[1]), None))
+                col.q.put((submit(srv, req, omega), len(req[1]), None))
             except saba.SabaError as e:
                 if e.name != "SABA_E_BUSY":
                     raise
@@ -733,6 +734,22 @@ def bench_serve(args, saba, torch, np):
         res["sustained"] = open_loop(srv, rate, args.serve_sustain_seconds, 12, "sustained")
         res["sustained"]["server"] = srv.stats()
 
+    if args.serve_omega > 0:
+        # the same offered load in the eigenpair form; each graph's pairs are found at its
+        # first such request and cached in the handle, so they are computed beforehand
+        with server(max_queued_edges=args.serve_queue_edges) as srv:
+            t0 = time.perf_counter()
+            for k in range(len(graphs)):
+                srv.wait(submit(srv, (k, ces[k][:8], 0.1), args.serve_omega))
+            res["omega_pairs_s"] = time.perf_counter() - t0
+            progress(f"serve workload: offered load with omega {args.serve_omega} "
+                     f"(pairs found in {res['omega_pairs_s']:.1f} s)")
+            res["offered_omega"] = open_loop(srv, args.serve_rate, args.serve_seconds, 11,
+                                             f"offered omega {args.serve_omega}",
+                                             args.serve_omega)
+            res["offered_omega"]["omega"] = args.serve_omega
+            res["offered_omega"]["server"] = srv.stats()
+
     # plain one-request-per-call path against the server on the same requests: requests of
     # the workload's size, and small requests (1-64 edges), where per-call work dominates
     res["plain_vs_served"] = compare(stream(13), args.serve_compare, "workload-sized")
@@ -795,6 +812,8 @@ def main():
     ap.add_argument("--serve-sustain-frac", type=float, default=0.7)
     ap.add_argument("--serve-sustain-seconds", type=float, default=20.0)
     ap.add_argument("--serve-compare", type=int, default=48)
+    ap.add_argument("--serve-omega", type=int, default=64,
+                    help="eigenpairs of the serving run's extra offered phase (0: none)")
     ap.add_argument("--mode", choices=["bouquet", "naive"], default="bouquet")
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--spread", type=int, default=0)
