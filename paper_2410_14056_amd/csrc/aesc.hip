@@ -443,6 +443,8 @@ __global__ __launch_bounds__(kBlock) void expand_hub_kernel(
 // in ascending vertex order (one block per instance).  Its hub rows are also appended, in any
 // order, to the hub-row list of the next level's parity.
 // Hub bits of the 32 vertices v0 .. v0 + 31 (handle ids) from the handle's hub bitmap.
+constexpr int kCompactWords = 8;  // bitmap words per thread and round of the compaction
+
 __device__ __forceinline__ uint32_t hub_word(const uint32_t *__restrict__ hubbm, int32_t v0) {
     const int32_t w = v0 >> 5, sh = v0 & 31;
     return sh == 0 ? hubbm[w] : (hubbm[w] >> sh) | (hubbm[w + 1] << (32 - sh));
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
     const uint32_t *__restrict__ hubbm, const Slot *__restrict__ slots, BatchState *__restrict__ bs,
     int32_t level, const uint32_t *__restrict__ bmnext_all, int32_t *__restrict__ Fnext_all,
     int2 *__restrict__ hubs_all, int64_t hubcap, Flags *__restrict__ fl) {
-    __shared__ uint32_t wave_tot[kWavesPerBlock];
+    __shared__ uint32_t wave_tot[kCompactWords][kWavesPerBlock];
     __shared__ int32_t carry;
     const int64_t b = blockIdx.x;
     if (!bs[b].active) return;
@@ -464,35 +466,54 @@ __global__ __launch_bounds__(kBlock) void compact_frontier_kernel(
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int64_t w0 = 0; w0 < nw; w0 += kBlock) {
-        const int64_t wi = w0 + threadIdx.x;
-        const uint32_t word = wi < nw ? bm[wi] : 0u;
-        const uint32_t cnt = __popc(word);
-        uint32_t inc = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(inc, o);
-            if (lane >= o) inc += t;
+    // A round covers kCompactWords stripes of kBlock consecutive words; thread t takes word t
+    // of every stripe (all loads in flight together), and the stripes are written one after
+    // the other, each by consecutive threads at consecutive positions.
+    for (int64_t w0 = 0; w0 < nw; w0 += (int64_t)kBlock * kCompactWords) {
+        uint32_t words[kCompactWords], cnt[kCompactWords], inc[kCompactWords];
+#pragma unroll
+        for (int k = 0; k < kCompactWords; ++k) {
+            const int64_t wi = w0 + (int64_t)k * kBlock + threadIdx.x;
+            words[k] = wi < nw ? bm[wi] : 0u;
+            cnt[k] = __popc(words[k]);
+            inc[k] = cnt[k];
         }
-        if (lane == 63) wave_tot[wave] = inc;
+#pragma unroll
+        for (int k = 0; k < kCompactWords; ++k)
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc[k], o);
+                if (lane >= o) inc[k] += t;
+            }
+        if (lane == 63)
+#pragma unroll
+            for (int k = 0; k < kCompactWords; ++k) wave_tot[k][wave] = inc[k];
         __syncthreads();
-        uint32_t before = 0, all = 0;
-        for (int k = 0; k < kWavesPerBlock; ++k) {
-            if (k < wave) before += wave_tot[k];
-            all += wave_tot[k];
-        }
-        int32_t pos = carry + (int32_t)(before + inc - cnt);
-        uint32_t rest = word;
-        const uint32_t hw = word ? hub_word(hubbm, sl.goff + (int32_t)(wi * 32)) : 0u;
-        while (rest) {
-            const int bit = __builtin_ctz(rest);
-            rest &= rest - 1;
-            const int32_t x = sl.goff + (int32_t)(wi * 32 + bit);
-            Fn[pos++] = x;
-            if ((hw >> bit) & 1u)
-                hubs_all[nxt * hubcap + atomicAdd(&fl->nhub[nxt], 1)] = make_int2((int32_t)b, x);
+        int32_t base = carry;
+#pragma unroll
+        for (int k = 0; k < kCompactWords; ++k) {
+            uint32_t before = 0, all = 0;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                if (w < wave) before += wave_tot[k][w];
+                all += wave_tot[k][w];
+            }
+            int32_t pos = base + (int32_t)(before + inc[k] - cnt[k]);
+            base += (int32_t)all;
+            uint32_t rest = words[k];
+            if (!rest) continue;
+            const int64_t wi = w0 + (int64_t)k * kBlock + threadIdx.x;
+            const uint32_t hw = hub_word(hubbm, sl.goff + (int32_t)(wi * 32));
+            while (rest) {
+                const int bit = __builtin_ctz(rest);
+                rest &= rest - 1;
+                const int32_t x = sl.goff + (int32_t)(wi * 32 + bit);
+                Fn[pos++] = x;
+                if ((hw >> bit) & 1u)
+                    hubs_all[nxt * hubcap + atomicAdd(&fl->nhub[nxt], 1)] =
+                        make_int2((int32_t)b, x);
+            }
         }
         __syncthreads();
-        if (threadIdx.x == 0) carry += (int32_t)all;
+        if (threadIdx.x == 0) carry = base;
         __syncthreads();
     }
     if (threadIdx.x == 0) bs[b].fsz[nxt] = carry;
