@@ -88,11 +88,20 @@ def measured_traffic(walks: int, steps: int, chunks: int):
     return float(c["hbm_bytes_per_dispatch"])
 
 
+def host_threads() -> int:
+    """Threads for the oracle's CPU baselines: the host's CPU share as OMP_NUM_THREADS states
+    it, else the visible cores."""
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return os.cpu_count() or 1
+
+
 def walks_cpu_baseline(g, L, seed, target_s=12.0):
     """The oracle as it stands, on all host cores, on a slice of the walks."""
     import graphgen
     import oracle
-    cores = os.cpu_count() or 1
+    cores = host_threads()
     nw = 1 << 18
     src = graphgen.uniform_sources(g, nw, seed + 1000)
     t0 = time.perf_counter()
@@ -330,7 +339,7 @@ def _aesc_cpu_baseline(args, g, lam, q, k, out):
     """The oracle on the host cores, on the first edges of the same query."""
     if not args.no_cpu_baseline:
         import oracle
-        cores = os.cpu_count() or 1
+        cores = host_threads()
         # double the sample until it takes more than 6 s of host work (the last one is kept)
         nq = 64
         while True:
@@ -800,7 +809,7 @@ def bench_c1(args, saba, torch, np):
            "sum_sc": float(sc.sum().item()), "n_minus_1": g.n - 1}
     if not args.no_cpu_baseline:
         import oracle
-        cores = os.cpu_count() or 1
+        cores = host_threads()
         t0 = time.perf_counter()
         oracle.aesc(g, 0.3, lam, 1, nthreads=1)
         d1 = time.perf_counter() - t0
