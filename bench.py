@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 WALK_KERNEL_BYTES_PER_STEP = 132
 # the same step counted in 64 B sectors (the HBM3E burst), for comparison
 WALK_KERNEL_BYTES_PER_STEP_64B = 68
-# whole walk call, counted as the survey's unit: vertex record, adjacency entry and a random
-# visit-counter update per step
+# whole walk call, priced at a vertex record, an adjacency entry and a random visit-counter
+# update per step
 WALK_STEP_BYTES = 192
 # estimator walk kernel: the 128 B line of the walk entry of the next vertex per step (the
 # support bitmaps, and the h values of frequently hit vertices, are meant to stay cached)
