@@ -24,7 +24,10 @@ constexpr int kWalkBlock = 256;
 constexpr int kMaxBucketShift = 14;      // LDS histogram of up to 16384 bins (64 KiB)
 constexpr int kMaxBuckets = 2048;        // LDS bucket counters in the walk and scatter kernels
 constexpr int64_t kLogCap = 1ll << 29;   // visit-log entries per chunk of walks
-constexpr int64_t kHistSlice = 1 << 18;  // log entries per histogram block
+// log entries per histogram block: enough blocks for the GPU (kHistBlocks), but no fewer
+// entries than LDS bins flushed (a block flushes up to 4096 bins per bucket it meets)
+constexpr int64_t kHistSliceMin = 1 << 14, kHistSliceMax = 1 << 18;
+constexpr int64_t kHistBlocks = 2048;
 constexpr int kPersistBlocks = 8192;
 
 // Counts of equal keys held by adjacent active lanes are merged, so one wavefront
@@ -290,8 +293,6 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
     if (CNT) distinct8_flush(lhist, distinct);
 }
 
-// Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order:
-// block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].
 // Block-wide exclusive scan of one value per thread (blockDim.x == kWalkBlock).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_tot) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -308,13 +309,17 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
     return before + inc - v;
 }
 
-constexpr int kSortRows = 16;  // log rows per local sort: 16 x 256 entries
+// Log rows per local sort: groups of 32 rows x 256 walks for the visit log (longer runs per
+// bucket) while its LDS fits 64 KiB, else 16; 16 for a single row (the end row), where the
+// larger group only costs LDS.
+constexpr int kSortRowsLog = 32, kSortRowsRow = 16;
 
 // Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order.
 // Block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].  Each
-// group of 16 rows x 256 walks is first sorted by bucket in LDS, so every bucket leaves
-// the block as one contiguous run.  The walks with a valid start are
+// group of kSortRows rows x 256 walks is first sorted by bucket in LDS, so every bucket
+// leaves the block as one contiguous run.  The walks with a valid start are
 // w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.
+template <int kSortRows>
 __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     const int32_t *__restrict__ vlog, int32_t rows, int64_t wc, const int64_t *__restrict__ offs,
     int32_t n, int64_t w0, int bsh, int32_t nbk, const int64_t *__restrict__ pos,
@@ -327,23 +332,39 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     uint32_t *wave_tot = reinterpret_cast<uint32_t *>(keys + kSortRows * kWalkBlock);  // [4]
     const int per = (nbk + kWalkBlock - 1) / kWalkBlock;  // buckets per thread in the scan
     for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] = pos[(int64_t)b * gridDim.x + blockIdx.x];
-    const int64_t valid = min(wc, offs[n] - w0);
-    for (int64_t tile = blockIdx.x; tile * kWalkBlock < valid; tile += gridDim.x) {
-        const int64_t i = tile * kWalkBlock + threadIdx.x;
-        const bool live = i < valid;
-        for (int32_t r0 = 0; r0 < rows; r0 += kSortRows) {
-            const int nr = min(kSortRows, rows - r0);
-            int32_t v[kSortRows];
+    const int64_t valid = rows > 0 ? min(wc, offs[n] - w0) : 0;
+    // The block's groups in order: tile blockIdx.x, blockIdx.x + gridDim.x, ..., and within a
+    // tile rows 0-15, 16-31, ...  The entries of the next group are loaded before the current
+    // one is sorted, so their memory round trip overlaps the LDS passes (the barriers wait for
+    // LDS operations only).
+    int64_t tile = blockIdx.x;
+    int32_t r0 = 0;
+    int32_t v[kSortRows], nxt[kSortRows];
+    const auto load_group = [&](int64_t t, int32_t r, int32_t(&dst)[kSortRows]) {
+        const int64_t i = t * kWalkBlock + threadIdx.x;
+        const int nr = min(kSortRows, rows - r);
+#pragma unroll
+        for (int k = 0; k < kSortRows; ++k)
+            dst[k] = (i < valid && k < nr)
+                         ? __builtin_nontemporal_load(vlog + (int64_t)(r + k) * wc + i)
+                         : -1;
+    };
+    if (tile * kWalkBlock < valid) load_group(tile, r0, v);
+    while (tile * kWalkBlock < valid) {
+        int64_t tile2 = tile;
+        int32_t r2 = r0 + kSortRows;
+        if (r2 >= rows) {
+            r2 = 0;
+            tile2 += gridDim.x;
+        }
+        const bool more = tile2 * kWalkBlock < valid;
+        if (more) load_group(tile2, r2, nxt);
+        {
             for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lcnt[b] = 0;
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < kSortRows; ++k) {
-                v[k] = -1;
-                if (live && k < nr) {
-                    v[k] = __builtin_nontemporal_load(vlog + (int64_t)(r0 + k) * wc + i);
-                    atomicAdd(lcnt + (v[k] >> bsh), 1u);
-                }
-            }
+            for (int k = 0; k < kSortRows; ++k)
+                if (v[k] >= 0) atomicAdd(lcnt + (v[k] >> bsh), 1u);
             __syncthreads();
             // local offsets: exclusive scan of lcnt, `per` buckets per thread
             uint32_t mine = 0;
@@ -381,16 +402,29 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
             for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] += loff[b + 1] - loff[b];
             __syncthreads();
         }
+        if (!more) break;
+#pragma unroll
+        for (int k = 0; k < kSortRows; ++k) v[k] = nxt[k];
+        tile = tile2;
+        r0 = r2;
     }
 }
 
-static size_t scatter_lds_bytes(int32_t nbk) {
+static size_t scatter_lds_bytes(int32_t nbk, int sort_rows) {
     return sizeof(int64_t) * nbk + sizeof(uint32_t) * (2 * (size_t)nbk + 1) +
-           sizeof(int32_t) * kSortRows * kWalkBlock + sizeof(uint32_t) * 4 + 16;
+           sizeof(int32_t) * sort_rows * kWalkBlock + sizeof(uint32_t) * 4 + 16;
 }
 
 // Histogram of the bucket-ordered entries: block j counts part[j*slice, (j+1)*slice) bucket
-// by bucket in LDS and adds the nonzero bins to out.  Bucket b starts at pos[b * nblk].
+// by bucket in LDS and adds the nonzero bins to out.  Bucket b starts at pos[b * nblk].  The
+// entries are read 16 bytes at a time, kHistUnroll reads in flight per thread, so the stream
+// is not bound by the latency of one read per LDS update.
+constexpr int kHistUnroll = 4;
+
+__device__ __forceinline__ void hist_add(uint32_t *lds_h, int32_t x, int32_t mask) {
+    atomicAdd(lds_h + (x & mask), 1u);
+}
+
 __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
     const int32_t *__restrict__ part, const int64_t *__restrict__ pos, int nblk, int bsh,
     int32_t nbk, int64_t slice, int32_t n, unsigned long long *__restrict__ out) {
@@ -408,6 +442,7 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
         else
             hi = mid;
     }
+    const nbr_vec4 *part4 = reinterpret_cast<const nbr_vec4 *>(part);  // 4 int32 entries
     for (int32_t b = lo; b < nbk; ++b) {
         const int64_t bs = pos[(int64_t)b * nblk];
         const int64_t be = pos[(int64_t)(b + 1) * nblk];
@@ -416,8 +451,30 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
         if (a >= z) continue;
         for (int i = threadIdx.x; i < bins; i += kWalkBlock) lds_h[i] = 0;
         __syncthreads();
-        for (int64_t i = a + threadIdx.x; i < z; i += kWalkBlock)
-            atomicAdd(lds_h + (part[i] & (bins - 1)), 1u);
+        // entries a .. z: an unaligned head and tail one by one, whole 16-byte words between
+        const int64_t q0 = (a + 3) >> 2, q1 = z >> 2;
+        if (q0 >= q1) {
+            for (int64_t i = a + threadIdx.x; i < z; i += kWalkBlock)
+                hist_add(lds_h, part[i], bins - 1);
+        } else {
+            if (a + threadIdx.x < 4 * q0) hist_add(lds_h, part[a + threadIdx.x], bins - 1);
+            if (4 * q1 + threadIdx.x < z) hist_add(lds_h, part[4 * q1 + threadIdx.x], bins - 1);
+            for (int64_t q = q0 + threadIdx.x; q < q1; q += kHistUnroll * kWalkBlock) {
+                nbr_vec4 x[kHistUnroll];
+#pragma unroll
+                for (int u = 0; u < kHistUnroll; ++u)
+                    if (q + u * kWalkBlock < q1)
+                        x[u] = __builtin_nontemporal_load(part4 + q + u * kWalkBlock);
+#pragma unroll
+                for (int u = 0; u < kHistUnroll; ++u)
+                    if (q + u * kWalkBlock < q1) {
+                        hist_add(lds_h, x[u].x, bins - 1);
+                        hist_add(lds_h, x[u].y, bins - 1);
+                        hist_add(lds_h, x[u].z, bins - 1);
+                        hist_add(lds_h, x[u].w, bins - 1);
+                    }
+            }
+        }
         __syncthreads();
         const int64_t base = (int64_t)b << bsh;
         for (int i = threadIdx.x; i < bins; i += kWalkBlock) {
@@ -436,6 +493,11 @@ struct EventSet {
     }
 };
 
+// Histogram slice for a log of at most `bound` entries.
+static int64_t hist_slice(int64_t bound) {
+    return std::min(kHistSliceMax, std::max(kHistSliceMin, (bound + kHistBlocks - 1) / kHistBlocks));
+}
+
 // Bucketed count of one log (rows x wc entries, `valid` walks per row) into out.
 static int bucket_count(int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
                         int64_t w0, int nblk, int bsh, int32_t nbk, int64_t *cnt, int64_t *pos,
@@ -443,13 +505,18 @@ static int bucket_count(int32_t *vlog, int32_t rows, int64_t wc, const int64_t *
                         hipStream_t s) {
     const int64_t ncnt = (int64_t)nbk * nblk;
     SABA_TRY(scan_i64(cnt, pos, ncnt, scan_tmp, s));
-    bucket_scatter_kernel<<<nblk, kWalkBlock, scatter_lds_bytes(nbk), s>>>(vlog, rows, wc, offs, n,
-                                                                          w0, bsh, nbk, pos, part);
+    if (rows >= kSortRowsLog && scatter_lds_bytes(nbk, kSortRowsLog) <= 65536)
+        bucket_scatter_kernel<kSortRowsLog><<<nblk, kWalkBlock, scatter_lds_bytes(nbk, kSortRowsLog),
+                                              s>>>(vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part);
+    else
+        bucket_scatter_kernel<kSortRowsRow><<<nblk, kWalkBlock, scatter_lds_bytes(nbk, kSortRowsRow),
+                                              s>>>(vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part);
     SABA_HIP_TRY(hipGetLastError());
     const int64_t bound = (int64_t)rows * wc;  // at least the number of entries counted
-    const unsigned hblocks = (unsigned)std::max<int64_t>(1, (bound + kHistSlice - 1) / kHistSlice);
+    const int64_t slice = hist_slice(bound);
+    const unsigned hblocks = (unsigned)std::max<int64_t>(1, (bound + slice - 1) / slice);
     bucket_hist_kernel<<<hblocks, kWalkBlock, sizeof(uint32_t) << bsh, s>>>(
-        part, pos, nblk, bsh, nbk, kHistSlice, n, out);
+        part, pos, nblk, bsh, nbk, slice, n, out);
     SABA_HIP_TRY(hipGetLastError());
     return SABA_OK;
 }
