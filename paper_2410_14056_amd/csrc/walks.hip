@@ -62,6 +62,31 @@ __global__ __launch_bounds__(kWalkBlock) void source_count_kernel(
     }
 }
 
+// Sources, bucketed: block k counts the valid starts among entries 256 (k + m * gridDim.x) ..
+// + 255 (m = 0, 1, ...) per vertex bucket in LDS and writes cnt[b * gridDim.x + k]; invalid
+// starts set the error flag and are not counted.  The scatter and histogram of the walk log
+// then turn these into per-vertex walk counts without a global atomic per walk.
+__global__ __launch_bounds__(kWalkBlock) void source_bucket_count_kernel(
+    const int32_t *__restrict__ src, int64_t W, const int2 *__restrict__ vrec, int32_t n, int bsh,
+    int32_t nbk, long long *__restrict__ cnt, int32_t *__restrict__ err) {
+    extern __shared__ uint32_t lds_sc[];
+    for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lds_sc[b] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kWalkBlock + threadIdx.x; i < W;
+         i += (int64_t)gridDim.x * kWalkBlock) {
+        const int32_t v = src[i];
+        if (v < 0 || v >= n || vrec[v].y == 0)
+            bad = true;
+        else
+            atomicAdd(lds_sc + (v >> bsh), 1u);
+    }
+    if (bad) atomicOr(err, 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += kWalkBlock)
+        cnt[(int64_t)b * gridDim.x + blockIdx.x] = lds_sc[b];
+}
+
 // Bucket order: bsrc[w] = s for offs[s] <= w < offs[s + 1].
 __global__ __launch_bounds__(kWalkBlock) void source_fill_kernel(const int64_t *__restrict__ offs,
                                                                  int32_t n,
@@ -318,12 +343,15 @@ constexpr int kSortRowsLog = 32, kSortRowsRow = 16;
 // Block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].  Each
 // group of kSortRows rows x 256 walks is first sorted by bucket in LDS, so every bucket
 // leaves the block as one contiguous run.  The walks with a valid start are
-// w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.
-template <int kSortRows>
+// w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.  With
+// offs null all wc entries are read, and with CHECK (the list of start vertices) an entry
+// that is not a valid start (outside 0 .. n - 1, or without neighbours) is dropped, as the
+// count of source_bucket_count_kernel drops it.
+template <int kSortRows, bool CHECK>
 __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     const int32_t *__restrict__ vlog, int32_t rows, int64_t wc, const int64_t *__restrict__ offs,
     int32_t n, int64_t w0, int bsh, int32_t nbk, const int64_t *__restrict__ pos,
-    int32_t *__restrict__ part) {
+    int32_t *__restrict__ part, const int2 *__restrict__ vrec) {
     extern __shared__ unsigned char lds_raw[];
     int64_t *gpos = reinterpret_cast<int64_t *>(lds_raw);           // [nbk] global cursor
     uint32_t *lcnt = reinterpret_cast<uint32_t *>(gpos + nbk);       // [nbk] counts / cursors
@@ -332,7 +360,7 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     uint32_t *wave_tot = reinterpret_cast<uint32_t *>(keys + kSortRows * kWalkBlock);  // [4]
     const int per = (nbk + kWalkBlock - 1) / kWalkBlock;  // buckets per thread in the scan
     for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] = pos[(int64_t)b * gridDim.x + blockIdx.x];
-    const int64_t valid = rows > 0 ? min(wc, offs[n] - w0) : 0;
+    const int64_t valid = rows <= 0 ? 0 : offs ? min(wc, offs[n] - w0) : wc;
     // The block's groups in order: tile blockIdx.x, blockIdx.x + gridDim.x, ..., and within a
     // tile rows 0-15, 16-31, ...  The entries of the next group are loaded before the current
     // one is sorted, so their memory round trip overlaps the LDS passes (the barriers wait for
@@ -359,6 +387,11 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
         }
         const bool more = tile2 * kWalkBlock < valid;
         if (more) load_group(tile2, r2, nxt);
+        if (CHECK) {
+#pragma unroll
+            for (int k = 0; k < kSortRows; ++k)
+                if (v[k] >= n || (v[k] >= 0 && vrec[v[k]].y == 0)) v[k] = -1;
+        }
         {
             for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lcnt[b] = 0;
             __syncthreads();
@@ -499,18 +532,23 @@ static int64_t hist_slice(int64_t bound) {
 }
 
 // Bucketed count of one log (rows x wc entries, `valid` walks per row) into out.
-static int bucket_count(int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
+static int bucket_count(const int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
                         int64_t w0, int nblk, int bsh, int32_t nbk, int64_t *cnt, int64_t *pos,
                         void *scan_tmp, int32_t *part, int32_t n, unsigned long long *out,
-                        hipStream_t s) {
+                        hipStream_t s, const int2 *check_vrec = nullptr) {
     const int64_t ncnt = (int64_t)nbk * nblk;
     SABA_TRY(scan_i64(cnt, pos, ncnt, scan_tmp, s));
-    if (rows >= kSortRowsLog && scatter_lds_bytes(nbk, kSortRowsLog) <= 65536)
-        bucket_scatter_kernel<kSortRowsLog><<<nblk, kWalkBlock, scatter_lds_bytes(nbk, kSortRowsLog),
-                                              s>>>(vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part);
+    const size_t lds_log = scatter_lds_bytes(nbk, kSortRowsLog);
+    const size_t lds_row = scatter_lds_bytes(nbk, kSortRowsRow);
+    if (check_vrec)
+        bucket_scatter_kernel<kSortRowsRow, true><<<nblk, kWalkBlock, lds_row, s>>>(
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, check_vrec);
+    else if (rows >= kSortRowsLog && lds_log <= 65536)
+        bucket_scatter_kernel<kSortRowsLog, false><<<nblk, kWalkBlock, lds_log, s>>>(
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, nullptr);
     else
-        bucket_scatter_kernel<kSortRowsRow><<<nblk, kWalkBlock, scatter_lds_bytes(nbk, kSortRowsRow),
-                                              s>>>(vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part);
+        bucket_scatter_kernel<kSortRowsRow, false><<<nblk, kWalkBlock, lds_row, s>>>(
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, nullptr);
     SABA_HIP_TRY(hipGetLastError());
     const int64_t bound = (int64_t)rows * wc;  // at least the number of entries counted
     const int64_t slice = hist_slice(bound);
@@ -721,17 +759,24 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         void *scan_tmp = offs + n + 1;
         int32_t *bsrc = g->walk_scratch[2].as<int32_t>();
         SABA_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int64_t) * (size_t)n, s));
-        unsigned cblocks = (unsigned)std::min<int64_t>((W + kWalkBlock - 1) / kWalkBlock, 1 << 16);
-        source_count_kernel<<<cblocks, kWalkBlock, 0, s>>>(p->d_sources, W, g->vrec, n, counts, err);
-        SABA_HIP_TRY(hipGetLastError());
-        SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
-        source_fill_kernel<<<cblocks, kWalkBlock, 0, s>>>(offs, n, bsrc);
-        SABA_HIP_TRY(hipGetLastError());
+        const unsigned cblocks =
+            (unsigned)std::min<int64_t>((W + kWalkBlock - 1) / kWalkBlock, 1 << 16);
+        // walks per start vertex counted into `counts`: offsets and the bucket order follow
+        const auto order_walks = [&]() -> int {
+            SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
+            source_fill_kernel<<<cblocks, kWalkBlock, 0, s>>>(offs, n, bsrc);
+            SABA_HIP_TRY(hipGetLastError());
+            return SABA_OK;
+        };
 
         int bsh = 12;
         while (bsh < kMaxBucketShift && (((int64_t)n + (1 << bsh) - 1) >> bsh) > kMaxBuckets) ++bsh;
         const int32_t nbk = (int32_t)(((int64_t)n + (1 << bsh) - 1) >> bsh);
         if (nbk > kMaxBuckets) {
+            source_count_kernel<<<cblocks, kWalkBlock, 0, s>>>(p->d_sources, W, g->vrec, n, counts,
+                                                                err);
+            SABA_HIP_TRY(hipGetLastError());
+            SABA_TRY(order_walks());
             if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
             unsigned blocks = (unsigned)((W + kWalkBlock - 1) / kWalkBlock);
             switch (sm) {
@@ -764,7 +809,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             const int64_t ncnt = (int64_t)nbk * nblk;
             const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
             SABA_TRY(g->walk_scratch[4].ensure(sizeof(int32_t) * (size_t)(logn + wc)));
-            SABA_TRY(g->walk_scratch[5].ensure(sizeof(int32_t) * (size_t)(std::max<int32_t>(L, 1) * wc)));
+            // bucket-ordered entries of the largest log: the visit log, or the start list
+            const int64_t partn = std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * wc, W);
+            SABA_TRY(g->walk_scratch[5].ensure(sizeof(int32_t) * (size_t)partn));
             SABA_TRY(g->walk_scratch[6].ensure(sizeof(int64_t) * (size_t)(4 * ncnt + 2) +
                                                scan_tmp_bytes(ncnt)));
             int32_t *vlog = g->walk_scratch[4].as<int32_t>();
@@ -774,6 +821,14 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             int64_t *cnt_e = cnt_v + ncnt;
             int64_t *pos = cnt_e + ncnt;  // ncnt + 1 entries
             void *ctmp = pos + ncnt + 2;
+            // walks per start vertex, counted like the visits (per bucket and block in LDS,
+            // then bucket order, then a histogram per bucket) on the same nblk blocks
+            source_bucket_count_kernel<<<nblk, kWalkBlock, sizeof(uint32_t) * nbk, s>>>(
+                p->d_sources, W, g->vrec, n, bsh, nbk, reinterpret_cast<long long *>(cnt_v), err);
+            SABA_HIP_TRY(hipGetLastError());
+            SABA_TRY(bucket_count(p->d_sources, 1, W, nullptr, 0, nblk, bsh, nbk, cnt_v, pos, ctmp,
+                                  part, n, counts, s, g->vrec));
+            SABA_TRY(order_walks());
             float walk_ms = 0.f, count_ms = 0.f;
             for (int64_t w0 = 0; w0 < W; w0 += wc) {
                 const int64_t this_wc = std::min<int64_t>(wc, W - w0);
