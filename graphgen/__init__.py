@@ -14,6 +14,7 @@ from .generators import (  # noqa: F401
     chung_lu,
     grid_diagonals,
     toy_graph,
+    circulant,
     from_edges,
     uniform_sources,
     spectral_lambda,

@@ -178,6 +178,28 @@ def grid_diagonals(rows: int, cols: int, frac: float, seed: int) -> Graph:
                                "frac": frac, "seed": seed})
 
 
+def circulant(n: int, steps=(1, 2)) -> Graph:
+    """Circulant graph C_n(steps): vertex i is joined to i - s and i + s (mod n) for every s in
+    `steps` (0 < s < n/2, distinct).  Every vertex has degree 2 |steps|.  The CSR is built
+    directly, without the edge-list canonicalisation, so graphs of 10^7-10^8 vertices take
+    seconds (large vertex counts for bucket-count limits)."""
+    st = sorted({int(x) for x in steps})
+    if not st or st[0] <= 0 or 2 * st[-1] >= n:
+        raise ValueError("steps must lie in 0 < s < n/2")
+    k = 2 * len(st)
+    if (n + 1) * k >= 2**31:
+        raise ValueError("graph too large for int32 CSR")
+    off = np.array([-x for x in st] + st, dtype=np.int64)
+    col = np.empty((n, k), dtype=np.int32)
+    base = np.arange(n, dtype=np.int64)
+    for j, o in enumerate(off):
+        col[:, j] = (base + o) % n
+    col.sort(axis=1)
+    row_ptr = (np.arange(n + 1, dtype=np.int64) * k).astype(np.int32)
+    return Graph(row_ptr, col.reshape(-1), name=f"circulant{n}_{'_'.join(map(str, st))}",
+                 meta={"gen": "circulant", "n": n, "steps": st})
+
+
 def toy_graph() -> Graph:
     """The 4-vertex, 5-edge sample graph of Fig. 1: A,D of degree 2, B,C of degree 3
     (K4 minus the edge A-D). Vertex ids: A=0, B=1, C=2, D=3."""

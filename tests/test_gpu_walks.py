@@ -143,3 +143,70 @@ def test_rmat20_full_size(saba, orc, rmat20):
     ep_o, vi_o = orc.walks_histogram(g, sub, L, seed=1)
     ep, vi = _run(saba, sg, sub, L, 1, 1, 0, saba.SABA_WALK_BOUQUET)
     assert np.array_equal(ep, ep_o) and np.array_equal(vi, vi_o)
+
+
+def test_skewed_starts_match_oracle(saba, orc):
+    """Most walks share one start (the largest hub) and a second one: the per-bucket start
+    count, the start scatter and the walk order by start vertex see heavy collisions."""
+    g = GRAPHS["rmat12"]()
+    deg = np.diff(g.row_ptr)
+    order = np.argsort(deg, kind="stable")
+    hub, second = int(order[-1]), int(order[-2])
+    src = np.concatenate([np.full(40000, hub), np.full(7000, second),
+                          graphgen.uniform_sources(g, 3001, 8)]).astype(np.int32)
+    np.random.default_rng(3).shuffle(src)
+    sg = saba.SabaGraph.from_graph(g)
+    for L in (7, 64):
+        print(f"skewed starts L={L} W={src.size}", flush=True)
+        ep_o, vi_o = orc.walks_histogram(g, src, L, seed=5)
+        for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+            ep, vi = _run(saba, sg, src, L, 5, 1, 0, mode)
+            assert np.array_equal(ep, ep_o), (L, mode)
+            assert np.array_equal(vi, vi_o), (L, mode)
+
+
+def test_invalid_start_in_long_list(saba, orc):
+    """One invalid start among 300,000 (past the last vertex, isolated, negative; at the front,
+    the middle or the end of the list) fails the call in both modes; the handle then gives the
+    oracle's result."""
+    import torch
+    g = GRAPHS["rmat12"]()
+    iso = int(np.flatnonzero(np.diff(g.row_ptr) == 0)[0])
+    good = graphgen.uniform_sources(g, 300000, 4)
+    sg = saba.SabaGraph.from_graph(g)
+    for bad in (g.n, iso, -3):
+        for at in (0, 150000, 299999):
+            src = good.copy()
+            src[at] = bad
+            t = torch.from_numpy(src).cuda()
+            for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+                with pytest.raises(saba.SabaError) as ei:
+                    saba.walks(sg, t, 9, 2, mode=mode)
+                assert ei.value.name == "SABA_E_INVALID", (bad, at, mode)
+    ep_o, vi_o = orc.walks_histogram(g, good, 9, seed=2)
+    ep, vi = _run(saba, sg, good, 9, 2, 1, 0, saba.SABA_WALK_BOUQUET)
+    assert np.array_equal(ep, ep_o) and np.array_equal(vi, vi_o)
+
+
+@pytest.mark.parametrize("n", [1 << 24, (1 << 25) + 7])
+def test_many_vertex_buckets(saba, orc, n):
+    """2^24 vertices give 2048 buckets of 8192 ids, where the 32-row sort of the visit log no
+    longer fits 64 KiB of LDS and 16-row groups are used; 2^25 + 7 vertices need more than 2048
+    buckets, and the walks count with global atomics instead.  Naive and bouquet order agree
+    bit for bit, and a slice of the walks matches the oracle."""
+    import torch
+    g = graphgen.circulant(n, (1, 1000))
+    print(f"many buckets n={n}", flush=True)
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    W, L = 1 << 20, 40
+    src = torch.from_numpy(graphgen.uniform_sources(g, W, 2)).cuda()
+    rb = saba.walks(sg, src, L, 3, mode=saba.SABA_WALK_BOUQUET)
+    bep, bvi = rb.endpoint.cpu().numpy(), rb.visits.cpu().numpy()
+    rn = saba.walks(sg, src, L, 3, mode=saba.SABA_WALK_NAIVE)
+    assert np.array_equal(bep, rn.endpoint.cpu().numpy())
+    assert np.array_equal(bvi, rn.visits.cpu().numpy())
+    assert bep.sum() == W and bvi.sum() == W * L
+    sub = graphgen.uniform_sources(g, 1 << 13, 6)
+    ep_o, vi_o = orc.walks_histogram(g, sub, L, seed=3)
+    ep, vi = _run(saba, sg, sub, L, 3, 1, 0, saba.SABA_WALK_BOUQUET)
+    assert np.array_equal(ep, ep_o) and np.array_equal(vi, vi_o)

@@ -30,6 +30,21 @@ GENS = {
 }
 
 
+def test_circulant_is_canonical_and_regular():
+    g = graphgen.circulant(1000, (1, 7, 100))
+    _canonical(g)
+    assert g.n == 1000 and g.m == 3000 and np.all(np.diff(g.row_ptr) == 6)
+    # vertex 0 is joined to 1, 7, 100 and their negatives mod n
+    assert list(g.col_idx[:6]) == [1, 7, 100, 900, 993, 999]
+    # the direct build equals canonicalising the same edge list
+    u = np.repeat(np.arange(1000), 3)
+    v = (u + np.tile([1, 7, 100], 1000)) % 1000
+    h = graphgen.canonical_csr(u, v, 1000)
+    assert np.array_equal(g.row_ptr, h.row_ptr) and np.array_equal(g.col_idx, h.col_idx)
+    with pytest.raises(ValueError):
+        graphgen.circulant(10, (5,))
+
+
 @pytest.mark.parametrize("name", list(GENS))
 def test_deterministic_and_canonical(name):
     g1, g2, g3 = GENS[name](1), GENS[name](1), GENS[name](2)
