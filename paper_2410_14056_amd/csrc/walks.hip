@@ -62,24 +62,42 @@ __global__ __launch_bounds__(kWalkBlock) void source_count_kernel(
     }
 }
 
-// Sources, bucketed: block k counts the valid starts among entries 256 (k + m * gridDim.x) ..
-// + 255 (m = 0, 1, ...) per vertex bucket in LDS and writes cnt[b * gridDim.x + k]; invalid
-// starts set the error flag and are not counted.  The scatter and histogram of the walk log
-// then turn these into per-vertex walk counts without a global atomic per walk.
+// Sources, bucketed.  The start list is read as a log of `rows` rows of wc entries (entry r,
+// i is src[r * wc + i], up to W): block k counts the starts of columns 256 (k + m * gridDim.x)
+// .. + 255 (m = 0, 1, ...) per vertex bucket in LDS and writes cnt[b * gridDim.x + k], the
+// column order the scatter uses.  A start outside 0 .. n - 1 sets the error flag and is not
+// counted; a start without neighbours is caught by start_check_kernel once the counts are per
+// vertex, so this pass reads no vertex records.
+constexpr int kStartLoads = 8;
+
 __global__ __launch_bounds__(kWalkBlock) void source_bucket_count_kernel(
-    const int32_t *__restrict__ src, int64_t W, const int2 *__restrict__ vrec, int32_t n, int bsh,
+    const int32_t *__restrict__ src, int64_t W, int32_t rows, int64_t wc, int32_t n, int bsh,
     int32_t nbk, long long *__restrict__ cnt, int32_t *__restrict__ err) {
     extern __shared__ uint32_t lds_sc[];
     for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lds_sc[b] = 0;
     __syncthreads();
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kWalkBlock + threadIdx.x; i < W;
-         i += (int64_t)gridDim.x * kWalkBlock) {
-        const int32_t v = src[i];
-        if (v < 0 || v >= n || vrec[v].y == 0)
-            bad = true;
-        else
-            atomicAdd(lds_sc + (v >> bsh), 1u);
+    for (int64_t tile = blockIdx.x; tile * kWalkBlock < wc; tile += gridDim.x) {
+        const int64_t i = tile * kWalkBlock + threadIdx.x;
+        if (i >= wc) continue;
+        for (int32_t r0 = 0; r0 < rows; r0 += kStartLoads) {
+            int32_t v[kStartLoads];
+            bool has[kStartLoads];
+#pragma unroll
+            for (int u = 0; u < kStartLoads; ++u) {
+                const int64_t e = (int64_t)(r0 + u) * wc + i;
+                has[u] = r0 + u < rows && e < W;
+                v[u] = has[u] ? src[e] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kStartLoads; ++u)
+                if (has[u]) {
+                    if (v[u] < 0 || v[u] >= n)
+                        bad = true;
+                    else
+                        atomicAdd(lds_sc + (v[u] >> bsh), 1u);
+                }
+        }
     }
     if (bad) atomicOr(err, 1);
     __syncthreads();
@@ -87,22 +105,66 @@ __global__ __launch_bounds__(kWalkBlock) void source_bucket_count_kernel(
         cnt[(int64_t)b * gridDim.x + blockIdx.x] = lds_sc[b];
 }
 
-// Bucket order: bsrc[w] = s for offs[s] <= w < offs[s + 1].
+// Walks per start vertex, counted: a vertex without neighbours is not a valid start.  Its
+// count is cleared (no walk is laid out for it) and the error flag set.
+__global__ __launch_bounds__(kWalkBlock) void start_check_kernel(
+    const int2 *__restrict__ vrec, int32_t n, unsigned long long *__restrict__ counts,
+    int32_t *__restrict__ err) {
+    bool bad = false;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (counts[v] != 0 && vrec[v].y == 0) {
+            counts[v] = 0;
+            bad = true;
+        }
+    if (bad) atomicOr(err, 1);
+}
+
+// Bucket order: bsrc[w] = s for offs[s] <= w < offs[s + 1].  A thread fills kFillRun
+// consecutive walks; it finds the start vertex of the first by binary search and of each later
+// one by a step to the next vertex or, past vertices without walks, another search.
+constexpr int kFillRun = 16;
+
+__device__ __forceinline__ int32_t last_at_or_below(const int64_t *__restrict__ offs, int32_t lo,
+                                                    int32_t hi, int64_t w) {
+    // largest s in [lo, hi) with offs[s] <= w, given offs[lo] <= w
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (offs[mid] <= w)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(kWalkBlock) void source_fill_kernel(const int64_t *__restrict__ offs,
                                                                  int32_t n,
                                                                  int32_t *__restrict__ bsrc) {
+    // a block fills 4096 consecutive walks: thread t the run 16 t .. 16 t + 15, staged in LDS
+    // (17 words per run, so the 64 lanes of a wavefront hit distinct banks) and stored
+    // coalesced
+    constexpr int kSpan = kWalkBlock * kFillRun;
+    __shared__ int32_t stage[kWalkBlock * (kFillRun + 1)];
     const int64_t W = offs[n];
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        int32_t lo = 0, hi = n;  // largest s with offs[s] <= w
-        while (hi - lo > 1) {
-            int32_t mid = lo + ((hi - lo) >> 1);
-            if (offs[mid] <= w)
-                lo = mid;
-            else
-                hi = mid;
+    for (int64_t b0 = (int64_t)blockIdx.x * kSpan; b0 < W; b0 += (int64_t)gridDim.x * kSpan) {
+        const int64_t w0 = b0 + (int64_t)threadIdx.x * kFillRun;
+        if (w0 < W) {
+            int32_t v = last_at_or_below(offs, 0, n, w0);
+            int64_t next = offs[v + 1];
+            const int64_t w1 = min(W, w0 + kFillRun);
+            for (int64_t w = w0; w < w1; ++w) {
+                if (w >= next) {
+                    v = offs[v + 2] > w ? v + 1 : last_at_or_below(offs, v + 1, n, w);
+                    next = offs[v + 1];
+                }
+                stage[threadIdx.x * (kFillRun + 1) + (int)(w - w0)] = v;
+            }
         }
-        bsrc[w] = lo;
+        __syncthreads();
+        for (int q = threadIdx.x; q < kSpan; q += kWalkBlock)
+            if (b0 + q < W) bsrc[b0 + q] = stage[q + q / kFillRun];
+        __syncthreads();
     }
 }
 
@@ -344,14 +406,14 @@ constexpr int kSortRowsLog = 32, kSortRowsRow = 16;
 // group of kSortRows rows x 256 walks is first sorted by bucket in LDS, so every bucket
 // leaves the block as one contiguous run.  The walks with a valid start are
 // w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.  With
-// offs null all wc entries are read, and with CHECK (the list of start vertices) an entry
-// that is not a valid start (outside 0 .. n - 1, or without neighbours) is dropped, as the
-// count of source_bucket_count_kernel drops it.
+// offs null all wc columns are read, and entries at r * wc + i >= limit are not.  With CHECK
+// (the list of start vertices) an entry outside 0 .. n - 1 is dropped, as the count of
+// source_bucket_count_kernel drops it.
 template <int kSortRows, bool CHECK>
 __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     const int32_t *__restrict__ vlog, int32_t rows, int64_t wc, const int64_t *__restrict__ offs,
     int32_t n, int64_t w0, int bsh, int32_t nbk, const int64_t *__restrict__ pos,
-    int32_t *__restrict__ part, const int2 *__restrict__ vrec) {
+    int32_t *__restrict__ part, int64_t limit) {
     extern __shared__ unsigned char lds_raw[];
     int64_t *gpos = reinterpret_cast<int64_t *>(lds_raw);           // [nbk] global cursor
     uint32_t *lcnt = reinterpret_cast<uint32_t *>(gpos + nbk);       // [nbk] counts / cursors
@@ -372,10 +434,10 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
         const int64_t i = t * kWalkBlock + threadIdx.x;
         const int nr = min(kSortRows, rows - r);
 #pragma unroll
-        for (int k = 0; k < kSortRows; ++k)
-            dst[k] = (i < valid && k < nr)
-                         ? __builtin_nontemporal_load(vlog + (int64_t)(r + k) * wc + i)
-                         : -1;
+        for (int k = 0; k < kSortRows; ++k) {
+            const int64_t e = (int64_t)(r + k) * wc + i;
+            dst[k] = (i < valid && k < nr && e < limit) ? __builtin_nontemporal_load(vlog + e) : -1;
+        }
     };
     if (tile * kWalkBlock < valid) load_group(tile, r0, v);
     while (tile * kWalkBlock < valid) {
@@ -390,7 +452,7 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
         if (CHECK) {
 #pragma unroll
             for (int k = 0; k < kSortRows; ++k)
-                if (v[k] >= n || (v[k] >= 0 && vrec[v[k]].y == 0)) v[k] = -1;
+                if (v[k] >= n) v[k] = -1;
         }
         {
             for (int b = threadIdx.x; b < nbk; b += kWalkBlock) lcnt[b] = 0;
@@ -535,20 +597,24 @@ static int64_t hist_slice(int64_t bound) {
 static int bucket_count(const int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
                         int64_t w0, int nblk, int bsh, int32_t nbk, int64_t *cnt, int64_t *pos,
                         void *scan_tmp, int32_t *part, int32_t n, unsigned long long *out,
-                        hipStream_t s, const int2 *check_vrec = nullptr) {
+                        hipStream_t s, int64_t limit, bool check = false) {
     const int64_t ncnt = (int64_t)nbk * nblk;
     SABA_TRY(scan_i64(cnt, pos, ncnt, scan_tmp, s));
     const size_t lds_log = scatter_lds_bytes(nbk, kSortRowsLog);
     const size_t lds_row = scatter_lds_bytes(nbk, kSortRowsRow);
-    if (check_vrec)
+    const bool tall = rows >= kSortRowsLog && lds_log <= 65536;
+    if (check && tall)
+        bucket_scatter_kernel<kSortRowsLog, true><<<nblk, kWalkBlock, lds_log, s>>>(
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, limit);
+    else if (check)
         bucket_scatter_kernel<kSortRowsRow, true><<<nblk, kWalkBlock, lds_row, s>>>(
-            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, check_vrec);
-    else if (rows >= kSortRowsLog && lds_log <= 65536)
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, limit);
+    else if (tall)
         bucket_scatter_kernel<kSortRowsLog, false><<<nblk, kWalkBlock, lds_log, s>>>(
-            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, nullptr);
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, limit);
     else
         bucket_scatter_kernel<kSortRowsRow, false><<<nblk, kWalkBlock, lds_row, s>>>(
-            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, nullptr);
+            vlog, rows, wc, offs, n, w0, bsh, nbk, pos, part, limit);
     SABA_HIP_TRY(hipGetLastError());
     const int64_t bound = (int64_t)rows * wc;  // at least the number of entries counted
     const int64_t slice = hist_slice(bound);
@@ -764,7 +830,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         // walks per start vertex counted into `counts`: offsets and the bucket order follow
         const auto order_walks = [&]() -> int {
             SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
-            source_fill_kernel<<<cblocks, kWalkBlock, 0, s>>>(offs, n, bsrc);
+            const unsigned fblocks = (unsigned)std::min<int64_t>(
+                (W + (int64_t)kWalkBlock * kFillRun - 1) / ((int64_t)kWalkBlock * kFillRun), 1 << 16);
+            source_fill_kernel<<<fblocks, kWalkBlock, 0, s>>>(offs, n, bsrc);
             SABA_HIP_TRY(hipGetLastError());
             return SABA_OK;
         };
@@ -821,13 +889,21 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             int64_t *cnt_e = cnt_v + ncnt;
             int64_t *pos = cnt_e + ncnt;  // ncnt + 1 entries
             void *ctmp = pos + ncnt + 2;
-            // walks per start vertex, counted like the visits (per bucket and block in LDS,
-            // then bucket order, then a histogram per bucket) on the same nblk blocks
-            source_bucket_count_kernel<<<nblk, kWalkBlock, sizeof(uint32_t) * nbk, s>>>(
-                p->d_sources, W, g->vrec, n, bsh, nbk, reinterpret_cast<long long *>(cnt_v), err);
+            // walks per start vertex, counted like the visits: the start list read as a log of
+            // up to 32 rows (per bucket and block in LDS, then bucket order, then a histogram
+            // per bucket), then starts without neighbours cleared and flagged
+            const int32_t srows = (int32_t)std::min<int64_t>(
+                kSortRowsLog, std::max<int64_t>(1, W / kWalkBlock));
+            const int64_t wcs = ((W + srows - 1) / srows + kWalkBlock - 1) / kWalkBlock * kWalkBlock;
+            const int sblk = (int)std::min<int64_t>(nblk, wcs / kWalkBlock);
+            source_bucket_count_kernel<<<sblk, kWalkBlock, sizeof(uint32_t) * nbk, s>>>(
+                p->d_sources, W, srows, wcs, n, bsh, nbk, reinterpret_cast<long long *>(cnt_v), err);
             SABA_HIP_TRY(hipGetLastError());
-            SABA_TRY(bucket_count(p->d_sources, 1, W, nullptr, 0, nblk, bsh, nbk, cnt_v, pos, ctmp,
-                                  part, n, counts, s, g->vrec));
+            SABA_TRY(bucket_count(p->d_sources, srows, wcs, nullptr, 0, sblk, bsh, nbk, cnt_v, pos,
+                                  ctmp, part, n, counts, s, W, true));
+            start_check_kernel<<<(unsigned)std::min<int64_t>((n + kWalkBlock - 1) / kWalkBlock, 1 << 16),
+                                 kWalkBlock, 0, s>>>(g->vrec, n, counts, err);
+            SABA_HIP_TRY(hipGetLastError());
             SABA_TRY(order_walks());
             float walk_ms = 0.f, count_ms = 0.f;
             for (int64_t w0 = 0; w0 < W; w0 += wc) {
@@ -861,9 +937,9 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                 if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
                 if (L > 0)
                     SABA_TRY(bucket_count(vlog, L, this_wc, offs, w0, nblk, bsh, nbk, cnt_v, pos,
-                                          ctmp, part, n, vi, s));
+                                          ctmp, part, n, vi, s, (int64_t)L * this_wc));
                 SABA_TRY(bucket_count(elog, 1, this_wc, offs, w0, nblk, bsh, nbk, cnt_e, pos, ctmp,
-                                      part, n, ep, s));
+                                      part, n, ep, s, this_wc));
                 if (timing) {
                     SABA_HIP_TRY(hipEventRecord(ev.e[3], s));
                     SABA_HIP_TRY(hipEventSynchronize(ev.e[3]));
