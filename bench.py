@@ -509,27 +509,37 @@ def parallel_build(fn, items, label):
     return built
 
 
+def batch_workload(G=256, edges_per_graph=32):
+    """The batched workload's inputs: G graphs (kind k % 3, n uniform in [1e3, 2e5], seed
+    1000 + k), lambda per graph, eps per graph from {0.1, 0.2, 0.3}, and edges_per_graph
+    seeded query edges per graph (int32 [q, 2])."""
+    import graphgen
+    import numpy as np
+    rng = np.random.default_rng(4)
+    specs = [(k % 3, int(rng.integers(1000, 200001)), 1000 + k) for k in range(G)]
+    epss = [float(rng.choice([0.1, 0.2, 0.3])) for _ in range(G)]
+    built = parallel_build(_batch_graph_indexed, specs, "batch workload")
+    graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
+    lams = [lam for _, _, lam in built]
+    qs = []
+    for g in graphs:
+        ce = graphgen.canonical_edges(g)
+        pick = np.sort(rng.choice(g.m, min(g.m, edges_per_graph), replace=False))
+        qs.append(np.ascontiguousarray(ce[pick]))
+    return graphs, lams, epss, qs
+
+
 def bench_batch(args, saba, torch, np):
     """Batched estimation: 256 graphs of uneven size (n uniform in [1e3, 2e5]; one third each
     Erdos-Renyi with average degree 8, Chung-Lu with exponent 2.3, square grids with 5% random
     diagonals), eps drawn from {0.1, 0.2, 0.3}, 32 random query edges per graph, tau capped at
     128.  One saba_aesc_batch call on a multi-graph handle against one saba_aesc_query call per
     graph; both must give identical results."""
-    import graphgen
-    rng = np.random.default_rng(4)
     G = args.batch_graphs
-    specs = [(k % 3, int(rng.integers(1000, 200001)), 1000 + k) for k in range(G)]
-    epss = [float(rng.choice([0.1, 0.2, 0.3])) for _ in range(G)]
     t0 = time.perf_counter()
-    built = parallel_build(_batch_graph_indexed, specs, "batch workload")
+    graphs, lams, epss, qnp = batch_workload(G, args.batch_edges)
     prep_s = time.perf_counter() - t0
-    graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
-    lams = [lam for _, _, lam in built]
-    qs = []
-    for k, g in enumerate(graphs):
-        ce = graphgen.canonical_edges(g)
-        pick = np.sort(rng.choice(g.m, min(g.m, args.batch_edges), replace=False))
-        qs.append(torch.from_numpy(np.ascontiguousarray(ce[pick])).cuda())
+    qs = [torch.from_numpy(q).cuda() for q in qnp]
     nq = sum(int(q.shape[0]) for q in qs)
     # one call per graph (each graph resident in its own handle, uploaded beforehand)
     handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
@@ -629,6 +639,17 @@ def _latency_summary(done, t_start):
             "mean_batches_per_request": float(np.mean([d["batches"] for d in done]))}
 
 
+def serve_workload():
+    """The serving workload's resident graphs: Chung-Lu (average degree 10, exponent 2.5),
+    n_i = round(10^(4 + 2i/15)) for i = 0..15, seeds 1..16, largest components; and lambda per
+    graph."""
+    import graphgen
+    ns = [int(round(10 ** (4 + 2 * i / 15))) for i in range(16)]
+    built = parallel_build(_serve_graph_indexed, [(n, i + 1) for i, n in enumerate(ns)],
+                           "serve workload")
+    return [graphgen.Graph(rp, ci) for rp, ci, _ in built], [lam for _, _, lam in built]
+
+
 def bench_serve(args, saba, torch, np):
     """Serving: 16 resident Chung-Lu graphs (n_i = round(10^(4 + 2i/15)), i = 0..15, seeds
     1..16, largest components), SC query requests of 1-4096 uniformly chosen edges of one
@@ -642,13 +663,9 @@ def bench_serve(args, saba, torch, np):
                  launch) against all of them submitted to the server at once; the results must
                  be identical."""
     import graphgen
-    ns = [int(round(10 ** (4 + 2 * i / 15))) for i in range(16)]
     t0 = time.perf_counter()
-    built = parallel_build(_serve_graph_indexed, [(n, i + 1) for i, n in enumerate(ns)],
-                           "serve workload")
+    graphs, lams = serve_workload()
     prep_s = time.perf_counter() - t0
-    graphs = [graphgen.Graph(rp, ci) for rp, ci, _ in built]
-    lams = [lam for _, _, lam in built]
     ces = [graphgen.canonical_edges(g) for g in graphs]
     mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
     budget = int(args.serve_mem_gib * (1 << 30))

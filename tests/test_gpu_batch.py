@@ -123,3 +123,30 @@ def test_batch_errors(saba, graphs):
     # still usable
     outs, _ = saba.aesc_batch(mg, [{"graph": 0, "eps": 0.2, "lam": lams[2], "seed": 1, "m": 5}])
     assert outs[0].numel() == 5
+
+
+def test_config4_full_size_sampled_edges_match_oracle(saba, orc):
+    """The batched benchmark's workload at full size (256 graphs, 26 million vertices, 32 query
+    edges each, tau capped at 128) in its launch configuration: one saba_aesc_batch call with
+    the grids autotuned on every 16th request.  Requests of several graphs of each kind equal the
+    same request run alone, and 8 edges of the median-size graph of each kind match the oracle
+    (Alg. 1 on that graph, those edges only)."""
+    import torch
+    import bench
+    print("config 4 full size: building 256 graphs", flush=True)
+    graphs, lams, epss, qnp = bench.batch_workload(256, 32)
+    mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    reqs = [{"graph": k, "eps": epss[k], "lam": lams[k], "seed": 1,
+             "edges": torch.from_numpy(qnp[k]).cuda(), "tau_cap": 128} for k in range(len(graphs))]
+    saba.autotune_aesc(mg, reqs[::16])
+    outs, _ = saba.aesc_batch(mg, reqs)
+    for k in (0, 1, 2, 127, 128, 129, 253, 254, 255):
+        alone = _alone(saba, graphs[k], lams[k], epss[k], 1, edges=qnp[k], tau_cap=128)
+        assert np.array_equal(outs[k].cpu().numpy(), alone), k
+    sel = list(range(0, 32, 4))
+    for kind in range(3):
+        ks = [k for k in range(len(graphs)) if k % 3 == kind]
+        k = sorted(ks, key=lambda j: graphs[j].n)[len(ks) // 2]
+        print(f"config 4 oracle: graph {k} kind {kind} n={graphs[k].n} eps={epss[k]}", flush=True)
+        so, _ = orc.aesc(graphs[k], epss[k], lams[k], 1, query=qnp[k][sel], tau_cap=128)
+        np.testing.assert_allclose(outs[k].cpu().numpy()[sel], so, rtol=1e-12, atol=1e-15)

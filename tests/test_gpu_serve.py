@@ -188,3 +188,43 @@ def test_destroy_with_requests_in_flight(saba, graphs):
     sg = saba.SabaGraph.from_graph(gs[3])
     sc, _ = saba.aesc_query(sg, e, 0.2, lams[3], 1)
     assert sc.numel() == 2
+
+
+def test_config5_full_size_served_match_alone_and_oracle(saba, orc):
+    """The serving benchmark's 16 resident graphs at full size (Chung-Lu, n = 10^4 .. 10^6) under
+    its server settings (2 lanes, 32 GiB of source scratch): a burst of 16 requests of 1-512
+    edges (one of them on the 10^6-vertex graph) served together equals each request run alone,
+    and 6 edges of the largest graph's request and of another match the oracle."""
+    import os
+    import torch
+    import bench
+    print("config 5 full size: building 16 graphs", flush=True)
+    gs, lams = bench.serve_workload()
+    ces = [graphgen.canonical_edges(g) for g in gs]
+    rng = np.random.default_rng(11)
+    reqs = []
+    for j in range(16):
+        k = 15 if j == 0 else int(rng.integers(len(gs)))
+        q = int(rng.integers(1, 513))
+        pick = np.sort(rng.choice(ces[k].shape[0], q, replace=False))
+        reqs.append({"graph": k, "edges": np.ascontiguousarray(ces[k][pick]),
+                     "eps": float(rng.choice([0.1, 0.2, 0.3])), "seed": 1, "tau_cap": 4096})
+    mg = saba.SabaGraph.from_graphs(gs, trusted=True)
+    with saba.SabaServer(mg, lanes=2, mem_budget=32 << 30) as srv:
+        tickets = [_submit(srv, lams, r) for r in reqs]
+        served = [srv.wait(t)[0].cpu().numpy() for t in tickets]
+    handles = {}
+    for r, sc in zip(reqs, served):
+        k = r["graph"]
+        if k not in handles:
+            handles[k] = saba.SabaGraph.from_graph(gs[k], trusted=True)
+        alone, _ = saba.aesc_query(handles[k], torch.from_numpy(r["edges"]).cuda(), r["eps"],
+                                   lams[k], 1, tau_cap=4096)
+        assert np.array_equal(sc, alone.cpu().numpy()), k
+    for j in (0, 1):
+        r = reqs[j]
+        sel = np.arange(min(6, r["edges"].shape[0]))
+        print(f"config 5 oracle: graph {r['graph']} n={gs[r['graph']].n} eps={r['eps']}", flush=True)
+        so, _ = orc.aesc(gs[r["graph"]], r["eps"], lams[r["graph"]], 1, query=r["edges"][sel],
+                         tau_cap=4096, nthreads=min(16, os.cpu_count() or 1))
+        np.testing.assert_allclose(served[j][sel], so, rtol=1e-12, atol=1e-15)
