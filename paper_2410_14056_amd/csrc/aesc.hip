@@ -312,29 +312,45 @@ constexpr int kPullWin = 4;     // 64-entry chunks per pass of the ordinary-row 
 __global__ __launch_bounds__(1024) void group_scan_kernel(const BatchState *__restrict__ bs,
                                                           int32_t nb, int parity,
                                                           int64_t *__restrict__ gofs) {
+    // tiles of kTile slots: their group counts are staged in LDS (consecutive threads read
+    // consecutive slot records), then each thread scans kTile / 1024 consecutive counts
+    constexpr int kTile = 8192, kPer = kTile / 1024;
+    __shared__ uint32_t cnt[kTile];
     __shared__ long long wtot[16];
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const int32_t per = (nb + 1023) / 1024;
-    const int32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
-    auto groups = [&](int32_t b) -> long long {
-        return bs[b].active ? ((long long)bs[b].fsz[parity] + 63) / 64 : 0;
-    };
-    long long loc = 0;
-    for (int32_t b = b0; b < b1; ++b) loc += groups(b);
-    long long inc = loc;
-    for (int o = 1; o < 64; o <<= 1) {
-        const long long t = __shfl_up(inc, o);
-        if (lane >= o) inc += t;
+    long long carry = 0;
+    for (int32_t t0 = 0; t0 < nb; t0 += kTile) {
+        const int32_t tn = min(kTile, nb - t0);
+        for (int32_t i = tid; i < tn; i += 1024) {
+            const BatchState &x = bs[t0 + i];
+            cnt[i] = x.active ? (uint32_t)(((long long)x.fsz[parity] + 63) / 64) : 0u;
+        }
+        __syncthreads();
+        const int32_t i0 = tid * kPer;
+        long long loc = 0;
+        for (int k = 0; k < kPer; ++k)
+            if (i0 + k < tn) loc += cnt[i0 + k];
+        long long inc = loc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) wtot[wave] = inc;
+        __syncthreads();
+        long long run = carry + inc - loc, tile_total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wave) run += wtot[k];
+            tile_total += wtot[k];
+        }
+        for (int k = 0; k < kPer; ++k)
+            if (i0 + k < tn) {
+                gofs[t0 + i0 + k] = run;
+                run += cnt[i0 + k];
+            }
+        carry += tile_total;
+        __syncthreads();  // cnt and wtot are rewritten by the next tile
     }
-    if (lane == 63) wtot[wave] = inc;
-    __syncthreads();
-    long long run = inc - loc;
-    for (int k = 0; k < wave; ++k) run += wtot[k];
-    for (int32_t b = b0; b < b1; ++b) {
-        gofs[b] = run;
-        run += groups(b);
-    }
-    if (tid == 1023) gofs[nb] = run;
+    if (tid == 0) gofs[nb] = carry;
 }
 
 struct GroupCursor {  // the slot of the current group of a wavefront (all fields wave-uniform)
@@ -733,6 +749,34 @@ __global__ __launch_bounds__(kBlock) void clear_level_kernel(
         const int32_t x = F[i] - sl.goff;
         h[x] = 0.0;
         bm[x >> 5] = 0u;
+    }
+}
+
+// The end of a level: h and the support bitmap of parity `parity` cleared over the frontier of
+// every active slot, by the frontier groups numbered in gofs (the same groups as the level's
+// expansion), so the work follows the frontiers rather than the number of slots.
+__global__ __launch_bounds__(kBlock) void clear_groups_kernel(
+    const Slot *__restrict__ slots, const BatchState *__restrict__ bs, int32_t nb, int parity,
+    const int64_t *__restrict__ gofs, double *__restrict__ h_all, uint32_t *__restrict__ bm_all,
+    const int32_t *__restrict__ F_all) {
+    const int lane = __lane_id();
+    int64_t first, stride, total;
+    wave_groups(gofs, nb, first, stride, total);
+    GroupCursor gc;
+    Slot sl{};
+    int32_t fsz = 0;
+    for (int64_t gi = first; gi < total; gi += stride) {
+        if (gi >= gc.gnext) {
+            group_seek(gc, gofs, nb, gi);
+            sl = slots[gc.b];
+            fsz = bs[gc.b].fsz[parity];
+        }
+        const int64_t i = (gi - gc.gbase) * 64 + lane;
+        if (i < fsz) {
+            const int32_t x = F_all[sl.hoff + i] - sl.goff;
+            h_all[sl.hoff + x] = 0.0;
+            bm_all[sl.bmoff + (x >> 5)] = 0u;
+        }
     }
 }
 
@@ -1158,8 +1202,8 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
                                                  gofs_nxt, hcur, bmcur, hnext, Fnext, fl);
         pull_hub_kernel<<<kHubGrid, kBlock, 0, s>>>(g->vrec, g->col_idx, d_slots, bs, level, hubs,
                                                     hubcap, hcur, slotbm, hnext, fl);
-        clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, cur, true, hA, hB, bmA, bmB, FA,
-                                                   FB);
+        clear_groups_kernel<<<push_blocks, kBlock, 0, s>>>(d_slots, bs, nb, cur, gofs_cur, hcur,
+                                                            bmcur, Fcur);
         SABA_HIP_TRY(hipGetLastError());
     }
     // walk pairs of the batch's instance edges
@@ -1285,13 +1329,11 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     };
 
     // instances: per parameter set, every vertex of its graph (an all-edges request) or the
-    // endpoints of its query pairs; the instance list is ordered by (parameter set, vertex)
+    // distinct endpoints of its query pairs; the instance list is ordered by (parameter set,
+    // vertex).  Query-only sets keep their endpoints as a sorted list, so the set-up costs
+    // O(q log q) per set, not a pass over the graph's vertices.
     std::vector<uint8_t> pall(P, 0);
-    std::vector<std::vector<uint8_t>> mark(P);
-    for (int32_t k = 0; k < P; ++k) {
-        const int32_t gn = g->goff[pgraph[k] + 1] - g->goff[pgraph[k]];
-        mark[k].assign(gn, 0);
-    }
+    std::vector<std::vector<int32_t>> pverts(P);
     for (size_t i = 0; i < reqs.size(); ++i) {
         const Request &r = reqs[i];
         const int32_t ga = g->goff[r.graph], gn = g->goff[r.graph + 1] - ga;
@@ -1305,29 +1347,41 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
                 set_error("a query pair is not an edge of the graph");
                 return SABA_E_NOT_EDGE;
             }
-            mark[r.pid][u] = 1;
-            mark[r.pid][v] = 1;
+            pverts[r.pid].push_back(u);
+            pverts[r.pid].push_back(v);
         }
     }
     std::vector<int32_t> inst_v, inst_p;
     std::vector<int64_t> iebase;
-    std::vector<std::vector<int32_t>> inst_of(P);
-    std::vector<int64_t> pbase(P, 0);
+    std::vector<int64_t> pbase(P, 0), pfirst(P, 0);
     int64_t NE = 0;
     for (int32_t k = 0; k < P; ++k) {
         const int32_t ga = g->goff[pgraph[k]];
-        const int32_t gn = (int32_t)mark[k].size();
-        inst_of[k].assign(gn, -1);
+        const int32_t gn = g->goff[pgraph[k] + 1] - ga;
         pbase[k] = NE;
-        for (int32_t x = 0; x < gn; ++x) {
-            if (!pall[k] && !mark[k][x]) continue;
-            inst_of[k][x] = (int32_t)inst_v.size();
+        pfirst[k] = (int64_t)inst_v.size();
+        const auto add = [&](int32_t x) {
             inst_v.push_back(ga + x);
             inst_p.push_back(k);
             iebase.push_back(NE);
             NE += rp[ga + x + 1] - rp[ga + x];
+        };
+        if (pall[k]) {
+            pverts[k].clear();
+            for (int32_t x = 0; x < gn; ++x) add(x);
+        } else {
+            std::vector<int32_t> &pv = pverts[k];
+            std::sort(pv.begin(), pv.end());
+            pv.erase(std::unique(pv.begin(), pv.end()), pv.end());
+            for (const int32_t x : pv) add(x);
         }
     }
+    // the instance of graph-local vertex x in parameter set k (x an instance vertex of k)
+    const auto inst_of = [&](int32_t k, int32_t x) -> int64_t {
+        if (pall[k]) return pfirst[k] + x;
+        const std::vector<int32_t> &pv = pverts[k];
+        return pfirst[k] + (std::lower_bound(pv.begin(), pv.end(), x) - pv.begin());
+    };
     const int64_t ns = (int64_t)inst_v.size();
     iebase.push_back(NE);
 
@@ -1347,8 +1401,8 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         for (int64_t j = 0; j < r.q; ++j) {
             const int32_t u = hq[i][2 * j], v = hq[i][2 * j + 1];
             const int32_t euv = find_pos(ga + u, ga + v), evu = find_pos(ga + v, ga + u);
-            const int64_t a = iebase[inst_of[r.pid][u]] + (euv - rp[ga + u]);
-            const int64_t b = iebase[inst_of[r.pid][v]] + (evu - rp[ga + v]);
+            const int64_t a = iebase[inst_of(r.pid, u)] + (euv - rp[ga + u]);
+            const int64_t b = iebase[inst_of(r.pid, v)] + (evu - rp[ga + v]);
             want[a] = want[b] = 1;
             qpairs[i][2 * j] = a;
             qpairs[i][2 * j + 1] = b;
