@@ -382,13 +382,20 @@ __device__ __forceinline__ void expand_entry(const int32_t *__restrict__ col,
                                              const int32_t *__restrict__ slotv, const Slot &sl,
                                              uint32_t *__restrict__ bm, uint32_t *__restrict__ sbm,
                                              int32_t e) {
-    const int32_t x = col[e] - sl.goff;
-    atomicOr(bm + (x >> 5), 1u << (x & 31));
+    // Bits only go from 0 to 1 while the support is built, so a read that already sees the bit
+    // set makes the atomic OR redundant; a read that misses a bit set meanwhile (by another
+    // compute unit, or an older cached copy) only costs the OR.  The read is a relaxed atomic
+    // at workgroup scope: it may be served by this compute unit's cache.  Most bits are
+    // reached from several frontier vertices.
+    const auto set_bit = [](uint32_t *words, int32_t i) {
+        uint32_t *w = words + (i >> 5);
+        const uint32_t bit = 1u << (i & 31);
+        if (!(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & bit))
+            atomicOr(w, bit);
+    };
+    set_bit(bm, col[e] - sl.goff);
     const int32_t slot = slotv[e];
-    if (slot >= 0) {
-        const int32_t ls = slot - sl.gpos;
-        atomicOr(sbm + (ls >> 5), 1u << (ls & 31));
-    }
+    if (slot >= 0) set_bit(sbm, slot - sl.gpos);
 }
 
 __global__ __launch_bounds__(kBlock) void expand_kernel(
