@@ -736,17 +736,16 @@ __global__ __launch_bounds__(kBlock) void pull_hub_kernel(
     if (lane == 0 && visits) atomicAdd(&fl->push_visits, visits);
 }
 
-// After a level: zero h_l and its support bitmap over the support, so both are clean when the
-// buffers are reused for level l + 2.  (Every set bit of a touched bitmap word belongs to the
-// support, so the whole word is cleared.)  parity < 0 clears each slot's final level.
-__global__ __launch_bounds__(kBlock) void clear_level_kernel(
-    const Slot *__restrict__ slots, const BatchState *__restrict__ bs, int parity,
-    bool only_active, double *__restrict__ hA, double *__restrict__ hB, uint32_t *__restrict__ bmA,
-    uint32_t *__restrict__ bmB, const int32_t *__restrict__ FA, const int32_t *__restrict__ FB) {
+// The end of a batch: zero h_ttau and its support bitmap over the final support of every
+// slot (the buffers of the slot's last level), so the scratch is clean for the next batch.
+// Every set bit of a touched bitmap word belongs to the support, so the whole word is cleared.
+__global__ __launch_bounds__(kBlock) void clear_final_kernel(
+    const Slot *__restrict__ slots, const BatchState *__restrict__ bs, double *__restrict__ hA,
+    double *__restrict__ hB, uint32_t *__restrict__ bmA, uint32_t *__restrict__ bmB,
+    const int32_t *__restrict__ FA, const int32_t *__restrict__ FB) {
     const int64_t b = blockIdx.y;
-    if (only_active && !bs[b].active) return;
     const Slot sl = slots[b];
-    const int pb = parity < 0 ? bs[b].finalbuf : parity;
+    const int pb = bs[b].finalbuf;
     double *h = (pb ? hB : hA) + sl.hoff;
     uint32_t *bm = (pb ? bmB : bmA) + sl.bmoff;
     const int32_t *F = (pb ? FB : FA) + sl.hoff;
@@ -759,9 +758,10 @@ __global__ __launch_bounds__(kBlock) void clear_level_kernel(
     }
 }
 
-// The end of a level: h and the support bitmap of parity `parity` cleared over the frontier of
-// every active slot, by the frontier groups numbered in gofs (the same groups as the level's
-// expansion), so the work follows the frontiers rather than the number of slots.
+// The end of a level: h_l and its support bitmap (parity `parity`) cleared over the frontier of
+// every active slot, so both are clean when the buffers are reused for level l + 2.  The work
+// goes by the frontier groups numbered in gofs (the level's expansion groups), so it follows
+// the frontiers rather than the number of slots.
 __global__ __launch_bounds__(kBlock) void clear_groups_kernel(
     const Slot *__restrict__ slots, const BatchState *__restrict__ bs, int32_t nb, int parity,
     const int64_t *__restrict__ gofs, double *__restrict__ h_all, uint32_t *__restrict__ bm_all,
@@ -1247,7 +1247,7 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     edge_reduce_kernel<<<grid_for(nle, kBlock, 1 << 16), kBlock, 0, s>>>(
         g->vrec, d_slots, nb, d_eb, ie0, coff, nle, ea.want, ea.nreq, ea.D, partial, ea.MC, ea.g);
     // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
-    clear_level_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, -1, false, hA, hB, bmA, bmB, FA, FB);
+    clear_final_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, hA, hB, bmA, bmB, FA, FB);
     SABA_HIP_TRY(hipGetLastError());
     ws.clean = true;
     return SABA_OK;

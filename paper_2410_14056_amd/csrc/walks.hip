@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] = pos[(int64_t)b * gridDim.x + blockIdx.x];
     const int64_t valid = rows <= 0 ? 0 : offs ? min(wc, offs[n] - w0) : wc;
     // The block's groups in order: tile blockIdx.x, blockIdx.x + gridDim.x, ..., and within a
-    // tile rows 0-15, 16-31, ...  The entries of the next group are loaded before the current
+    // tile kSortRows rows at a time.  The entries of the next group are loaded before the current
     // one is sorted, so their memory round trip overlaps the LDS passes (the barriers wait for
     // LDS operations only).
     int64_t tile = blockIdx.x;
