@@ -264,6 +264,46 @@ def bench_ablation(args, saba, torch, np):
             "rows": rows}
 
 
+def bench_walks_paper(args, saba, torch, np):
+    """The shape of the paper's walk-generation experiment (its Table 7): a fixed number of walks
+    from every non-isolated vertex of the walk benchmark graph, 15 and 5 steps, naive order
+    against bouquet order (G = 1) and grouped bouquets (G = 64).  The paper reports the speed-up
+    of its SABA arrangement over naive generation; this is the same ratio on the GPU."""
+    import graphgen
+    g = graphgen.rmat(args.scale, 16, 0.57, 0.19, 0.19, 1)
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    pool = torch.from_numpy(np.flatnonzero(np.diff(g.row_ptr) > 0).astype(np.int32)).cuda()
+    ep = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    vi = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    NV, BQ = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET
+    arrangements = [("naive", NV, 1, 0), ("bouquet G=1", BQ, 1, 0),
+                    ("bouquet G=64 S=20", BQ, 64, 20), ("bouquet G=64 S=12", BQ, 64, 12)]
+    rows = []
+    for per_vertex, L in ((args.paper_walks, 15), (args.paper_walks, 5)):
+        src = torch.repeat_interleave(pool, per_vertex)  # every start, in vertex order
+        W = int(src.numel())
+        for name, mode, G, S in arrangements:
+            progress(f"walks_paper: {per_vertex} walks/vertex x {L} steps, {name}")
+            saba.walks(sg, src, L, 1, group=G, spread=S, mode=mode, endpoint=ep, visits=vi)
+            torch.cuda.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                saba.walks(sg, src, L, 1, group=G, spread=S, mode=mode, endpoint=ep, visits=vi)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            assert int(vi.sum().item()) == W * L and int(ep.sum().item()) == W
+            rows.append({"walks_per_vertex": per_vertex, "steps": L, "walks": W,
+                         "arrangement": name, "seconds": dt, "walk_steps_per_s": W * L / dt})
+        del src
+        torch.cuda.empty_cache()
+    for r in rows:
+        base = next(x for x in rows if x["steps"] == r["steps"] and x["arrangement"] == "naive")
+        r["speedup_vs_naive"] = base["seconds"] / r["seconds"]
+    return {"workload": f"rmat{args.scale}_ef16_every_vertex_x{args.paper_walks}_walks",
+            "starts": int(pool.numel()), "rows": rows}
+
+
 def bench_aesc(args, saba, torch, np):
     import graphgen
     t0 = time.perf_counter()
@@ -846,9 +886,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
                     choices=["all", "walks", "aesc", "aesc_full", "c1", "batch", "serve", "ablation",
-                             "omega", "copy"],
+                             "omega", "copy", "walks_paper"],
                     default="all")
     ap.add_argument("--batch-graphs", type=int, default=256)
+    ap.add_argument("--paper-walks", type=int, default=2048,
+                    help="walks per non-isolated vertex in --workload walks_paper")
     ap.add_argument("--batch-edges", type=int, default=32)
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--serve-mem-gib", type=float, default=32.0)
@@ -934,6 +976,13 @@ def main():
         head = next(r for r in a["rows"] if "headline" in r["name"])
         out.update({"value": head["walk_steps_per_s"], "ms_per_step": head["ms_per_step"],
                     "config": {"workload": a["workload"]}, "ablation": a})
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "walks_paper":
+        a = bench_walks_paper(args, saba, torch, np)
+        head = next(r for r in a["rows"] if r["steps"] == 15 and r["arrangement"] == "bouquet G=1")
+        out.update({"value": head["walk_steps_per_s"], "ms_per_step": head["seconds"] * 1e3,
+                    "config": {"workload": a["workload"]}, "walks_paper": a})
         print(json.dumps(out), flush=True)
         return
     if args.workload == "omega":
