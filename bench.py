@@ -844,8 +844,8 @@ def bench_serve(args, saba, torch, np):
     return res
 
 
-def bench_c1(args, saba, torch, np):
-    """Config 1: all edges of ER n=2000, m=8000, seed 1 (largest component), eps=0.3, plain walks."""
+def bench_er2000(args, saba, torch, np):
+    """All edges of ER n=2000, m=8000, seed 1 (largest component), eps=0.3, plain walks."""
     import graphgen
     g = graphgen.largest_component(graphgen.er_gnm(2000, 8000, 1))
     lam = graphgen.spectral_lambda(g)
@@ -885,7 +885,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
-                    choices=["all", "walks", "aesc", "aesc_full", "c1", "batch", "serve", "ablation",
+                    choices=["all", "walks", "aesc", "aesc_full", "er2000", "batch", "serve", "ablation",
                              "omega", "copy", "walks_paper"],
                     default="all")
     ap.add_argument("--batch-graphs", type=int, default=256)
@@ -1001,12 +1001,12 @@ def main():
                     "p50_ms": sus.get("p50_ms"), "p99_ms": sus.get("p99_ms"), "serve": r})
         print(json.dumps(out), flush=True)
         return
-    if args.workload in ("all", "c1"):
-        out["c1"] = bench_c1(args, saba, torch, np)
-        if args.workload == "c1":
-            out.update({"value": out["c1"]["edges_per_s"], "unit": "edges/s", "dtype": "f64",
-                        "ms_per_step": out["c1"]["latency_ms_median"],
-                        "config": {"workload": out["c1"]["workload"]}})
+    if args.workload in ("all", "er2000"):
+        out["er2000"] = bench_er2000(args, saba, torch, np)
+        if args.workload == "er2000":
+            out.update({"value": out["er2000"]["edges_per_s"], "unit": "edges/s", "dtype": "f64",
+                        "ms_per_step": out["er2000"]["latency_ms_median"],
+                        "config": {"workload": out["er2000"]["workload"]}})
     if args.workload in ("all", "aesc"):
         a = bench_aesc(args, saba, torch, np)
         out["aesc"] = a

@@ -137,7 +137,7 @@ def test_toy_graph(saba, orc):
     assert np.max(np.abs(sc.cpu().numpy() - np.array([0.625, 0.625, 0.5, 0.625, 0.625]))) <= 0.05
 
 
-def test_config1_parity_and_eps(saba, orc):
+def test_er2000_parity_and_eps(saba, orc):
     # ER n=2000, m=8000, seed 1, largest component, eps=0.3, plain (G = 1) walks
     g = graphgen.largest_component(graphgen.er_gnm(2000, 8000, 1))
     lam = graphgen.spectral_lambda(g)
@@ -147,7 +147,7 @@ def test_config1_parity_and_eps(saba, orc):
     _compare(o_gpu, o_orc, o_gpu["sc"].cpu().numpy(), sc_o)
     ex = exact_sc.sc_pinv(g.row_ptr, g.col_idx, g.n)
     err = np.abs(o_gpu["sc"].cpu().numpy() - ex)
-    print(f"config1: max err {err.max():.4g} mean {err.mean():.4g} sum {o_gpu['sc'].sum().item():.2f}"
+    print(f"er2000: max err {err.max():.4g} mean {err.mean():.4g} sum {o_gpu['sc'].sum().item():.2f}"
           f" (n-1={g.n - 1}) steps {st['walk_steps']}", flush=True)
     assert err.max() <= 0.3
 
@@ -196,7 +196,7 @@ def test_chung_lu_query_matches_oracle(saba, orc):
     np.testing.assert_allclose(sq.cpu().numpy(), so, rtol=RTOL, atol=1e-15)
 
 
-def test_config3_sampled_edges_match_oracle(saba, orc):
+def test_chung_lu_1e6_query_sampled_edges_match_oracle(saba, orc):
     """The 10^6-vertex Chung-Lu graph at eps = 0.1 in the benchmark's launch configuration (the
     1% query with the default source scratch): 24 of its edges, computed by the oracle on their
     own, equal the GPU's entries (a query's entries do not depend on the other pairs)."""
@@ -208,7 +208,7 @@ def test_config3_sampled_edges_match_oracle(saba, orc):
     perm = np.random.default_rng(7).permutation(g.m)
     k = int(round(0.01 * g.m))
     q = np.ascontiguousarray(ce[np.sort(perm[:k])])
-    print(f"config3 sampled parity n={g.n} m={g.m} q={k}", flush=True)
+    print(f"chung-lu 1e6 sampled parity n={g.n} m={g.m} q={k}", flush=True)
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     sq, st = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.1, lam, 1)
     pick = np.sort(np.random.default_rng(3).choice(k, 24, replace=False))

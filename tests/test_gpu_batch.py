@@ -125,7 +125,7 @@ def test_batch_errors(saba, graphs):
     assert outs[0].numel() == 5
 
 
-def test_config4_full_size_sampled_edges_match_oracle(saba, orc):
+def test_256_graph_batch_full_size_sampled_edges_match_oracle(saba, orc):
     """The batched benchmark's workload at full size (256 graphs, 26 million vertices, 32 query
     edges each, tau capped at 128) in its launch configuration: one saba_aesc_batch call with
     the grids autotuned on every 16th request.  Requests of several graphs of each kind equal the
@@ -133,7 +133,7 @@ def test_config4_full_size_sampled_edges_match_oracle(saba, orc):
     (Alg. 1 on that graph, those edges only)."""
     import torch
     import bench
-    print("config 4 full size: building 256 graphs", flush=True)
+    print("256-graph batch at full size: building the graphs", flush=True)
     graphs, lams, epss, qnp = bench.batch_workload(256, 32)
     mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
     reqs = [{"graph": k, "eps": epss[k], "lam": lams[k], "seed": 1,
@@ -147,6 +147,6 @@ def test_config4_full_size_sampled_edges_match_oracle(saba, orc):
     for kind in range(3):
         ks = [k for k in range(len(graphs)) if k % 3 == kind]
         k = sorted(ks, key=lambda j: graphs[j].n)[len(ks) // 2]
-        print(f"config 4 oracle: graph {k} kind {kind} n={graphs[k].n} eps={epss[k]}", flush=True)
+        print(f"256-graph batch, oracle check: graph {k} kind {kind} n={graphs[k].n} eps={epss[k]}", flush=True)
         so, _ = orc.aesc(graphs[k], epss[k], lams[k], 1, query=qnp[k][sel], tau_cap=128)
         np.testing.assert_allclose(outs[k].cpu().numpy()[sel], so, rtol=1e-12, atol=1e-15)

@@ -190,7 +190,7 @@ def test_destroy_with_requests_in_flight(saba, graphs):
     assert sc.numel() == 2
 
 
-def test_config5_full_size_served_match_alone_and_oracle(saba, orc):
+def test_16_graph_server_full_size_served_match_alone_and_oracle(saba, orc):
     """The serving benchmark's 16 resident graphs at full size (Chung-Lu, n = 10^4 .. 10^6) under
     its server settings (2 lanes, 32 GiB of source scratch): a burst of 16 requests of 1-512
     edges (one of them on the 10^6-vertex graph) served together equals each request run alone,
@@ -198,7 +198,7 @@ def test_config5_full_size_served_match_alone_and_oracle(saba, orc):
     import os
     import torch
     import bench
-    print("config 5 full size: building 16 graphs", flush=True)
+    print("16-graph server at full size: building the graphs", flush=True)
     gs, lams = bench.serve_workload()
     ces = [graphgen.canonical_edges(g) for g in gs]
     rng = np.random.default_rng(11)
@@ -224,7 +224,7 @@ def test_config5_full_size_served_match_alone_and_oracle(saba, orc):
     for j in (0, 1):
         r = reqs[j]
         sel = np.arange(min(6, r["edges"].shape[0]))
-        print(f"config 5 oracle: graph {r['graph']} n={gs[r['graph']].n} eps={r['eps']}", flush=True)
+        print(f"16-graph server, oracle check: graph {r['graph']} n={gs[r['graph']].n} eps={r['eps']}", flush=True)
         so, _ = orc.aesc(gs[r["graph"]], r["eps"], lams[r["graph"]], 1, query=r["edges"][sel],
                          tau_cap=4096, nthreads=min(16, os.cpu_count() or 1))
         np.testing.assert_allclose(served[j][sel], so, rtol=1e-12, atol=1e-15)

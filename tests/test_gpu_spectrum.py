@@ -236,14 +236,14 @@ def test_omega_errors(saba):
         assert ei.value.name == "SABA_E_INVALID"
 
 
-def test_spectrum_config3_graph(saba):
+def test_spectrum_chung_lu_1e6(saba):
     """The 10^6-vertex graph of the estimator benchmark: eight pairs converge, the rest of the
     spectrum is smaller than lambda, and every kept |theta| is at least the rest's radius."""
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     r = saba.graph_spectrum(sg, 8, vectors=False)
     lam = saba.graph_lambda(sg, max_iters=1000)
-    print(f"spectrum config3 {dict((k, v) for k, v in r.items() if k != 'vectors')} "
+    print(f"spectrum chung-lu 1e6 {dict((k, v) for k, v in r.items() if k != 'vectors')} "
           f"lambda={lam['lambda']}", flush=True)
     assert r["converged"] == 1 and r["pairs"] == 8
     assert abs(abs(r["values"][0]) - lam["lambda"]) < 1e-8

@@ -86,7 +86,7 @@ def test_chung_lu_follows_its_weights():
     assert 9.5 < deg.mean() <= 10.0
 
 
-def test_config3_graph_figures():
+def test_chung_lu_1e6_graph_figures():
     """The 10^6-vertex Chung-Lu graph of the estimator benchmark (seed 1): its largest
     component has the vertex and edge counts stated with the workload."""
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))

@@ -99,7 +99,7 @@ def test_tilde_tau_cap_and_seed_sensitivity(orc):
 
 
 @pytest.mark.slow
-def test_config1_eps_contract(orc):
+def test_er2000_eps_contract(orc):
     # ER n=2000, m=8000, seed 1, largest component, eps=0.3, plain walks
     g = graphgen.largest_component(graphgen.er_gnm(2000, 8000, 1))
     lam = graphgen.spectral_lambda(g)
