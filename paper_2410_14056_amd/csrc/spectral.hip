@@ -432,19 +432,33 @@ int lanczos_extremes(const SpecOp &op, const double *x, int32_t nx, int32_t max_
     const hipStream_t s = op.s;
     const int K = std::max(4, std::min(max_iters, gn - 1));
     DevBuf buf;
-    SABA_TRY(buf.ensure(sizeof(double) * ((size_t)gn * 3 + 2 * (size_t)K + 4)));
+    // vectors, the tridiagonal coefficients, and the partial and final dots of the projection
+    // against x
+    const size_t nxd = nx > 0 ? (size_t)nx * (kDotBlocks + 1) : 0;
+    SABA_TRY(buf.ensure(sizeof(double) * ((size_t)gn * 3 + 2 * (size_t)K + 4 + nxd)));
     struct Guard {
         DevBuf *b;
         ~Guard() { b->release(); }
     } guard{&buf};
     double *vprev = buf.as<double>(), *v = vprev + gn, *w = v + gn;
     double *alpha = w + gn, *beta = alpha + K + 2;  // beta[j]: off-diagonal before v_j
+    double *xpart = beta + K + 2, *xh = xpart + (size_t)nx * kDotBlocks;
     SABA_HIP_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * (2 * (size_t)K + 4), s));
     SABA_HIP_TRY(hipMemsetAsync(vprev, 0, sizeof(double) * gn, s));
     const unsigned grid = op.grid;
+    // y = y - X (X^T y), twice (classical Gram-Schmidt with one reorthogonalisation pass):
+    // the nx dots in one launch, the update in another, instead of nx sequential projections
+    auto project_x = [&](double *y) {
+        if (nx <= 0) return;
+        for (int rep = 0; rep < 2; ++rep) {
+            spec_mdot_kernel<<<dim3(kDotBlocks, nx), kBlk, 0, s>>>(gn, x, y, xpart);
+            spec_mdot_final_kernel<<<nx, 64, 0, s>>>(xpart, xh);
+            spec_mupdate_kernel<<<grid, kBlk, 0, s>>>(gn, x, nx, xh, y);
+        }
+    };
     auto deflate = [&](double *y) {
         op.project(op.u1, y);
-        for (int32_t k = 0; k < nx; ++k) op.project(x + (int64_t)k * gn, y);
+        project_x(y);
     };
     // w = start with u1 (and x) projected out; v = w / |w|
     spec_start_kernel<<<grid, kBlk, 0, s>>>(gn, seed, w);
@@ -461,7 +475,7 @@ int lanczos_extremes(const SpecOp &op, const double *x, int32_t nx, int32_t max_
     for (int j = 0; j < K; ++j) {
         // w = N' v with x projected out
         op.apply(v, w);
-        for (int32_t q = 0; q < nx; ++q) op.project(x + (int64_t)q * gn, w);
+        project_x(w);
         // alpha_j = w . v ; w = w - alpha_j v - beta_j vprev
         op.dot(w, v, alpha + j);
         spec_lanczos_update_kernel<<<grid, kBlk, 0, s>>>(gn, alpha + j, beta + j, v, vprev, w);
