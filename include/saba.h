@@ -400,6 +400,11 @@ int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
  *   d_visits[n] (int64): visits at positions 1..L.
  *   Both outputs are overwritten (the library clears them on `stream`).
  *   stats may be NULL.
+ *   Errors (SABA_E_INVALID; the outputs are then unspecified and the handle stays usable):
+ *   a start outside 0 .. n-1 or on an isolated vertex, anywhere in the list; n_walks < 0,
+ *   L < 0, G = 0, S > 31 or (G - 1) << S beyond 32 bits; an unknown mode, sampler or source
+ *   mode; a null output or source array; n_walks >= 2^31 in naive order.  SABA_E_OVERFLOW:
+ *   n_walks * max(L, 1) >= 2^62.
  */
 int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, int64_t *d_visits,
                saba_stats *stats, void *stream);
