@@ -42,7 +42,7 @@ extern "C" {
 #define SABA_E_DISCONNECTED (-5) /* the estimator needs a connected graph */
 #define SABA_E_BIPARTITE (-6)    /* the estimator needs a non-bipartite graph (lambda < 1) */
 #define SABA_E_NOT_EDGE (-7)     /* a query pair is not an edge of the graph */
-#define SABA_E_OVERFLOW (-8)     /* a walk count exceeds the 64-bit range */
+#define SABA_E_OVERFLOW (-8)     /* a walk count exceeds its range (2^32 - 1 pairs per edge, 2^32 - 1 walks) */
 #define SABA_E_NODEVICE (-9)     /* no usable gfx950 device */
 #define SABA_E_BUSY (-10)        /* the server's admission queue is full (backpressure) */
 #define SABA_E_TIMEOUT (-11)     /* a server request has not finished within the wait */
@@ -404,7 +404,8 @@ int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
  *   a start outside 0 .. n-1 or on an isolated vertex, anywhere in the list; n_walks < 0,
  *   L < 0, G = 0, S > 31 or (G - 1) << S beyond 32 bits; an unknown mode, sampler or source
  *   mode; a null output or source array; n_walks >= 2^31 in naive order.  SABA_E_OVERFLOW:
- *   n_walks * max(L, 1) >= 2^62.
+ *   n_walks * max(L, 1) >= 2^62, or n_walks >= 2^32 (a walk key holds a 32-bit index, so
+ *   more walks from one start would repeat earlier ones).
  */
 int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, int64_t *d_visits,
                saba_stats *stats, void *stream);
@@ -414,7 +415,8 @@ int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, in
  * estimated to within eps with probability 1 - delta when group == 1.
  *   d_sc[m] (double): estimate of the i-th undirected edge in canonical order
  *   (u < v, lexicographic).  Errors: SABA_E_DISCONNECTED, SABA_E_BIPARTITE,
- *   SABA_E_INVALID (parameters), SABA_E_OVERFLOW (walk counts).
+ *   SABA_E_INVALID (parameters), SABA_E_OVERFLOW (a directed edge needing 2^32 or more
+ *   walk pairs: walk keys carry a 32-bit index).
  */
 int saba_aesc(saba_graph *g, const saba_aesc_params *p, double *d_sc, saba_stats *stats,
               void *stream);
@@ -444,6 +446,49 @@ int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc,
                          int32_t *d_ttau, int64_t *d_nreq, double *d_D, double *d_MC,
                          int64_t *d_vis0, int64_t *d_vis1, double *d_g, saba_stats *stats,
                          void *stream);
+
+/*
+ * Integer visit counts of the walk pairs of Alg. 1 (its inner loop) for a list of sources,
+ * for parity checks: the statistic X of a pair is sum_b h(W^s[b]) - sum_b h(W^t[b]) over
+ * positions b = 1..L, so the Monte-Carlo sum of a directed edge (s, t) is
+ * MC = sum over x in supp(h_ttau) of h_ttau(x) (c0(x) - c1(x)), where c0(x) and c1(x) count
+ * the positions of the walks from s and from t that are at x.  These counts, the support and
+ * h_ttau are exported exactly; the estimator itself sums h_ttau per walk.
+ * layout[nsrc] (host): per source, `source` (vertex id, in) and, filled by the library:
+ *   degree d_s, ttau, support |supp(h_ttau)|, and the offsets of a dense packing in list
+ *   order: supp_off (into d_supp / d_h), edge_off (into the per-edge arrays) and hist_off.
+ * Two calls.  Sizing: d_supp = d_h = d_hist = NULL; the library fills layout (the per-edge
+ *   arrays may be given already).  Totals: supp_off + support, edge_off + degree and
+ *   hist_off + 2 degree support of the last entry.
+ * Filling: all three given (device), with the layout of the sizing call for the same graph
+ *   and parameters:
+ *   d_supp[] int32: the support of each source, ascending vertex ids;
+ *   d_h[] double: h_ttau at those vertices;
+ *   d_hist[] int64: entry hist_off + (2 i + side) support + p counts the positions of the
+ *   side-`side` walks (0: from s, 1: from t = the i-th neighbour of s in row order) of edge i
+ *   that are at the p-th support vertex.
+ * Per-edge outputs (device, entry edge_off + i; any may be NULL in either call): d_tau int32,
+ * d_nreq int64, d_D double, d_MC double (the estimator's own per-walk sum), d_vis0 / d_vis1
+ * int64 (the totals of the two histograms), d_g double, as saba_aesc_edge_stats defines them.
+ * Every value equals what saba_aesc computes for that source and edge.
+ * Errors: SABA_E_INVALID (empty or repeated source list, an isolated or out-of-range source,
+ * partial outputs, a layout that is not the sizing call's), and saba_aesc's errors.
+ */
+typedef struct saba_count_source {
+    int32_t source;
+    int32_t degree;
+    int32_t ttau;
+    int32_t reserved;
+    int64_t support;
+    int64_t supp_off;
+    int64_t edge_off;
+    int64_t hist_off;
+} saba_count_source;
+
+int saba_aesc_counts(saba_graph *g, const saba_aesc_params *p, saba_count_source *layout,
+                     int32_t nsrc, int32_t *d_supp, double *d_h, int64_t *d_hist, int32_t *d_tau,
+                     int64_t *d_nreq, double *d_D, double *d_MC, int64_t *d_vis0,
+                     int64_t *d_vis1, double *d_g, saba_stats *stats, void *stream);
 
 /*
  * Several estimator requests evaluated together (Alg. 1 for each): batched multi-graph

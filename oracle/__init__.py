@@ -68,6 +68,9 @@ def lib():
         L.orc_nwalks_export.restype = i64
         L.orc_tau_export.argtypes = [i32, i32, f64, f64, i32]
         L.orc_tau_export.restype = i32
+        L.orc_source_counts.argtypes = [P, P, i32, i32, f64, f64, f64, u32, u32, u32, i32, i32,
+                                        i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_source_counts.restype = i64
         _lib = L
     return _lib
 
@@ -202,3 +205,39 @@ def aesc(g, eps, lam, seed, delta=0.01, G=1, S=0, tau_cap=1 << 20, tilde_tau_max
     if rc != 0:
         raise ValueError(f"orc_aesc failed ({rc})")
     return sc, out
+
+
+def source_counts(g, s, eps, lam, seed, delta=0.01, G=1, S=0, tau_cap=1 << 20, tilde_tau_max=-1,
+                  push_all=False):
+    """The integer visit counts of source s (Alg. 1's inner loop, per edge, side and support
+    vertex).  Returns a dict:
+      supp  int32[ns]   support of h_ttau, ascending;  h  float64[ns]  h_ttau there;
+      hist  int64[d_s, 2, ns]  visits of the side-0 / side-1 walks of edge i (row order);
+      MCh   float64[d_s]  sum over the support, ascending, of h * (c0 - c1);
+      tau, ttau, nreq, D, MC, vis0, vis1, g  per edge of the row of s."""
+    L = lib()
+    args0 = (_p(g.row_ptr), _p(g.col_idx), g.n, int(s), float(eps), float(delta), float(lam),
+             seed, G, S, int(tau_cap), int(tilde_tau_max), int(bool(push_all)))
+    if not 0 <= int(s) < g.n:
+        raise ValueError(f"source {s} out of range")
+    d = int(g.row_ptr[s + 1] - g.row_ptr[s])
+    out = {
+        "tau": np.zeros(d, dtype=np.int32), "ttau": np.zeros(d, dtype=np.int32),
+        "nreq": np.zeros(d, dtype=np.int64), "D": np.zeros(d, dtype=np.float64),
+        "MC": np.zeros(d, dtype=np.float64), "vis0": np.zeros(d, dtype=np.int64),
+        "vis1": np.zeros(d, dtype=np.int64), "g": np.zeros(d, dtype=np.float64),
+    }
+    edge_keys = ["tau", "ttau", "nreq", "D", "MC", "vis0", "vis1", "g"]
+    ns = L.orc_source_counts(*args0, None, None, None, None, *[_p(out[k]) for k in edge_keys])
+    if ns < 0:
+        raise ValueError(f"orc_source_counts failed ({ns})")
+    out.update({
+        "supp": np.zeros(ns, dtype=np.int32), "h": np.zeros(ns, dtype=np.float64),
+        "hist": np.zeros((d, 2, ns), dtype=np.int64), "MCh": np.zeros(d, dtype=np.float64),
+    })
+    keys = ["supp", "h", "hist", "MCh"] + edge_keys
+    r = L.orc_source_counts(*args0, *[_p(out[k]) for k in keys])
+    if r != ns:
+        raise ValueError(f"orc_source_counts failed ({r})")
+    return out
+

@@ -399,6 +399,7 @@ double orc_cconst(double eps, double delta, int64_t m)
 }
 
 typedef struct {
+    int64_t ebase;   /* the arrays below hold directed edges ebase, ebase + 1, ... */
     int32_t *tau;    /* [nnz] per directed edge (CSR position) */
     int32_t *ttau;   /* [nnz] tilde-tau of the edge's source */
     int64_t *nreq;   /* [nnz] walk pairs */
@@ -409,6 +410,29 @@ typedef struct {
     double *g;       /* [nnz] directed estimate g(s,t) */
 } orc_edge_out;
 
+/* Integer form of the Monte-Carlo statistic of one source (the per-pair X of
+ * Alg. 1's inner loop, split by side and by support vertex):
+ *   supp[p]  the p-th vertex of supp(h_ttau) in ascending order (ns of them);
+ *   h[p]     h_ttau(supp[p]);
+ *   hist[(i*2 + side)*ns + p]  positions 1..L of the side-`side` walks of the
+ *            i-th edge of the source (CSR order) that are at supp[p];
+ *   MCh[i]   sum over p ascending of h[p] * (c0[p] - c1[p]), the Monte-Carlo
+ *            sum of that edge formed from the counts.
+ * With supp == NULL only ns is produced (the walks are not run). */
+typedef struct {
+    int32_t *pos;   /* [n] scratch: support rank of each support vertex */
+    int64_t ns;     /* out: support size */
+    int32_t *supp;
+    double *h;
+    int64_t *hist;
+    double *MCh;
+} orc_count_out;
+
+/* Walk keys carry a 32-bit walk index (the group number hashed into key_hi), so
+ * an edge needing 2^32 pairs or more would repeat walks; the estimate would no
+ * longer rest on independent walks and the call fails instead. */
+#define ORC_MAX_PAIRS 0xFFFFFFFFll
+
 /* Per-source part of Alg. 1 (its outer loop body) for source s: push levels
  * while the support volume is below the walks still needed, then the walk
  * pairs for the directed edges s->t that are wanted (want[e] != 0). */
@@ -416,7 +440,7 @@ static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_
                           int32_t s, double lambda, double eps, double c, int32_t tau_cap,
                           int32_t tilde_tau_max, int32_t push_all, uint32_t seed,
                           uint32_t G, uint32_t S, const uint8_t *want, orc_edge_out *o,
-                          double *hcur, double *hnext)
+                          double *hcur, double *hnext, orc_count_out *co)
 {
     int32_t e0 = row_ptr[s], e1 = row_ptr[s + 1];
     int32_t ds = e1 - e0;
@@ -424,9 +448,9 @@ static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_
     for (int32_t e = e0; e < e1; ++e) {
         int32_t t = col_idx[e];
         int32_t dt = row_ptr[t + 1] - row_ptr[t];
-        o->tau[e] = orc_tau(ds, dt, lambda, eps, tau_cap);
-        if (o->tau[e] > maxtau) maxtau = o->tau[e];
-        o->D[e] = 0.0;
+        o->tau[e - o->ebase] = orc_tau(ds, dt, lambda, eps, tau_cap);
+        if (o->tau[e - o->ebase] > maxtau) maxtau = o->tau[e - o->ebase];
+        o->D[e - o->ebase] = 0.0;
     }
     for (int32_t x = 0; x < n; ++x) hcur[x] = 0.0;
     hcur[s] = 1.0; /* p_0(., v_i) = e_{v_i} */
@@ -444,13 +468,13 @@ static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_
         }
         /* deterministic terms of level l */
         for (int32_t e = e0; e < e1; ++e) {
-            if (l <= o->tau[e]) o->D[e] += hcur[s] - hcur[col_idx[e]];
+            if (l <= o->tau[e - o->ebase]) o->D[e - o->ebase] += hcur[s] - hcur[col_idx[e]];
         }
         /* walks still needed if the push stopped here */
         int64_t need = 0;
         for (int32_t e = e0; e < e1; ++e) {
-            if (o->tau[e] > l) {
-                int64_t nw = orc_nwalks(o->tau[e] - l, hmax, ds, c);
+            if (o->tau[e - o->ebase] > l) {
+                int64_t nw = orc_nwalks(o->tau[e - o->ebase] - l, hmax, ds, c);
                 if (nw < 0) return -3;
                 need += nw;
             }
@@ -475,20 +499,37 @@ static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_
         l += 1;
     }
     int32_t ttau = l;
+    int64_t ns = 0;
+    if (co) {
+        /* the support of h_ttau in ascending vertex order */
+        for (int32_t x = 0; x < n; ++x) {
+            if (hcur[x] != 0.0) {
+                if (co->supp) {
+                    co->supp[ns] = x;
+                    co->h[ns] = hcur[x];
+                    co->pos[x] = (int32_t)ns;
+                }
+                ns += 1;
+            }
+        }
+        co->ns = ns;
+        if (!co->supp) return 0;
+        memset(co->hist, 0, sizeof(int64_t) * (size_t)(2 * ds) * (size_t)ns);
+    }
     for (int32_t e = e0; e < e1; ++e) {
-        o->ttau[e] = ttau;
-        o->nreq[e] = 0;
-        o->MC[e] = 0.0;
-        o->vis0[e] = 0;
-        o->vis1[e] = 0;
+        o->ttau[e - o->ebase] = ttau;
+        o->nreq[e - o->ebase] = 0;
+        o->MC[e - o->ebase] = 0.0;
+        o->vis0[e - o->ebase] = 0;
+        o->vis1[e - o->ebase] = 0;
         if (!want[e]) continue;
         int32_t t = col_idx[e];
-        double g = o->D[e] / (double)ds;
-        int32_t L = o->tau[e] - ttau;
+        double g = o->D[e - o->ebase] / (double)ds;
+        int32_t L = o->tau[e - o->ebase] - ttau;
         if (L > 0) {
             int64_t nr = orc_nwalks(L, hmax, ds, c);
-            if (nr < 0) return -3;
-            o->nreq[e] = nr;
+            if (nr < 0 || nr > ORC_MAX_PAIRS) return -3;
+            o->nreq[e - o->ebase] = nr;
             double mc = 0.0;
             for (int64_t k = 0; k < nr; ++k) {
                 /* one walk from s (side 0) and one from t (side 1), as in the
@@ -505,20 +546,28 @@ static int32_t orc_source(const int32_t *row_ptr, const int32_t *col_idx, int32_
                         cur = orc_step(row_ptr, col_idx, cur, (uint32_t)b, khi, klo);
                         acc += hcur[cur];
                         hits += hcur[cur] != 0.0;
+                        if (co && hcur[cur] != 0.0)
+                            co->hist[((int64_t)(e - e0) * 2 + side) * ns + co->pos[cur]] += 1;
                     }
                     sum[side] = acc;
                     if (side == 0)
-                        o->vis0[e] += hits;
+                        o->vis0[e - o->ebase] += hits;
                     else
-                        o->vis1[e] += hits;
+                        o->vis1[e - o->ebase] += hits;
                 }
                 double X = sum[0] - sum[1];
                 mc += X;
                 g += X / ((double)nr * (double)ds);
             }
-            o->MC[e] = mc;
+            o->MC[e - o->ebase] = mc;
         }
-        o->g[e] = g;
+        if (co) {
+            const int64_t *c0 = co->hist + (int64_t)(e - e0) * 2 * ns, *c1 = c0 + ns;
+            double mch = 0.0;
+            for (int64_t p = 0; p < ns; ++p) mch += co->h[p] * (double)(c0[p] - c1[p]);
+            co->MCh[e - e0] = mch;
+        }
+        o->g[e - o->ebase] = g;
     }
     return 0;
 }
@@ -550,6 +599,7 @@ int32_t orc_aesc(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, doub
         vis1 = (int64_t *)malloc(sizeof(int64_t) * nnz);
         gout = (double *)malloc(sizeof(double) * nnz);
     }
+    o.ebase = 0;
     o.tau = tau; o.ttau = ttau; o.nreq = nreq; o.D = D; o.MC = MC;
     o.vis0 = vis0; o.vis1 = vis1; o.g = gout;
     uint8_t *want = (uint8_t *)calloc((size_t)nnz, 1);
@@ -584,7 +634,8 @@ int32_t orc_aesc(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, doub
             for (int32_t s = 0; s < n; ++s) {
                 if (!srcw[s]) continue;
                 int32_t r = orc_source(row_ptr, col_idx, n, s, lambda, eps, c, tau_cap,
-                                       tilde_tau_max, push_all, seed, G, S, want, &o, ha, hb);
+                                       tilde_tau_max, push_all, seed, G, S, want, &o, ha, hb,
+                                       NULL);
                 if (r != 0) {
 #ifdef _OPENMP
 #pragma omp critical
@@ -634,4 +685,51 @@ int64_t orc_nwalks_export(int32_t L, double hmax, int32_t ds, double c) { return
 int32_t orc_tau_export(int32_t ds, int32_t dt, double lambda, double eps, int32_t tau_cap)
 {
     return orc_tau(ds, dt, lambda, eps, tau_cap);
+}
+
+/* The counts of one source s (see orc_count_out): the push and the walk pairs
+ * of all edges of s exactly as orc_aesc runs them, with the visits to the
+ * support of h_ttau tallied per edge, side and support vertex.  The per-edge
+ * outputs tau .. g (required, d_s entries each) are indexed by the edge's
+ * position i in the row of s.  supp == NULL: only the support size is
+ * computed (and tau, D of the push).  Returns the support size,
+ * or a negative code (-1 bad source, -2 memory, -3 walk-count overflow). */
+int64_t orc_source_counts(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t s,
+                          double eps, double delta, double lambda, uint32_t seed, uint32_t G,
+                          uint32_t S, int32_t tau_cap, int32_t tilde_tau_max, int32_t push_all,
+                          int32_t *supp, double *h, int64_t *hist, double *MCh, int32_t *tau,
+                          int32_t *ttau, int64_t *nreq, double *D, double *MC, int64_t *vis0,
+                          int64_t *vis1, double *g)
+{
+    if (s < 0 || s >= n || row_ptr[s + 1] == row_ptr[s]) return -1;
+    int64_t m = (int64_t)row_ptr[n] / 2;
+    double c = orc_cconst(eps, delta, m);
+    int32_t ds = row_ptr[s + 1] - row_ptr[s];
+    orc_edge_out o;
+    o.ebase = row_ptr[s];
+    o.tau = tau; o.ttau = ttau; o.nreq = nreq; o.D = D; o.MC = MC;
+    o.vis0 = vis0; o.vis1 = vis1; o.g = g;
+    uint8_t *want = (uint8_t *)calloc((size_t)row_ptr[n] + 1, 1);
+    double *ha = (double *)malloc(sizeof(double) * (size_t)n);
+    double *hb = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t rc = -2;
+    if (want && ha && hb && pos) {
+        memset(want + row_ptr[s], 1, (size_t)ds);
+        orc_count_out co;
+        co.pos = pos;
+        co.ns = 0;
+        co.supp = supp;
+        co.h = h;
+        co.hist = hist;
+        co.MCh = MCh;
+        int32_t r = orc_source(row_ptr, col_idx, n, s, lambda, eps, c, tau_cap, tilde_tau_max,
+                               push_all, seed, G, S, want, &o, ha, hb, &co);
+        rc = r != 0 ? (int64_t)r : co.ns;
+    }
+    free(want);
+    free(ha);
+    free(hb);
+    free(pos);
+    return rc;
 }

@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     WalkResult,
     aesc,
     aesc_batch,
+    aesc_counts,
     aesc_edge_stats,
     aesc_query,
     autotune_aesc,

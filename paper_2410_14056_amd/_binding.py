@@ -32,6 +32,8 @@ _ERRORS = {
     -8: "SABA_E_OVERFLOW", -9: "SABA_E_NODEVICE", -10: "SABA_E_BUSY", -11: "SABA_E_TIMEOUT",
     -12: "SABA_E_CANCELLED",
 }
+SABA_E_INVALID = -1
+SABA_E_OVERFLOW = -8
 SABA_E_BUSY = -10
 SABA_E_TIMEOUT = -11
 
@@ -150,6 +152,13 @@ class SpectrumResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class CountSource(ctypes.Structure):
+    _fields_ = [("source", ctypes.c_int32), ("degree", ctypes.c_int32), ("ttau", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("support", ctypes.c_int64),
+                ("supp_off", ctypes.c_int64), ("edge_off", ctypes.c_int64),
+                ("hist_off", ctypes.c_int64)]
+
+
 class ExecConfig(ctypes.Structure):
     _fields_ = [("walks_per_lane", ctypes.c_int32), ("walk_blocks", ctypes.c_int32),
                 ("est_walk_blocks", ctypes.c_int32), ("est_push_blocks", ctypes.c_int32)]
@@ -165,7 +174,7 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
            "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc",
-           "saba_debug_fail_allocation"]
+           "saba_debug_fail_allocation", "saba_aesc_counts"]
 
 _lib = None
 
@@ -190,6 +199,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_aesc_query.argtypes = [P, ctypes.POINTER(AescParams), P, i64, P, ctypes.POINTER(Stats), P]
     L.saba_aesc_edge_stats.argtypes = [P, ctypes.POINTER(AescParams), P, P, P, P, P, P, P, P, P,
                                        ctypes.POINTER(Stats), P]
+    L.saba_aesc_counts.argtypes = [P, ctypes.POINTER(AescParams), P, i32, P, P, P, P, P, P, P,
+                                   P, P, P, ctypes.POINTER(Stats), P]
     L.saba_aesc_batch.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions), ctypes.POINTER(Stats), P]
     L.saba_server_create.argtypes = [P, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
     L.saba_server_submit.argtypes = [P, ctypes.POINTER(ServerRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -468,6 +479,64 @@ def aesc_edge_stats(graph: SabaGraph, eps: float, lam: float, seed: int, device=
         _ptr(out["nreq"]), _ptr(out["D"]), _ptr(out["MC"]), _ptr(out["vis0"]), _ptr(out["vis1"]),
         _ptr(out["g"]), ctypes.byref(st), _stream_ptr(stream)))
     return out, st.as_dict()
+
+
+def aesc_counts(graph: SabaGraph, sources, eps: float, lam: float, seed: int, device="cuda",
+                stream=None, histograms: bool = True, **kw):
+    """saba_aesc_counts: the integer visit counts of the walk pairs of the given sources.
+
+    Returns (per-source list, dict of device tensors, stats).  Each list entry is a dict with
+    source, degree, ttau, support, edge_off and, with histograms, the entries supp/h (support,
+    h_ttau there) and hist (int64 [degree, 2, support]) as views into the packed tensors; the
+    dict holds the packed supp, h, hist and the per-edge tau, nreq, D, MC, vis0, vis1, g
+    (entry edge_off + i).  histograms=False stops after the sizing call (per-edge outputs
+    and the layout only)."""
+    L = load()
+    p = _aesc_params(eps, lam, seed, **kw)
+    K = len(sources)
+    lay = (CountSource * K)()
+    for k, v in enumerate(sources):
+        lay[k].source = int(v)
+    st = Stats()
+    s = _stream_ptr(stream)
+    _check(L.saba_aesc_counts(graph.handle, ctypes.byref(p), lay, K, None, None, None, None,
+                              None, None, None, None, None, None, ctypes.byref(st), s))
+    last = lay[K - 1]
+    ns = last.supp_off + last.support
+    ne = last.edge_off + last.degree
+    nh = last.hist_off + 2 * last.degree * last.support
+    out = {
+        "tau": torch.empty(ne, dtype=torch.int32, device=device),
+        "nreq": torch.empty(ne, dtype=torch.int64, device=device),
+        "D": torch.empty(ne, dtype=torch.float64, device=device),
+        "MC": torch.empty(ne, dtype=torch.float64, device=device),
+        "vis0": torch.empty(ne, dtype=torch.int64, device=device),
+        "vis1": torch.empty(ne, dtype=torch.int64, device=device),
+        "g": torch.empty(ne, dtype=torch.float64, device=device),
+    }
+    edge_ptrs = [_ptr(out[k]) for k in ("tau", "nreq", "D", "MC", "vis0", "vis1", "g")]
+    if histograms:
+        out["supp"] = torch.empty(ns, dtype=torch.int32, device=device)
+        out["h"] = torch.empty(ns, dtype=torch.float64, device=device)
+        out["hist"] = torch.empty(nh, dtype=torch.int64, device=device)
+        _check(L.saba_aesc_counts(graph.handle, ctypes.byref(p), lay, K, _ptr(out["supp"]),
+                                  _ptr(out["h"]), _ptr(out["hist"]), *edge_ptrs,
+                                  ctypes.byref(st), s))
+    else:
+        _check(L.saba_aesc_counts(graph.handle, ctypes.byref(p), lay, K, None, None, None,
+                                  *edge_ptrs, ctypes.byref(st), s))
+    per = []
+    for k in range(K):
+        c = lay[k]
+        d, z = c.degree, c.support
+        e = {"source": c.source, "degree": d, "ttau": c.ttau, "support": z,
+             "edge_off": c.edge_off}
+        if histograms:
+            e["supp"] = out["supp"][c.supp_off:c.supp_off + z]
+            e["h"] = out["h"][c.supp_off:c.supp_off + z]
+            e["hist"] = out["hist"][c.hist_off:c.hist_off + 2 * d * z].view(d, 2, z)
+        per.append(e)
+    return per, out, st.as_dict()
 
 
 def aesc_batch(graph: SabaGraph, requests, mem_budget: int = 0, batch_sources: int = 0,

@@ -95,6 +95,8 @@ __device__ __forceinline__ int32_t tau_of(int32_t ds, int32_t dt, double lambda,
     return tau;
 }
 
+constexpr long long kMaxPairs = 0xFFFFFFFFll;  // walk pairs of one directed edge
+
 // NWalks (Hoeffding): max(1, ceil(c * q * q)), q = L * hmax / d_s; -1 on overflow.
 __device__ __forceinline__ long long nwalks(int32_t L, double hmax, int32_t ds, double c) {
     const double q = ((double)L * hmax) / (double)ds;
@@ -809,7 +811,8 @@ __global__ __launch_bounds__(kBlock) void nreq_kernel(
         const int32_t L = tau[ie] - tt;
         if (want[ie] && L > 0) {
             nr = nwalks(L, hmax, r.y, c);
-            if (nr < 0) {
+            // walk keys carry a 32-bit walk index: 2^32 pairs or more would repeat walks
+            if (nr < 0 || nr > kMaxPairs) {
                 ovf = 1;
                 nr = 0;
             }
@@ -835,6 +838,32 @@ __global__ __launch_bounds__(kBlock) void nreq_kernel(
 // covers the flat chunk space of the whole batch (every instance edge of every request) in a
 // fixed wavefront-strided order; the loop control depends only on the wavefront index, so the
 // wavefront stays converged around its reductions.
+//
+// kCount (the counts export): every visit to the support of h_ttau also adds one to the
+// integer histogram entry of (edge, side, support rank of the vertex), the rank found by
+// binary search in the slot's final frontier list (the support in ascending order).  The
+// walks, the sums and the totals are those of the plain instantiation.
+struct CountArgs {
+    const int32_t *FA = nullptr, *FB = nullptr;  // frontier lists of the two level parities
+    const int64_t *hoff = nullptr;  // per instance: first histogram entry, -1 if not exported
+    const int64_t *expect = nullptr;  // per instance: the support size of the caller's layout
+    unsigned long long *hist = nullptr;
+};
+
+__device__ __forceinline__ int32_t support_rank(const int32_t *__restrict__ F, int32_t fsz,
+                                                int32_t v) {
+    int32_t lo = 0, hi = fsz;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (F[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <bool kCount>
 __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int4 *__restrict__ nbr,
     const Slot *__restrict__ slots,
@@ -844,7 +873,7 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const double *__restrict__ hA, const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
     const uint32_t *__restrict__ bmB, double *__restrict__ partial,
     unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
-    Flags *__restrict__ fl) {
+    Flags *__restrict__ fl, CountArgs ca) {
     const int lane = __lane_id();
     const int64_t T = coff[nle];
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -868,6 +897,16 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
         const long long k = j - side * nr;
         double acc = 0.0;
         long long hits = 0;
+        const int32_t *F = nullptr;
+        int32_t fsz = 0;
+        int64_t hrow = -1;
+        if (kCount) {
+            F = (fb ? ca.FB : ca.FA) + sl.hoff;
+            fsz = bs[b].fsz[fb];
+            // a support that differs from the layout's is not counted (the export flags it)
+            const int64_t h0 = ca.hoff[sl.inst];
+            if (h0 >= 0 && ca.expect[sl.inst] == fsz) hrow = h0 + ((int64_t)i * 2 + side) * fsz;
+        }
         if (active) {
             const int32_t sloc = sl.v - sl.goff, tloc = t - sl.goff;
             Walker wk = walker_init<SABA_SAMPLER_KEYED>(walk_key(
@@ -881,6 +920,8 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
                 if (bm[xl >> 5] & (1u << (xl & 31))) {  // h_ttau is zero off its support
                     acc += h[xl];  // cached: the hubs' values are read again and again
                     hits += 1;
+                    if (kCount && hrow >= 0)
+                        atomicAdd(ca.hist + hrow + support_rank(F, fsz, p.v), 1ull);
                 }
             }
         }
@@ -892,6 +933,45 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
             if (h0) atomicAdd(vis0 + ie, (unsigned long long)h0);
             if (h1) atomicAdd(vis1 + ie, (unsigned long long)h1);
         }
+    }
+}
+
+// Counts export, per slot: the size of the final support and, where the instance is exported
+// (soff >= 0), the support in ascending order (graph-local ids) with h_ttau there.  A support
+// whose size differs from the one the caller laid its arrays out for sets kErrLayout and is
+// not written.
+struct CountExport {
+    int64_t *supp_sz = nullptr;      // per instance, out
+    const int64_t *soff = nullptr;   // per instance: first support entry, -1 if not exported
+    const int64_t *expect = nullptr; // per instance: the support size of the layout
+    int32_t *supp = nullptr;
+    double *h = nullptr;
+    CountArgs ca;
+};
+
+__global__ __launch_bounds__(kBlock) void count_support_kernel(
+    const Slot *__restrict__ slots, const BatchState *__restrict__ bs, const double *__restrict__ hA,
+    const double *__restrict__ hB, const int32_t *__restrict__ FA, const int32_t *__restrict__ FB,
+    CountExport cx, Flags *__restrict__ fl) {
+    const int64_t b = blockIdx.y;
+    const Slot sl = slots[b];
+    const int pb = bs[b].finalbuf;
+    const int32_t fsz = bs[b].fsz[pb];
+    if (blockIdx.x == 0 && threadIdx.x == 0) cx.supp_sz[sl.inst] = fsz;
+    if (!cx.supp) return;
+    const int64_t so = cx.soff[sl.inst];
+    if (so < 0) return;
+    if (cx.expect[sl.inst] != fsz) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&fl->err, kErrLayout);
+        return;
+    }
+    const double *h = (pb ? hB : hA) + sl.hoff;
+    const int32_t *F = (pb ? FB : FA) + sl.hoff;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fsz;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = F[i] - sl.goff;
+        cx.supp[so + i] = x;
+        cx.h[so + i] = h[x];
     }
 }
 
@@ -1145,7 +1225,7 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs,
 
 int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
               const std::vector<int64_t> &heb, int64_t ie0, int64_t nle, int64_t maxgn,
-              int64_t hubcap, BatchTiming *tm, hipStream_t s) {
+              int64_t hubcap, BatchTiming *tm, hipStream_t s, const CountExport *cx) {
     auto &E = ws.b;
     const int32_t nb = (int32_t)hslots.size();
     if (nb == 0) return SABA_OK;
@@ -1232,9 +1312,15 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     if (T > 0) {
         const bool timing = tm && tm->on;
         if (timing) SABA_HIP_TRY(hipEventRecord(tm->a, s));
-        mc_walk_kernel<<<grid_for(T, kWavesPerBlock, walk_blocks), kBlock, 0, s>>>(
-            g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq,
-            hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl);
+        const unsigned wgrid = grid_for(T, kWavesPerBlock, walk_blocks);
+        if (cx && cx->supp)
+            mc_walk_kernel<true><<<wgrid, kBlock, 0, s>>>(
+                g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle,
+                ea.tau, ea.nreq, hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, cx->ca);
+        else
+            mc_walk_kernel<false><<<wgrid, kBlock, 0, s>>>(
+                g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle,
+                ea.tau, ea.nreq, hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, CountArgs{});
         SABA_HIP_TRY(hipGetLastError());
         if (timing) {
             SABA_HIP_TRY(hipEventRecord(tm->b, s));
@@ -1246,6 +1332,8 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     }
     edge_reduce_kernel<<<grid_for(nle, kBlock, 1 << 16), kBlock, 0, s>>>(
         g->vrec, d_slots, nb, d_eb, ie0, coff, nle, ea.want, ea.nreq, ea.D, partial, ea.MC, ea.g);
+    if (cx)
+        count_support_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, hA, hB, FA, FB, *cx, fl);
     // leave the dense vectors and bitmaps of the batch zero: clear h_ttau over its support
     clear_final_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, hA, hB, bmA, bmB, FA, FB);
     SABA_HIP_TRY(hipGetLastError());
@@ -1270,6 +1358,17 @@ struct Exports {  // per CSR position (single graph, all edges)
     double *D = nullptr, *MC = nullptr, *g = nullptr;
 };
 
+// The counts export of saba_aesc_counts: one request whose instances are the listed sources,
+// with all their edges wanted.
+struct CountJob {
+    std::vector<int32_t> src;        // graph-local source vertices, in the caller's order
+    saba_count_source *layout = nullptr;
+    int32_t *supp = nullptr;         // all three null: layout only
+    double *h = nullptr;
+    int64_t *hist = nullptr;
+    Exports edges;                   // per-edge outputs, indexed by layout[k].edge_off + i
+};
+
 struct Opts {
     int64_t mem_budget = 0;
     int32_t batch_sources = 0;
@@ -1285,7 +1384,7 @@ static bool same_params(const Request &a, const Request &b) {
 }
 
 static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const Exports *ex,
-                    saba_stats *st, hipStream_t s) {
+                    saba_stats *st, hipStream_t s, CountJob *cj = nullptr) {
     const int32_t *rp = g->h_row_ptr.data();
     const int32_t *ci = g->h_col_idx.data();
     for (auto &r : reqs) {
@@ -1344,6 +1443,10 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     for (size_t i = 0; i < reqs.size(); ++i) {
         const Request &r = reqs[i];
         const int32_t ga = g->goff[r.graph], gn = g->goff[r.graph + 1] - ga;
+        if (cj) {
+            for (const int32_t x : cj->src) pverts[r.pid].push_back(x);
+            continue;
+        }
         if (r.q < 0) {
             pall[r.pid] = 1;
             continue;
@@ -1399,6 +1502,11 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         if (pall[k]) {
             const int32_t ga = g->goff[pgraph[k]], gz = g->goff[pgraph[k] + 1];
             std::fill(want.begin() + pbase[k], want.begin() + pbase[k] + (rp[gz] - rp[ga]), 1);
+        }
+    if (cj)
+        for (const int32_t x : cj->src) {
+            const int64_t k = inst_of(0, x);
+            std::fill(want.begin() + iebase[k], want.begin() + iebase[k + 1], 1);
         }
     for (size_t i = 0; i < reqs.size(); ++i) {
         const Request &r = reqs[i];
@@ -1483,6 +1591,46 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     }
     SABA_TRY(ensure_pools(ws, maxh, maxbm, maxsb, maxhubs, maxnb, maxne, s));
 
+    // counts export: per-instance support offsets and histogram offsets in the caller's layout
+    CountExport cx;
+    struct BufGuard {
+        DevBuf b;
+        ~BufGuard() { b.release(); }
+    } cbuf;
+    std::vector<int64_t> hsz;
+    if (cj) {
+        const size_t K = cj->src.size();
+        std::vector<int64_t> per(4 * (size_t)ns, -1);  // soff, hoff, expect, (support sizes)
+        if (cj->supp)
+            for (size_t k = 0; k < K; ++k) {
+                const int64_t i = inst_of(0, cj->src[k]);
+                per[i] = cj->layout[k].supp_off;
+                per[ns + i] = cj->layout[k].hist_off;
+                per[2 * ns + i] = cj->layout[k].support;
+            }
+        SABA_TRY(cbuf.b.ensure(sizeof(int64_t) * per.size()));
+        int64_t *dp = cbuf.b.as<int64_t>();
+        SABA_HIP_TRY(hipMemcpyAsync(dp, per.data(), sizeof(int64_t) * per.size(),
+                                    hipMemcpyHostToDevice, s));
+        cx.soff = dp;
+        cx.ca.hoff = dp + ns;
+        cx.expect = dp + 2 * ns;
+        cx.ca.expect = cx.expect;
+        cx.supp_sz = dp + 3 * ns;
+        cx.supp = cj->supp;
+        cx.h = cj->h;
+        cx.ca.hist = reinterpret_cast<unsigned long long *>(cj->hist);
+        cx.ca.FA = ws.b[B_FA].as<int32_t>();
+        cx.ca.FB = ws.b[B_FB].as<int32_t>();
+        if (cj->hist) {
+            int64_t tot = 0;
+            for (size_t k = 0; k < K; ++k)
+                tot = std::max(tot, cj->layout[k].hist_off +
+                                        2 * (int64_t)cj->layout[k].degree * cj->layout[k].support);
+            if (tot > 0) SABA_HIP_TRY(hipMemsetAsync(cj->hist, 0, sizeof(int64_t) * tot, s));
+        }
+    }
+
     std::vector<Slot> hslots;
     std::vector<int64_t> heb;
     for (const Batch &bt : batches) {
@@ -1513,7 +1661,57 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             heb[b] = iebase[i] - ie0;
         }
         heb[nb] = bt.ne;
-        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, bt.hubs, &tm, s));
+        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, bt.hubs, &tm, s,
+                           cj ? &cx : nullptr));
+    }
+    if (cj) {
+        // layout of the caller's arrays in list order, then the per-edge outputs
+        const size_t K = cj->src.size();
+        std::vector<int64_t> sz((size_t)ns);
+        std::vector<int32_t> tt((size_t)ns);
+        SABA_HIP_TRY(hipMemcpyAsync(sz.data(), cx.supp_sz, sizeof(int64_t) * ns,
+                                    hipMemcpyDeviceToHost, s));
+        SABA_HIP_TRY(hipMemcpyAsync(tt.data(), ea.ttau_inst, sizeof(int32_t) * ns,
+                                    hipMemcpyDeviceToHost, s));
+        int32_t err = 0;
+        SABA_HIP_TRY(hipMemcpyAsync(&err, &ea.fl->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SABA_HIP_TRY(hipStreamSynchronize(s));
+        if (err & kErrLayout) {
+            set_error("a support size differs from the layout: pass the layout the sizing call "
+                      "returned for the same parameters");
+            return SABA_E_INVALID;
+        }
+        int64_t so = 0, eo = 0, ho = 0;
+        for (size_t k = 0; k < K; ++k) {
+            const int64_t i = inst_of(0, cj->src[k]);
+            saba_count_source &c = cj->layout[k];
+            const int32_t d = (int32_t)(iebase[i + 1] - iebase[i]);
+            if (!cj->supp) {
+                c.degree = d;
+                c.support = sz[i];
+                c.supp_off = so;
+                c.edge_off = eo;
+                c.hist_off = ho;
+            }
+            c.ttau = tt[i];
+            so += sz[i];
+            eo += d;
+            ho += 2 * (int64_t)d * sz[i];
+            const Exports &x = cj->edges;
+            const int64_t e0 = iebase[i], o = c.edge_off;
+            auto cp = [&](void *dst, const void *src, size_t bytes) -> int {
+                if (dst && bytes)
+                    SABA_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+                return SABA_OK;
+            };
+            SABA_TRY(cp(x.tau ? x.tau + o : nullptr, ea.tau + e0, sizeof(int32_t) * d));
+            SABA_TRY(cp(x.nreq ? x.nreq + o : nullptr, ea.nreq + e0, sizeof(int64_t) * d));
+            SABA_TRY(cp(x.D ? x.D + o : nullptr, ea.D + e0, sizeof(double) * d));
+            SABA_TRY(cp(x.MC ? x.MC + o : nullptr, ea.MC + e0, sizeof(double) * d));
+            SABA_TRY(cp(x.vis0 ? x.vis0 + o : nullptr, ea.vis0 + e0, sizeof(int64_t) * d));
+            SABA_TRY(cp(x.vis1 ? x.vis1 + o : nullptr, ea.vis1 + e0, sizeof(int64_t) * d));
+            SABA_TRY(cp(x.g ? x.g + o : nullptr, ea.g + e0, sizeof(double) * d));
+        }
     }
 
     // results of every request
@@ -1670,6 +1868,72 @@ extern "C" int saba_aesc_edge_stats(saba_graph *gh, const saba_aesc_params *p, d
     ex.vis1 = d_vis1;
     ex.g = d_g;
     return aesc_run(G(gh), reqs, opts_of(p), &ex, st, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int saba_aesc_counts(saba_graph *gh, const saba_aesc_params *p,
+                                saba_count_source *layout, int32_t nsrc, int32_t *d_supp,
+                                double *d_h, int64_t *d_hist, int32_t *d_tau, int64_t *d_nreq,
+                                double *d_D, double *d_MC, int64_t *d_vis0, int64_t *d_vis1,
+                                double *d_g, saba_stats *st, void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!p || nsrc < 1 || !layout) {
+        set_error("params or layout is NULL, or the source list is empty");
+        return SABA_E_INVALID;
+    }
+    const bool fill = d_supp || d_h || d_hist;
+    if (fill && !(d_supp && d_h && d_hist)) {
+        set_error("d_supp, d_h and d_hist are given together or not at all");
+        return SABA_E_INVALID;
+    }
+    SABA_TRY(single_graph(G(gh)));
+    Graph *g = G(gh);
+    CountJob cj;
+    cj.src.resize((size_t)nsrc);
+    std::vector<int32_t> sorted((size_t)nsrc);
+    for (int32_t k = 0; k < nsrc; ++k) {
+        const int32_t v = layout[k].source;
+        if (v < 0 || v >= g->n || g->h_row_ptr[v + 1] == g->h_row_ptr[v]) {
+            set_error("a source is out of range or an isolated vertex");
+            return SABA_E_INVALID;
+        }
+        cj.src[k] = sorted[k] = v;
+    }
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+        set_error("a source is listed twice");
+        return SABA_E_INVALID;
+    }
+    if (fill) {  // the layout must be a dense packing, as the sizing call returns it
+        int64_t so = 0, eo = 0, ho = 0;
+        for (int32_t k = 0; k < nsrc; ++k) {
+            const saba_count_source &c = layout[k];
+            const int32_t v = c.source;
+            if (c.degree != g->h_row_ptr[v + 1] - g->h_row_ptr[v] || c.support < 1 ||
+                c.supp_off != so || c.edge_off != eo || c.hist_off != ho) {
+                set_error("the layout is not the one the sizing call returned");
+                return SABA_E_INVALID;
+            }
+            so += c.support;
+            eo += c.degree;
+            ho += 2 * (int64_t)c.degree * c.support;
+        }
+    }
+    cj.layout = layout;
+    cj.supp = d_supp;
+    cj.h = d_h;
+    cj.hist = d_hist;
+    cj.edges.tau = d_tau;
+    cj.edges.nreq = d_nreq;
+    cj.edges.D = d_D;
+    cj.edges.MC = d_MC;
+    cj.edges.vis0 = d_vis0;
+    cj.edges.vis1 = d_vis1;
+    cj.edges.g = d_g;
+    std::vector<Request> reqs(1);
+    reqs[0].p = *p;
+    reqs[0].q = 0;
+    return aesc_run(g, reqs, opts_of(p), nullptr, st, static_cast<hipStream_t>(stream), &cj);
 }
 
 extern "C" int saba_aesc_batch(saba_graph *gh, const saba_aesc_request *reqs, int32_t nreq,

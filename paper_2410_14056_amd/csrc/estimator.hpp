@@ -23,7 +23,7 @@ enum {
 };
 static_assert(B_COUNT <= 32, "Workspace holds 32 buffers");
 
-enum : int32_t { kErrOverflow = 1 };
+enum : int32_t { kErrOverflow = 1, kErrLayout = 2 };
 
 struct PSet {  // one parameter set; c = 32 ln(4m / delta) / eps^2 uses its graph's m
     double lambda, eps, c;
@@ -125,8 +125,11 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs,
 // instance edge of slot b relative to ie0 (eb[nb] = nle).  Leaves every pool entry it touched
 // zero again.  Returns after the walk launch has been queued; g is final once the stream has
 // reached the end of the batch.
+// cx (the counts export, may be null) also writes each slot's support and integer visit
+// histograms before the batch's scratch is cleared.
+struct CountExport;
 int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
               const std::vector<int64_t> &eb, int64_t ie0, int64_t nle, int64_t maxgn,
-              int64_t hubs, BatchTiming *tm, hipStream_t s);
+              int64_t hubs, BatchTiming *tm, hipStream_t s, const CountExport *cx = nullptr);
 
 }  // namespace saba

@@ -726,6 +726,10 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         set_error("walk count too large");
         return SABA_E_OVERFLOW;
     }
+    if (W > (int64_t)0xFFFFFFFFll) {  // walk keys carry a 32-bit walk index
+        set_error("more than 2^32 - 1 walks: walks of one start would repeat");
+        return SABA_E_OVERFLOW;
+    }
     EventSet ev;
     const bool timing = st && p->time_kernels;
     if (timing)

@@ -1,0 +1,209 @@
+"""GPU parity of the integer visit counts of Alg. 1's walk pairs (saba_aesc_counts) against
+the oracle's source_counts.
+
+Bit-exact: the support of h_ttau, h_ttau itself (both sides fold the pull recursion in CSR
+order), the per-(edge, side, support vertex) histograms, ttau, tau, the walk pairs, D and the
+visit totals.  The estimator's own Monte-Carlo sum (the GPU adds h_ttau per walk, then over a
+wavefront and over chunks) must agree with the count form MC_h = sum_x h(x) (c0(x) - c1(x))
+that the oracle forms from the same counts, within 1e-12 of the sum of the absolute terms
+A = sum_x h(x) (c0(x) + c1(x)).  g is compared with the oracle's g on the same counts,
+(D + MC_h / n) / d_s: the MC tolerance carried through the division, 1e-12 A / (n d_s), plus
+the rounding of the three operations, 2u (|D| + |MC_h| / n) / d_s + 2u |g| (u = 2^-52).
+"""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+@pytest.fixture(scope="module")
+def saba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_14056_amd as saba
+    saba.load()
+    return saba
+
+
+def _oracle_counts(orc, g, sources, eps, lam, seed, **kw):
+    okw = dict(kw)
+    if "group" in okw:
+        okw["G"], okw["S"] = okw.pop("group"), okw.pop("spread")
+    threads = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(threads) as ex:  # the oracle's C code runs without the GIL
+        return list(ex.map(lambda s: orc.source_counts(g, int(s), eps, lam, seed, **okw),
+                           sources))
+
+
+def _check(per, out, ref, histograms=True):
+    gpu = {k: v.cpu().numpy() for k, v in out.items() if k not in ("supp", "h", "hist")}
+    for e, o in zip(per, ref):
+        d, eo = e["degree"], e["edge_off"]
+        sl = slice(eo, eo + d)
+        assert d == o["tau"].size
+        assert e["ttau"] == int(o["ttau"][0])
+        for k in ("tau", "nreq", "vis0", "vis1", "D"):
+            assert np.array_equal(gpu[k][sl], o[k]), (e["source"], k)
+        assert e["support"] == o["supp"].size
+        scale = (o["hist"][:, 0, :] + o["hist"][:, 1, :]) @ o["h"]
+        scale = np.maximum(scale, 1e-300)
+        # the per-walk sums against the count form, and against the oracle's pair loop
+        assert np.all(np.abs(gpu["MC"][sl] - o["MCh"]) <= 1e-12 * scale), e["source"]
+        assert np.all(np.abs(gpu["MC"][sl] - o["MC"]) <= 1e-12 * scale), e["source"]
+        n = o["nreq"].astype(np.float64)
+        walked = o["nreq"] > 0
+        g_h = np.where(walked, (o["D"] + o["MCh"] / np.maximum(n, 1.0)) / d, o["D"] / d)
+        u = np.finfo(np.float64).eps
+        tol = np.where(walked, 1e-12 * scale / (np.maximum(n, 1.0) * d), 0.0)
+        tol += 2.0 * u * (np.abs(o["D"]) + np.abs(o["MCh"]) / np.maximum(n, 1.0)) / d
+        tol += 2.0 * u * np.abs(g_h)
+        assert np.all(np.abs(gpu["g"][sl] - g_h) <= tol), e["source"]
+        if histograms:
+            assert np.array_equal(e["supp"].cpu().numpy(), o["supp"]), e["source"]
+            assert np.array_equal(e["h"].cpu().numpy(), o["h"]), e["source"]
+            assert np.array_equal(e["hist"].cpu().numpy(), o["hist"]), e["source"]
+
+
+@pytest.mark.parametrize("kw", [{}, {"group": 64, "spread": 20}, {"tilde_tau_max": 1}])
+def test_counts_er300(saba, orc, kw):
+    g = graphgen.largest_component(graphgen.er_gnm(300, 1200, 3))
+    lam = graphgen.spectral_lambda(g)
+    sources = list(range(0, g.n, 3))[::-1]  # any order: the layout follows the list
+    print(f"counts er300 n={g.n} sources={len(sources)} {kw}", flush=True)
+    sg = saba.SabaGraph.from_graph(g)
+    per, out, st = saba.aesc_counts(sg, sources, 0.1, lam, 5, **kw)
+    ref = _oracle_counts(orc, g, sources, 0.1, lam, 5, **kw)
+    _check(per, out, ref)
+    assert st["walk_steps"] == sum(int(np.sum(2 * o["nreq"] * (o["tau"] - o["ttau"])))
+                                   for o in ref)
+    # the same entries as the all-edges run of the estimator
+    full, _ = saba.aesc_edge_stats(sg, 0.1, lam, seed=5, **kw)
+    for e in per:
+        s, d, eo = e["source"], e["degree"], e["edge_off"]
+        e0 = int(g.row_ptr[s])
+        for k in ("tau", "nreq", "MC", "vis0", "vis1", "g"):
+            assert np.array_equal(out[k][eo:eo + d].cpu().numpy(),
+                                  full[k][e0:e0 + d].cpu().numpy()), k
+
+
+def _hub_graph(seed=5):
+    # Erdos-Renyi core plus three hubs of degree 300 / 500 / 900 (rows above the 256-entry
+    # hub threshold at every level of the push)
+    rng = np.random.default_rng(seed)
+    base = graphgen.er_gnm(1500, 4500, seed)
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    u, v = [rows], [base.col_idx.astype(np.int64)]
+    for hub, deg in ((0, 300), (1, 500), (2, 900)):
+        nb = rng.choice(np.arange(3, base.n), size=deg, replace=False)
+        u.append(np.full(deg, hub))
+        v.append(nb)
+    g = graphgen.canonical_csr(np.concatenate(u), np.concatenate(v), base.n)
+    g = graphgen.largest_component(g)
+    return g, graphgen.spectral_lambda(g)
+
+
+def test_counts_hub_graph(saba, orc):
+    g, lam = _hub_graph()
+    deg = np.diff(g.row_ptr)
+    hubs = np.flatnonzero(deg > 256)
+    assert hubs.size == 3
+    # the hubs, some of their neighbours and some vertices far from them
+    others = np.random.default_rng(1).choice(np.setdiff1d(np.arange(g.n), hubs), 12,
+                                             replace=False)
+    sources = [int(x) for x in np.concatenate([hubs, others])]
+    print(f"counts hub graph n={g.n} dmax={deg.max()} sources={len(sources)}", flush=True)
+    sg = saba.SabaGraph.from_graph(g)
+    per, out, _ = saba.aesc_counts(sg, sources, 0.2, lam, 3)
+    ref = _oracle_counts(orc, g, sources, 0.2, lam, 3)
+    _check(per, out, ref)
+
+
+def test_counts_reject_bad_layouts(saba):
+    import ctypes
+    import torch
+    from paper_2410_14056_amd import _binding as b
+    g = graphgen.largest_component(graphgen.er_gnm(100, 300, 2))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    with pytest.raises(saba.SabaError):
+        saba.aesc_counts(sg, [4, 9, 4], 0.2, lam, 1)  # repeated source
+    with pytest.raises(saba.SabaError):
+        saba.aesc_counts(sg, [g.n], 0.2, lam, 1)  # out of range
+    # a filling call with a layout that is not the sizing call's
+    L = saba.load()
+    p = b._aesc_params(0.2, lam, 1)
+    lay = (b.CountSource * 2)()
+    lay[0].source, lay[1].source = 3, 7
+    st = b.Stats()
+    stream = b._stream_ptr()
+    assert L.saba_aesc_counts(sg.handle, ctypes.byref(p), lay, 2, None, None, None, None, None,
+                              None, None, None, None, None, ctypes.byref(st), stream) == 0
+    tot_s = lay[1].supp_off + lay[1].support
+    tot_h = lay[1].hist_off + 2 * lay[1].degree * lay[1].support
+    supp = torch.empty(tot_s, dtype=torch.int32, device="cuda")
+    h = torch.empty(tot_s, dtype=torch.float64, device="cuda")
+    hist = torch.empty(tot_h, dtype=torch.int64, device="cuda")
+    args = (b._ptr(supp), b._ptr(h), b._ptr(hist), None, None, None, None, None, None, None,
+            ctypes.byref(st), stream)
+    assert L.saba_aesc_counts(sg.handle, ctypes.byref(p), lay, 2, *args) == 0
+    lay[1].hist_off += 1  # not a dense packing
+    assert L.saba_aesc_counts(sg.handle, ctypes.byref(p), lay, 2, *args) == b.SABA_E_INVALID
+    lay[1].hist_off -= 1
+    # a layout sized under other parameters: pure Monte Carlo keeps the support {s}, so the
+    # sizes differ (checked on the device; nothing is written outside the layout)
+    assert max(lay[0].support, lay[1].support) > 1
+    p2 = b._aesc_params(0.2, lam, 1, tilde_tau_max=0)
+    assert L.saba_aesc_counts(sg.handle, ctypes.byref(p2), lay, 2, *args) == b.SABA_E_INVALID
+    # partial outputs
+    assert L.saba_aesc_counts(sg.handle, ctypes.byref(p), lay, 2, b._ptr(supp), None, None,
+                              None, None, None, None, None, None, None, ctypes.byref(st),
+                              stream) == b.SABA_E_INVALID
+    torch.cuda.synchronize()
+
+
+def test_chung_lu_1e6_counts_match_oracle(saba, orc):
+    """The 10^6-vertex Chung-Lu graph at eps = 0.1: 24 edges of the benchmark's seeded 1% query
+    (endpoints of degree <= 24) and a source whose row is above the hub threshold.  The integer internals of
+    the edges' directed estimates and the histograms of their sources match the oracle, and
+    the query run in the benchmark's launch configuration returns g(u, v) + g(v, u) of exactly
+    these directed estimates."""
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+    lam = graphgen.spectral_lambda(g)
+    ce = graphgen.canonical_edges(g)
+    perm = np.random.default_rng(7).permutation(g.m)
+    k = int(round(0.01 * g.m))
+    q = np.ascontiguousarray(ce[np.sort(perm[:k])])
+    deg = np.diff(g.row_ptr)
+    ok = np.flatnonzero(np.maximum(deg[q[:, 0]], deg[q[:, 1]]) <= 24)
+    pick = np.sort(np.random.default_rng(3).choice(ok, 24, replace=False))
+    sources = [int(x) for x in np.unique(q[pick].ravel())]
+    print(f"chung-lu 1e6 counts n={g.n} m={g.m} q={k} sources={len(sources)}", flush=True)
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    sq, _ = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.1, lam, 1)
+    per, out, _ = saba.aesc_counts(sg, sources, 0.1, lam, 1)
+    ref = _oracle_counts(orc, g, sources, 0.1, lam, 1)
+    _check(per, out, ref)
+    # the query's entries are the sums of these directed estimates, bit for bit
+    gd = out["g"].cpu().numpy()
+    at = {e["source"]: e for e in per}
+    sqh = sq.cpu().numpy()
+    for j in pick:
+        u, v = int(q[j, 0]), int(q[j, 1])
+        iu = int(np.searchsorted(g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]], v))
+        iv = int(np.searchsorted(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]], u))
+        assert sqh[j] == gd[at[u]["edge_off"] + iu] + gd[at[v]["edge_off"] + iv]
+    # a source with a hub row; the sizing call alone gives the same per-edge internals
+    hub = int(np.flatnonzero((deg > 256) & (deg <= 320))[0])
+    per_h, out_h, _ = saba.aesc_counts(sg, [hub], 0.1, lam, 1)
+    ref_h = _oracle_counts(orc, g, [hub], 0.1, lam, 1)
+    _check(per_h, out_h, ref_h)
+    per_s, out_s, _ = saba.aesc_counts(sg, [hub], 0.1, lam, 1, histograms=False)
+    assert per_s[0]["support"] == per_h[0]["support"] and per_s[0]["ttau"] == per_h[0]["ttau"]
+    for kk in ("tau", "nreq", "D", "MC", "vis0", "vis1", "g"):
+        assert torch.equal(out_s[kk], out_h[kk]), kk

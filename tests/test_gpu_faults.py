@@ -119,3 +119,23 @@ def test_fail_allocation_argument(saba):
     with pytest.raises(saba.SabaError) as ei:
         saba.fail_allocation(-1)
     assert ei.value.name == "SABA_E_INVALID"
+
+
+def test_walk_index_limits(saba, orc):
+    """Walk keys carry a 32-bit walk index: 2^32 walks from uniform starts, or a directed edge
+    needing 2^32 walk pairs, are refused (SABA_E_OVERFLOW) before any walk runs; the handle
+    stays usable.  The oracle refuses the same estimator case."""
+    g = graphgen.largest_component(graphgen.er_gnm(40, 120, 3))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    with pytest.raises(saba.SabaError) as e:
+        saba.walks(sg, None, 4, 1, n_walks=1 << 32)
+    assert e.value.name == "SABA_E_OVERFLOW"
+    # eps = 1e-4 with pure Monte Carlo: c = 32 ln(4m/delta) / eps^2 > 3e10 pairs per edge
+    with pytest.raises(saba.SabaError) as e:
+        saba.aesc(sg, 1e-4, lam, 1, tilde_tau_max=0)
+    assert e.value.name == "SABA_E_OVERFLOW"
+    with pytest.raises(ValueError):
+        orc.aesc(g, 1e-4, lam, 1, tilde_tau_max=0)
+    r = saba.walks(sg, None, 4, 1, n_walks=1000)
+    assert int(r.visits.sum()) == 4000

@@ -122,12 +122,20 @@ def rmat20():
 
 
 def test_rmat20_full_size(saba, orc, rmat20):
+    """The walk benchmark at full size (R-MAT scale 20, 2^24 walks of 64 steps, two visit-log
+    chunks) in its launch configuration (explicit uniform starts, autotuned knobs): the
+    endpoint and visit histograms of the bouquet and naive kernels equal the oracle's over
+    the whole workload, for independent walks (G = 1) and grouped ones (G = 64, S = 20)."""
+    import os
     import torch
     g = rmat20
     print(f"rmat20 n={g.n} nnz={g.nnz}", flush=True)
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     W, L = 1 << 24, 64
-    src = torch.from_numpy(graphgen.uniform_sources(g, W, 1)).cuda()
+    src_np = graphgen.uniform_sources(g, W, 1)
+    src = torch.from_numpy(src_np).cuda()
+    saba.autotune_walks(sg, src, L, 1)
+    threads = min(16, os.cpu_count() or 1)
     res = {}
     for G, S in ((1, 0), (64, 20)):
         for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
@@ -138,6 +146,9 @@ def test_rmat20_full_size(saba, orc, rmat20):
         assert a[0].sum() == W and a[1].sum() == W * L
         deg = np.diff(g.row_ptr)
         assert np.all(a[1][deg == 0] == 0)
+        print(f"rmat20 full-size oracle G={G} S={S} ({threads} threads)", flush=True)
+        ep_o, vi_o = orc.walks_histogram(g, src_np, L, seed=1, G=G, S=S, nthreads=threads)
+        assert np.array_equal(b[0], ep_o) and np.array_equal(b[1], vi_o)
     # bit-exact against the oracle on a 2^18-walk slice at full graph size
     sub = graphgen.uniform_sources(g, 1 << 18, 9)
     ep_o, vi_o = orc.walks_histogram(g, sub, L, seed=1)

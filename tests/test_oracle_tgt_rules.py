@@ -286,3 +286,15 @@ def test_push_stop_rule_ties_stop(orc, name):
         if checked >= 8:
             break
     assert checked >= 1, "no tie case found"
+
+
+def test_walk_pair_limit(orc):
+    """A directed edge whose NWalks count reaches 2^32 pairs is refused: walk keys carry a
+    32-bit index, so more pairs would repeat walks and the count's independence would fail.
+    Just below the limit the estimate runs."""
+    g = graphgen.largest_component(graphgen.er_gnm(16, 30, 2))
+    lam = graphgen.spectral_lambda(g)
+    with pytest.raises(ValueError):
+        orc.aesc(g, 1e-4, lam, seed=1, tilde_tau_max=0)
+    sc, o = orc.aesc(g, 0.3, lam, seed=1, tilde_tau_max=0)
+    assert o["nreq"].max() < 2 ** 32
