@@ -411,6 +411,24 @@ int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, in
                saba_stats *stats, void *stream);
 
 /*
+ * saba_walks for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same walks and the same
+ * histograms, bit for bit, with every scratch buffer taken from a fixed 256 MiB region of
+ * device memory that the library holds on each device until the process ends.  The call
+ * makes no hipMalloc, hipFree or other allocating call; the caller passes d_endpoint and
+ * d_visits (device, n int64 each) and the sources.  Only mode SABA_WALK_BOUQUET with
+ * SABA_SOURCES_EXPLICIT is accepted; time_kernels is ignored (no events are created).
+ * Scratch use: 8 n + 8 (n + 1) bytes for the start offsets, 4 W for the walk order, and the
+ * visit log of a chunk of walks (chunks shrink to fit, down to 256 walks).  A call that does
+ * not fit returns SABA_E_INVALID ("more scratch than the fixed region holds") before any walk
+ * runs.  All calls on one device share the region: calls that overlap in time on one device
+ * (other streams or threads) race and must not be issued.
+ * Errors: those of saba_walks, and SABA_E_INVALID for another mode or source mode.
+ */
+int saba_walks_noalloc(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint,
+                       int64_t *d_visits, saba_stats *stats, void *stream);
+
+/*
  * All-edges spanning centrality (Alg. 1, TGT+), SC(e) as defined in Sec. 2.1,
  * estimated to within eps with probability 1 - delta when group == 1.
  *   d_sc[m] (double): estimate of the i-th undirected edge in canonical order

@@ -32,4 +32,5 @@ from ._binding import (  # noqa: F401
     probe_random_reads,
     load,
     walks,
+    walks_noalloc,
 )

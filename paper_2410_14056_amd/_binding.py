@@ -174,7 +174,7 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
            "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc",
-           "saba_debug_fail_allocation", "saba_aesc_counts"]
+           "saba_debug_fail_allocation", "saba_aesc_counts", "saba_walks_noalloc"]
 
 _lib = None
 
@@ -195,6 +195,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_graph_destroy.argtypes = [P]
     L.saba_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
     L.saba_walks.argtypes = [P, ctypes.POINTER(WalkParams), P, P, ctypes.POINTER(Stats), P]
+    L.saba_walks_noalloc.argtypes = [P, ctypes.POINTER(WalkParams), P, P, ctypes.POINTER(Stats),
+                                     P]
     L.saba_aesc.argtypes = [P, ctypes.POINTER(AescParams), P, ctypes.POINTER(Stats), P]
     L.saba_aesc_query.argtypes = [P, ctypes.POINTER(AescParams), P, i64, P, ctypes.POINTER(Stats), P]
     L.saba_aesc_edge_stats.argtypes = [P, ctypes.POINTER(AescParams), P, P, P, P, P, P, P, P, P,
@@ -328,7 +330,8 @@ def walks(graph: SabaGraph, sources: torch.Tensor | None, length: int, seed: int
           spread: int = 0, mode: int = SABA_WALK_BOUQUET, time_kernels: bool = False,
           endpoint: torch.Tensor | None = None, visits: torch.Tensor | None = None,
           stream=None, sampler: int = SABA_SAMPLER_KEYED,
-          distinct: bool = False, n_walks: int | None = None) -> WalkResult:
+          distinct: bool = False, n_walks: int | None = None,
+          _entry: str = "saba_walks") -> WalkResult:
     """saba_walks: endpoint / visit histograms of the walks started at `sources` (int32,
     device), or, with sources=None, of n_walks walks from uniform sources the library draws
     (SABA_SOURCES_UNIFORM); with distinct=True also the branching statistics (int64 [9])."""
@@ -347,9 +350,19 @@ def walks(graph: SabaGraph, sources: torch.Tensor | None, length: int, seed: int
                    int(mode), int(bool(time_kernels)), sptr, int(sampler), smode,
                    None if dist is None else dist.data_ptr())
     st = Stats()
-    _check(load().saba_walks(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
-                             ctypes.byref(st), _stream_ptr(stream)))
+    _check(getattr(load(), _entry)(graph.handle, ctypes.byref(p), _ptr(endpoint), _ptr(visits),
+                                   ctypes.byref(st), _stream_ptr(stream)))
     return WalkResult(endpoint, visits, st.as_dict(), dist)
+
+
+def walks_noalloc(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int,
+                  endpoint: torch.Tensor, visits: torch.Tensor, group: int = 1, spread: int = 0,
+                  stream=None, sampler: int = SABA_SAMPLER_KEYED) -> WalkResult:
+    """saba_walks_noalloc: saba_walks in bouquet mode from explicit sources, with the caller's
+    output tensors and the library's fixed device scratch (no allocation in the call)."""
+    return walks(graph, sources, length, seed, group=group, spread=spread,
+                 mode=SABA_WALK_BOUQUET, endpoint=endpoint, visits=visits, stream=stream,
+                 sampler=sampler, _entry="saba_walks_noalloc")
 
 
 def probe_random_reads(log2_records: int = 26, steps: int = 256, stream=None) -> dict:

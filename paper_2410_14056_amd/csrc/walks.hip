@@ -15,6 +15,7 @@
 #include <hipcub/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <mutex>
 
 #include "saba_internal.hpp"
 
@@ -706,8 +707,63 @@ static int ensure_pool(Graph *g, hipStream_t s) {
     return SABA_OK;
 }
 
+// The fixed scratch of saba_walks_noalloc: one region per device, held until the process ends.
+// Host code uses only the address hipGetSymbolAddress returns for the current device (the
+// array's name is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int noalloc_scratch(void **out) {
+    int dev = 0;
+    SABA_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the fixed-scratch table");
+        return SABA_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        SABA_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("hipGetSymbolAddress returned no address for the fixed scratch");
+            return SABA_E_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SABA_OK;
+}
+
+// Scratch of one walk call: the handle's grow-only buffers, or a fixed device region carved
+// front to back (the entry point that allocates nothing).  Each slot is taken once per call.
+struct WalkArena {
+    Graph *g = nullptr;
+    char *base = nullptr;  // fixed region, or null for the handle's buffers
+    size_t cap = 0, used = 0;
+    static size_t up(size_t x) { return (x + 255) & ~(size_t)255; }
+    size_t left() const { return up(used) >= cap ? 0 : cap - up(used); }
+    template <class T>
+    int get(int slot, size_t bytes, T **out) {
+        if (!base) {
+            SABA_TRY(g->walk_scratch[slot].ensure(bytes));
+            *out = g->walk_scratch[slot].as<T>();
+            return SABA_OK;
+        }
+        if (bytes > left()) {
+            set_error("the walk call needs more scratch than the fixed region holds");
+            return SABA_E_INVALID;
+        }
+        *out = reinterpret_cast<T *>(base + up(used));
+        used = up(used) + bytes;
+        return SABA_OK;
+    }
+};
+
 static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
-                      int64_t *d_visits, saba_stats *st, hipStream_t s) {
+                      int64_t *d_visits, saba_stats *st, hipStream_t s, WalkArena &ar) {
     const int64_t W = p->n_walks;
     const int32_t n = g->n;
     const int32_t L = p->length;
@@ -743,8 +799,8 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             set_error("uniform sources need a vertex with an edge");
             return SABA_E_INVALID;
         }
-        SABA_TRY(g->walk_scratch[7].ensure(sizeof(int32_t) * (size_t)W));
-        int32_t *src = g->walk_scratch[7].as<int32_t>();
+        int32_t *src = nullptr;
+        SABA_TRY(ar.get(7, sizeof(int32_t) * (size_t)W, &src));
         uniform_sources_kernel<<<(unsigned)std::min<int64_t>((W + 255) / 256, 1 << 16), 256, 0, s>>>(
             g->pool, g->npool, p->seed, W, src);
         SABA_HIP_TRY(hipGetLastError());
@@ -754,8 +810,8 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         p = &drawn;
     }
 
-    SABA_TRY(g->walk_scratch[3].ensure(sizeof(int32_t)));
-    int32_t *err = g->walk_scratch[3].as<int32_t>();
+    int32_t *err = nullptr;
+    SABA_TRY(ar.get(3, sizeof(int32_t), &err));
     SABA_HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), s));
     SABA_HIP_TRY(hipMemsetAsync(d_endpoint, 0, sizeof(int64_t) * (size_t)n, s));
     SABA_HIP_TRY(hipMemsetAsync(d_visits, 0, sizeof(int64_t) * (size_t)n, s));
@@ -769,22 +825,23 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
 
     if (W > 0 && p->mode == SABA_WALK_NAIVE) {
         // rank of each walk among the walks of its start vertex, in list order
-        SABA_TRY(g->walk_scratch[0].ensure(sizeof(int64_t) * (size_t)n));
-        SABA_TRY(g->walk_scratch[1].ensure(sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n)));
-        SABA_TRY(g->walk_scratch[2].ensure(sizeof(int32_t) * (size_t)W));
-        SABA_TRY(g->walk_scratch[4].ensure(sizeof(uint32_t) * 2 * (size_t)W));
-        SABA_TRY(g->walk_scratch[5].ensure(sizeof(uint32_t) * (size_t)W));
-        auto *counts = g->walk_scratch[0].as<unsigned long long>();
-        int64_t *offs = g->walk_scratch[1].as<int64_t>();
+        unsigned long long *counts = nullptr;
+        int64_t *offs = nullptr;
+        int32_t *sorted_src = nullptr;
+        uint32_t *iota = nullptr, *rank = nullptr;
+        void *sort_tmp = nullptr;
+        SABA_TRY(ar.get(0, sizeof(int64_t) * (size_t)n, &counts));
+        SABA_TRY(ar.get(1, sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n), &offs));
+        SABA_TRY(ar.get(2, sizeof(int32_t) * (size_t)W, &sorted_src));
+        SABA_TRY(ar.get(4, sizeof(uint32_t) * 2 * (size_t)W, &iota));
+        SABA_TRY(ar.get(5, sizeof(uint32_t) * (size_t)W, &rank));
         void *scan_tmp = offs + n + 1;
-        int32_t *sorted_src = g->walk_scratch[2].as<int32_t>();
-        uint32_t *iota = g->walk_scratch[4].as<uint32_t>(), *sorted_j = iota + W;
-        uint32_t *rank = g->walk_scratch[5].as<uint32_t>();
+        uint32_t *sorted_j = iota + W;
         size_t sort_bytes = 0;
         SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, p->d_sources,
                                                         sorted_src, iota, sorted_j, (int)W, 0,
                                                         32, s));
-        SABA_TRY(g->walk_scratch[6].ensure(std::max<size_t>(sort_bytes, 1)));
+        SABA_TRY(ar.get(6, std::max<size_t>(sort_bytes, 1), &sort_tmp));
         SABA_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int64_t) * (size_t)n, s));
         const unsigned cblocks =
             (unsigned)std::min<int64_t>((W + kWalkBlock - 1) / kWalkBlock, 1 << 16);
@@ -793,7 +850,7 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         SABA_HIP_TRY(hipGetLastError());
         SABA_TRY(scan_i64(reinterpret_cast<int64_t *>(counts), offs, n, scan_tmp, s));
         iota_kernel<<<cblocks, kWalkBlock, 0, s>>>(iota, W);
-        SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(g->walk_scratch[6].ptr, sort_bytes,
+        SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes,
                                                         p->d_sources, sorted_src, iota, sorted_j,
                                                         (int)W, 0, 32, s));
         list_rank_kernel<<<cblocks, kWalkBlock, 0, s>>>(sorted_src, sorted_j, W, offs, g->vrec, n,
@@ -821,13 +878,13 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
     } else if (W > 0) {
         // bucket order of the walks
-        SABA_TRY(g->walk_scratch[0].ensure(sizeof(int64_t) * (size_t)n));
-        SABA_TRY(g->walk_scratch[1].ensure(sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n)));
-        SABA_TRY(g->walk_scratch[2].ensure(sizeof(int32_t) * (size_t)W));
-        auto *counts = g->walk_scratch[0].as<unsigned long long>();
-        int64_t *offs = g->walk_scratch[1].as<int64_t>();
+        unsigned long long *counts = nullptr;
+        int64_t *offs = nullptr;
+        int32_t *bsrc = nullptr;
+        SABA_TRY(ar.get(0, sizeof(int64_t) * (size_t)n, &counts));
+        SABA_TRY(ar.get(1, sizeof(int64_t) * ((size_t)n + 1) + scan_tmp_bytes(n), &offs));
+        SABA_TRY(ar.get(2, sizeof(int32_t) * (size_t)W, &bsrc));
         void *scan_tmp = offs + n + 1;
-        int32_t *bsrc = g->walk_scratch[2].as<int32_t>();
         SABA_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int64_t) * (size_t)n, s));
         const unsigned cblocks =
             (unsigned)std::min<int64_t>((W + kWalkBlock - 1) / kWalkBlock, 1 << 16);
@@ -877,19 +934,31 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             wc = std::min<int64_t>(W, wc / kWalkBlock * kWalkBlock);
             const int want_blocks = g->cfg.walk_blocks > 0 ? g->cfg.walk_blocks : kPersistBlocks;
             const int wpl = g->cfg.walks_per_lane > 0 ? g->cfg.walks_per_lane : 1;
+            // scratch of the chunk loop for chunks of c walks: the visit and endpoint logs, the
+            // bucket-ordered entries of the largest log (the visit log, or the start list) and
+            // the per-bucket counters with their scan
+            const auto chunk_bytes = [&](int64_t c, size_t *lg, size_t *pt, size_t *cn) {
+                const int nb = (int)std::min<int64_t>(want_blocks, (c + kWalkBlock - 1) / kWalkBlock);
+                const int64_t nc = (int64_t)nbk * nb;
+                *lg = sizeof(int32_t) * (size_t)(std::max<int64_t>((int64_t)L * c, 1) + c);
+                *pt = sizeof(int32_t) * (size_t)std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * c, W);
+                *cn = sizeof(int64_t) * (size_t)(4 * nc + 2) + scan_tmp_bytes(nc);
+                return WalkArena::up(*lg) + WalkArena::up(*pt) + WalkArena::up(*cn);
+            };
+            size_t lg_b = 0, pt_b = 0, cn_b = 0;
+            if (ar.base)  // a fixed region: shorter chunks until the chunk scratch fits
+                while (wc > kWalkBlock && chunk_bytes(wc, &lg_b, &pt_b, &cn_b) > ar.left())
+                    wc = std::max<int64_t>(kWalkBlock, (wc / 2) / kWalkBlock * kWalkBlock);
+            chunk_bytes(wc, &lg_b, &pt_b, &cn_b);
             const int nblk = (int)std::min<int64_t>(want_blocks, (wc + kWalkBlock - 1) / kWalkBlock);
             const int64_t ncnt = (int64_t)nbk * nblk;
             const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
-            SABA_TRY(g->walk_scratch[4].ensure(sizeof(int32_t) * (size_t)(logn + wc)));
-            // bucket-ordered entries of the largest log: the visit log, or the start list
-            const int64_t partn = std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * wc, W);
-            SABA_TRY(g->walk_scratch[5].ensure(sizeof(int32_t) * (size_t)partn));
-            SABA_TRY(g->walk_scratch[6].ensure(sizeof(int64_t) * (size_t)(4 * ncnt + 2) +
-                                               scan_tmp_bytes(ncnt)));
-            int32_t *vlog = g->walk_scratch[4].as<int32_t>();
+            int32_t *vlog = nullptr, *part = nullptr;
+            int64_t *cnt_v = nullptr;
+            SABA_TRY(ar.get(4, lg_b, &vlog));
+            SABA_TRY(ar.get(5, pt_b, &part));
+            SABA_TRY(ar.get(6, cn_b, &cnt_v));
             int32_t *elog = vlog + logn;
-            int32_t *part = g->walk_scratch[5].as<int32_t>();
-            int64_t *cnt_v = g->walk_scratch[6].as<int64_t>();
             int64_t *cnt_e = cnt_v + ncnt;
             int64_t *pos = cnt_e + ncnt;  // ncnt + 1 entries
             void *ctmp = pos + ncnt + 2;
@@ -989,6 +1058,30 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
 
 using namespace saba;
 
+extern "C" int saba_walks_noalloc(saba_graph *gh, const saba_walk_params *p,
+                                  int64_t *d_endpoint, int64_t *d_visits, saba_stats *st,
+                                  void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!p) {
+        set_error("params is NULL");
+        return SABA_E_INVALID;
+    }
+    if (p->mode != SABA_WALK_BOUQUET || p->source_mode != SABA_SOURCES_EXPLICIT) {
+        set_error("saba_walks_noalloc runs bouquet walks from explicit sources only");
+        return SABA_E_INVALID;
+    }
+    void *base = nullptr;
+    SABA_TRY(noalloc_scratch(&base));
+    saba_walk_params q = *p;
+    q.time_kernels = 0;  // no event objects either
+    WalkArena ar;
+    ar.g = G(gh);
+    ar.base = static_cast<char *>(base);
+    ar.cap = kNoAllocScratchBytes;
+    return walks_impl(G(gh), &q, d_endpoint, d_visits, st, static_cast<hipStream_t>(stream), ar);
+}
+
 extern "C" int saba_walks(saba_graph *gh, const saba_walk_params *p, int64_t *d_endpoint,
                           int64_t *d_visits, saba_stats *st, void *stream) {
     clear_error();
@@ -997,7 +1090,9 @@ extern "C" int saba_walks(saba_graph *gh, const saba_walk_params *p, int64_t *d_
         set_error("params is NULL");
         return SABA_E_INVALID;
     }
-    return walks_impl(G(gh), p, d_endpoint, d_visits, st, static_cast<hipStream_t>(stream));
+    WalkArena ar;
+    ar.g = G(gh);
+    return walks_impl(G(gh), p, d_endpoint, d_visits, st, static_cast<hipStream_t>(stream), ar);
 }
 
 extern "C" int saba_autotune_walks(saba_graph *gh, const saba_walk_params *sample,
@@ -1034,7 +1129,9 @@ extern "C" int saba_autotune_walks(saba_graph *gh, const saba_walk_params *sampl
             double ms = 0.0;
             for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
                 saba_stats st{};
-                const int rc = walks_impl(g, &p, ep, vi, &st, s);
+                WalkArena ar;
+                ar.g = g;
+                const int rc = walks_impl(g, &p, ep, vi, &st, s, ar);
                 if (rc != SABA_OK) {
                     g->cfg = saved;
                     return rc;
