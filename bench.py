@@ -8,12 +8,20 @@ neighbour choice, bouquet execution, G = 1.  A step is one saba_walks call:
 source bucketing, key set-up, the walks and the int64 endpoint / visit
 histograms (the synthetic benchmark of Sec. 5.4).
 
-Secondary (`aesc`): edges/s of the TGT+ estimator at eps = 0.1 on the Chung-Lu
-graph n = 10^6, average degree 10, exponent 2.5, seed 1, largest component,
-over a seeded 1% sample of its edges (saba_aesc_query; the paper estimates its
-largest graph the same way, from a fixed 5% of the edges).
+Secondary legs of the default run:
+  walks_side_by_side  naive generation and grouped bouquets (G = 64, S = 20) on the same starts;
+  er2000              all edges of ER n = 2000, m = 8000 at eps = 0.3 (latency);
+  aesc                edges/s of the TGT+ estimator at eps = 0.1 on the Chung-Lu graph
+                      n = 10^6, average degree 10, exponent 2.5, seed 1, largest component,
+                      over a seeded 1% sample of its edges (saba_aesc_query; the paper
+                      estimates its largest graph the same way, from a fixed 5% of the edges);
+  aesc_all_edges      all edges of the same graph (sum of the estimates against n - 1);
+  serve               16 resident graphs, Poisson requests: an offered load with backpressure
+                      and a sustained load at 70% of the served capacity; p50_ms / p99_ms are
+                      the sustained phase's.
 
-`roofline` prices the dominant kernel with its algorithmic bytes; `cpu_baseline`
+`roofline` prices the dominant kernel with its algorithmic bytes (64 B sectors), with the
+128 B line the L2 fetches and the measured random-read ceiling beside it; `cpu_baseline`
 times the CPU oracle on a bounded slice of the same workload.
 """
 from __future__ import annotations
@@ -30,19 +38,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walk-steps/s and AESC edges/s at ε=0.1 (1 GPU); p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-# walk kernel: one random 128 B line per step (the 16-byte walk entry of the next vertex) plus
-# the 4 B coalesced visit-log store.  gfx950's L2 fetches whole 128 B lines from memory for
-# every read: the request-size counters (TCC_EA0_RDREQ_{32B,64B,128B}) show only 128 B read
-# requests, for a plain copy and for the random walk-entry reads alike.
-WALK_KERNEL_BYTES_PER_STEP = 132
-# the same step counted in 64 B sectors (the HBM3E burst), for comparison
-WALK_KERNEL_BYTES_PER_STEP_64B = 68
-# whole walk call, priced at a vertex record, an adjacency entry and a random visit-counter
-# update per step
+# walk kernel, algorithmic bytes per step in 64 B sectors (the HBM3E access unit): one random
+# sector for the 16-byte walk entry of the next vertex, plus the 4 B coalesced visit-log store
+WALK_KERNEL_BYTES_PER_STEP = 68
+# the same step priced at what gfx950 moves for it: its L2 fetches whole 128 B lines for every
+# read (the request-size counters TCC_EA0_RDREQ_{32B,64B,128B} show only 128 B read requests,
+# for a plain copy and for the random walk-entry reads alike)
+WALK_KERNEL_BYTES_PER_STEP_LINE = 132
+# naive walk kernel: the vertex record and the adjacency entry (two random sectors) and a
+# random 8 B counter update (a third sector) per step
 WALK_STEP_BYTES = 192
-# estimator walk kernel: the 128 B line of the walk entry of the next vertex per step (the
-# support bitmaps, and the h values of frequently hit vertices, are meant to stay cached)
-AESC_STEP_BYTES = 128
+# estimator walk kernel: one random 64 B sector for the walk entry of the next vertex per step
+# (the support bitmaps, and the h values of frequently hit vertices, are meant to stay cached);
+# and the same step at the 128 B line the L2 fetches
+AESC_STEP_BYTES = 64
+AESC_STEP_BYTES_LINE = 128
+TRAFFIC_BASIS = ("bytes the L2 requested from the memory fabric (FETCH_SIZE x 2.0 + WRITE_SIZE, "
+                 "each scaled by a plain 1 GiB copy), served by HBM or the 256 MB Infinity Cache")
 COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
 
@@ -160,7 +172,10 @@ def bench_walks(args, saba, torch, np):
     per_launch_steps = W * L // chunks
     bouquet = mode == saba.SABA_WALK_BOUQUET
     kbytes = WALK_KERNEL_BYTES_PER_STEP if bouquet else WALK_STEP_BYTES
-    achieved = kbytes * per_launch_steps / (k_ms / chunks * 1e-3) / 1e9
+    launch_s = k_ms / chunks * 1e-3
+    achieved = kbytes * per_launch_steps / launch_s / 1e9
+    line = WALK_KERNEL_BYTES_PER_STEP_LINE * per_launch_steps / launch_s / 1e9
+    side = side_walks(args, saba, torch, np, sg, src, L, seed, ep, vi) if args.workload == "all" else None
     return g, {
         "value": W * L * args.steps / dt,
         "ms_per_step": dt * 1e3 / args.steps,
@@ -180,23 +195,56 @@ def bench_walks(args, saba, torch, np):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(W, L, chunks) if bouquet else None,
+            "traffic_basis": TRAFFIC_BASIS,
             "kernel": "walk_bouquet_log_kernel" if bouquet else "walk_naive_kernel",
             "kernel_ms_per_launch": k_ms / chunks,
             "launches_per_step": chunks,
             "bytes_per_step": kbytes,
-            "frac_at_64B_sectors": (WALK_KERNEL_BYTES_PER_STEP_64B * per_launch_steps /
-                                    (k_ms / chunks * 1e-3) / 1e9 / HBM_PEAK_GBS) if bouquet else None,
+            "bytes_basis": ("one random 64 B sector (the 16 B walk entry) + the 4 B coalesced "
+                            "log store per step") if bouquet else
+                           "vertex record, adjacency entry and counter update: 3 random 64 B sectors",
             "steps_per_launch": per_launch_steps,
+            "line_pricing": {
+                "bytes_per_step": WALK_KERNEL_BYTES_PER_STEP_LINE, "achieved": line,
+                "frac": line / HBM_PEAK_GBS,
+                "basis": "the 128 B L2 line a random read fetches on gfx950 (TCC_EA0_RDREQ_128B) "
+                         "+ the 4 B log store"} if bouquet else None,
             "random_read_ceiling": None if probe is None else {
                 "reads_per_s": probe["reads_per_s"],
-                "kernel_steps_per_s": per_launch_steps / (k_ms / chunks * 1e-3),
-                "frac": per_launch_steps / (k_ms / chunks * 1e-3) / probe["reads_per_s"],
+                "kernel_steps_per_s": per_launch_steps / launch_s,
+                "frac": per_launch_steps / launch_s / probe["reads_per_s"],
                 "probe": "saba_probe_random_reads: 2^26 records of 16 B (1 GiB), 8192 x 256 lanes, "
                          "256 dependent reads each"},
             "call": {"ms": call_ms, "count_ms": float(np.mean(cms)),
-                     "achieved_at_192B_per_step": WALK_STEP_BYTES * W * L / (call_ms * 1e-3) / 1e9},
+                     "walk_ms": k_ms, "steps_per_s": W * L / (call_ms * 1e-3)},
         },
+        "side_by_side": side,
     }
+
+
+def side_walks(args, saba, torch, np, sg, src, L, seed, ep, vi):
+    """The walk benchmark's other arrangements on the same starts: naive generation (one lane per
+    walk in list order, atomic counters) and the paper's grouped bouquets (G = 64, S = 20:
+    walks of a group share their path until their choices split, so a wavefront's reads
+    coalesce; the walks are then correlated within a group).  Same histograms as G = 1 only
+    for naive; G = 64 draws other walks."""
+    W = int(src.numel())
+    rows = []
+    for name, mode, G, S, reps in (("naive G=1", saba.SABA_WALK_NAIVE, 1, 0, 3),
+                                   ("bouquet G=64 S=20", saba.SABA_WALK_BOUQUET, 64, 20, 10)):
+        saba.walks(sg, src, L, seed, group=G, spread=S, mode=mode, endpoint=ep, visits=vi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = saba.walks(sg, src, L, seed, group=G, spread=S, mode=mode, endpoint=ep,
+                           visits=vi, time_kernels=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert int(vi.sum().item()) == W * L and int(ep.sum().item()) == W
+        rows.append({"arrangement": name, "ms_per_step": dt * 1e3,
+                     "walk_steps_per_s": W * L / dt, "walk_kernel_ms": r.stats["kernel_ms"]})
+        progress(f"walks {name}: {dt * 1e3:.2f} ms per call")
+    return rows
 
 
 def _hist_percentile(h, q):
@@ -304,12 +352,23 @@ def bench_walks_paper(args, saba, torch, np):
             "starts": int(pool.numel()), "rows": rows}
 
 
+_CL1M = {}
+
+
+def chung_lu_1e6():
+    """The 10^6-vertex Chung-Lu graph (average degree 10, exponent 2.5, seed 1, largest
+    component) and its lambda, built once per run."""
+    if not _CL1M:
+        import graphgen
+        t0 = time.perf_counter()
+        g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+        _CL1M.update(g=g, lam=graphgen.spectral_lambda(g), prep_s=time.perf_counter() - t0)
+    return _CL1M["g"], _CL1M["lam"], _CL1M["prep_s"]
+
+
 def bench_aesc(args, saba, torch, np):
     import graphgen
-    t0 = time.perf_counter()
-    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
-    lam = graphgen.spectral_lambda(g)
-    prep_s = time.perf_counter() - t0
+    g, lam, prep_s = chung_lu_1e6()
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     ce = graphgen.canonical_edges(g)
     perm = np.random.default_rng(7).permutation(g.m)
@@ -335,6 +394,7 @@ def bench_aesc(args, saba, torch, np):
     assert bool(torch.isfinite(sc).all().item())
     walk_s = st["kernel_ms"] * 1e-3
     achieved = AESC_STEP_BYTES * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
+    line = AESC_STEP_BYTES_LINE * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
     out = {
         "value": k / dt,
         "unit": "edges/s",
@@ -353,8 +413,13 @@ def bench_aesc(args, saba, torch, np):
         "roofline": {"bound": "hbm", "kernel": "mc_walk_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": estimator_traffic(st["walk_steps"], st["batches"]),
+                     "traffic_basis": TRAFFIC_BASIS,
                      "kernel_ms": st["kernel_ms"], "launches": st["batches"],
-                     "bytes_per_step": AESC_STEP_BYTES},
+                     "bytes_per_step": AESC_STEP_BYTES,
+                     "bytes_basis": "one random 64 B sector (the 16 B walk entry) per step",
+                     "line_pricing": {"bytes_per_step": AESC_STEP_BYTES_LINE, "achieved": line,
+                                      "frac": line / HBM_PEAK_GBS,
+                                      "basis": "the 128 B L2 line a random read fetches"}},
     }
     # the eigenpair form of the truncation (omega = 64) on the same query: the pairs are found
     # once per graph (timed separately) and cached; same eps guarantee
@@ -464,16 +529,16 @@ def bench_omega(args, saba, torch, np):
 
 def bench_aesc_full(args, saba, torch, np):
     """All edges of the 10^6-vertex Chung-Lu graph at eps = 0.1: the edges in canonical order
-    cut into 20 query calls (each result equals the all-edges call's entry), one progress line
-    per call."""
+    cut into 40 query calls (each result equals the all-edges call's entry), one progress line
+    per call (the last calls, edges between low-degree vertices, carry most of the walks)."""
     import graphgen
-    g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
+    g, lam1, _ = chung_lu_1e6()
     omega = args.omega
     # omega > 0: the radius of the rest of the spectrum comes from the library
-    lam = graphgen.spectral_lambda(g) if omega == 0 else 0.0
+    lam = lam1 if omega == 0 else 0.0
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     ce = graphgen.canonical_edges(g)
-    parts = np.array_split(np.arange(g.m), 20)
+    parts = np.array_split(np.arange(g.m), 40)
     saba.aesc_query(sg, torch.from_numpy(np.ascontiguousarray(ce[:64])).cuda(), args.aesc_eps, lam, 1,
                     omega=omega)
     torch.cuda.synchronize()
@@ -486,7 +551,7 @@ def bench_aesc_full(args, saba, torch, np):
         torch.cuda.synchronize()
         steps += st["walk_steps"]
         sums += float(sc.sum().item())
-        progress(f"aesc full: {k + 1}/20 parts, {time.perf_counter() - t0:.1f} s")
+        progress(f"aesc full: {k + 1}/{len(parts)} parts, {time.perf_counter() - t0:.1f} s")
     dt = time.perf_counter() - t0
     return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_all_edges"
             + (f"_omega{omega}" if omega else ""), "edges": g.m, "n": g.n,
@@ -797,6 +862,29 @@ def bench_serve(args, saba, torch, np):
                 "served_edges_per_s": nedge / t_served, "speedup": t_plain / t_served,
                 "identical": same}
 
+    if args.serve_short:
+        # the default run's serving leg: the offered load with backpressure, then a sustained
+        # load without refusals (its p50 / p99 are the headline latencies)
+        with server() as srv:
+            srv.wait(srv.submit(15, ces[15][:256], 0.1, lams[15], 1))
+        torch.cuda.synchronize()
+        res = {"workload": "serve_16_chung_lu_n1e4-1e6_k10_b2.5_q1-4096_eps0.1-0.3",
+               "graphs": len(graphs), "vertices": sum(g.n for g in graphs),
+               "edges": sum(g.m for g in graphs), "prep_s": prep_s, "lanes": args.serve_lanes,
+               "mem_budget_gib": args.serve_mem_gib}
+        with server(max_queued_edges=args.serve_queue_edges) as srv:
+            res["offered"] = open_loop(srv, args.serve_rate, args.serve_seconds, 11, "offered")
+            res["offered"]["queue_bound_edges"] = args.serve_queue_edges
+        off = res["offered"]
+        off["refused_frac"] = off["refused"] / max(1, off["offered"])
+        cap = off.get("edges_per_s", 0.0) / 2048.5
+        rate = max(0.2, args.serve_sustain_frac * cap)
+        progress(f"serve workload: sustained load at {rate:.2f} requests/s")
+        with server(max_queued_edges=1 << 40) as srv:
+            res["sustained"] = open_loop(srv, rate, args.serve_sustain_seconds, 12, "sustained")
+        res["sustained"]["refused_frac"] = res["sustained"]["refused"] / max(1, res["sustained"]["offered"])
+        return res
+
     # warm the lanes' scratch on the largest graph
     with server() as srv:
         t = srv.submit(15, ces[15][:256], 0.1, lams[15], 1)
@@ -916,6 +1004,12 @@ def main():
     ap.add_argument("--omega", type=int, default=0,
                     help="eigenpairs of the all-edges estimator run (aesc_full)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full", action="store_true",
+                    help="skip the all-edges estimator pass of the default run")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving leg of the default run")
+    ap.add_argument("--serve-short", action="store_true",
+                    help="serving: only the offered and sustained phases (the default run's leg)")
     ap.add_argument("--no-omega", action="store_true",
                     help="skip the omega = 64 row of the estimator leg (counter runs)")
     args = ap.parse_args()
@@ -953,6 +1047,8 @@ def main():
         g, w = bench_walks(args, saba, torch, np)
         out.update({"value": w["value"], "ms_per_step": w["ms_per_step"], "config": w["config"],
                     "roofline": w["roofline"]})
+        if w.get("side_by_side"):
+            out["walks_side_by_side"] = w["side_by_side"]
         print(json.dumps({"progress": "walks done", "value": w["value"]}), file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = walks_cpu_baseline(g, args.length, 1)
@@ -1010,12 +1106,28 @@ def main():
     if args.workload in ("all", "aesc"):
         a = bench_aesc(args, saba, torch, np)
         out["aesc"] = a
+        progress(f"aesc 1% query done: {a['value']:.0f} edges/s")
         if args.workload == "aesc":
             out.update({"value": a["value"], "unit": "edges/s", "dtype": "f64",
                         "ms_per_step": a["seconds"] * 1e3,
                         "config": {"workload": a["workload"]}, "roofline": a["roofline"]})
             if "cpu_baseline" in a:
                 out["cpu_baseline"] = a["cpu_baseline"]
+    if args.workload == "all" and not args.no_full:
+        f = bench_aesc_full(args, saba, torch, np)
+        out["aesc_all_edges"] = f
+        progress(f"aesc all edges done: {f['edges_per_s']:.0f} edges/s, sum {f['sum_sc']:.1f} "
+                 f"(n - 1 = {f['n_minus_1']})")
+    if args.workload == "all" and not args.no_serve:
+        args.serve_short = True
+        args.serve_sustain_seconds = min(args.serve_sustain_seconds, 10.0)
+        r = bench_serve(args, saba, torch, np)
+        sus = r["sustained"]
+        out["serve"] = r
+        out["p50_ms"], out["p99_ms"] = sus.get("p50_ms"), sus.get("p99_ms")
+        out["latency_load"] = (f"sustained Poisson load at {sus['offered_rate']:.2f} req/s "
+                               f"(70% of the served capacity), {sus['refused']} of "
+                               f"{sus['offered']} refused")
     print(json.dumps(out), flush=True)
 
 
