@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define SABA_ABI_VERSION 3
+#define SABA_ABI_VERSION 4
 
 /* status codes */
 #define SABA_OK 0
@@ -223,6 +223,10 @@ typedef struct {
     int32_t walk_blocks;     /* blocks of the persistent bouquet walk kernel (0: 8192) */
     int32_t est_walk_blocks; /* blocks of the estimator's walk-pair kernel (0: 1024) */
     int32_t est_push_blocks; /* blocks of the estimator's frontier kernels (0: 2048) */
+    int32_t walk_chunks;     /* chunks a bouquet walk call's visit log is cut into; the counting
+                                passes of a chunk run on a second stream while the next chunk
+                                walks (0: 4 when each chunk still holds 2^19 walks, else as few
+                                as the 2^29-entry log allows; at most 64) */
 } saba_exec_config;
 
 /* Options of saba_server_create; none of them changes a result. */
@@ -344,7 +348,8 @@ int saba_graph_set_config(saba_graph *g, const saba_exec_config *cfg);
 
 /*
  * Autotuner of the bouquet walk kernel: runs the walk workload `sample` (bouquet mode) under
- * each candidate (walks per lane 1, 2, 4; 1024, 2048, 4096 or 8192 persistent blocks), times
+ * each candidate (walks per lane 1, 2, 4; 1024, 2048, 4096 or 8192 persistent blocks; 1, 4 or
+ * 8 visit-log chunks), times
  * the whole call (walks and counting passes) with HIP events, keeps the fastest in the handle
  * and returns it in *best
  * (may be NULL).  The sample's outputs are written to scratch the call allocates.

@@ -281,6 +281,9 @@ static void destroy_graph(Graph *g) {
     if (g->nbr) (void)hipFree(g->nbr);
     if (g->pool) (void)hipFree(g->pool);
     for (auto &b : g->walk_scratch) b.release();
+    for (auto &e : g->walk_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->walk_aux) (void)hipStreamDestroy(g->walk_aux);
     g->est.release();
     for (auto &sp : g->spectra) sp->dev.release();
     delete g;
@@ -497,7 +500,7 @@ extern "C" int saba_graph_set_config(saba_graph *gh, const saba_exec_config *cfg
                   cfg->walks_per_lane == 2 || cfg->walks_per_lane == 4) ||
         cfg->walk_blocks < 0 || cfg->walk_blocks > (1 << 16) || cfg->est_walk_blocks < 0 ||
         cfg->est_walk_blocks > (1 << 16) || cfg->est_push_blocks < 0 ||
-        cfg->est_push_blocks > (1 << 16)) {
+        cfg->est_push_blocks > (1 << 16) || cfg->walk_chunks < 0 || cfg->walk_chunks > 64) {
         set_error("invalid execution configuration");
         return SABA_E_INVALID;
     }

@@ -90,6 +90,10 @@ struct Graph {
     int4 *nbr = nullptr;
     // reusable scratch of the synchronous calls
     DevBuf walk_scratch[8];
+    // the walk call's second stream and its buffer hand-over events (walks done x2, counting
+    // done x2), created on first use
+    hipStream_t walk_aux = nullptr;
+    hipEvent_t walk_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     Workspace est;
     saba_exec_config cfg{};  // execution knobs (0 = default)
     // lambda of each graph computed on the device for requests that leave it to the library

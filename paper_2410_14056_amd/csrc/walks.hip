@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "saba_internal.hpp"
 
@@ -30,6 +32,7 @@ constexpr int64_t kLogCap = 1ll << 29;   // visit-log entries per chunk of walks
 constexpr int64_t kHistSliceMin = 1 << 14, kHistSliceMax = 1 << 18;
 constexpr int64_t kHistBlocks = 2048;
 constexpr int kPersistBlocks = 8192;
+constexpr int64_t kPipeChunks = 4, kPipeMinWalks = (int64_t)1 << 19;
 
 // Counts of equal keys held by adjacent active lanes are merged, so one wavefront
 // issues one atomic per run of equal vertices instead of one per lane.
@@ -707,6 +710,39 @@ static int ensure_pool(Graph *g, hipStream_t s) {
     return SABA_OK;
 }
 
+// Events of one call's per-chunk timing, destroyed with the call.
+struct EventList {
+    std::vector<hipEvent_t> e;
+    int create(int64_t k) {
+        e.assign((size_t)k, nullptr);
+        for (auto &x : e) SABA_HIP_TRY(hipEventCreate(&x));
+        return SABA_OK;
+    }
+    ~EventList() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// The walk call's second stream (default priority) and the events that hand the visit-log
+// buffers between the walks and the counting passes, created once per handle.
+static int ensure_walk_pipeline(Graph *g) {
+    if (g->walk_aux) return SABA_OK;
+    hipStream_t st = nullptr;
+    SABA_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (auto &e : g->walk_ev) {
+        if (e) continue;
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) {
+            (void)hipStreamDestroy(st);
+            set_error(std::string("hipEventCreateWithFlags: ") + hipGetErrorString(r));
+            return SABA_E_HIP;
+        }
+    }
+    g->walk_aux = st;
+    return SABA_OK;
+}
+
 // The fixed scratch of saba_walks_noalloc: one region per device, held until the process ends.
 // Host code uses only the address hipGetSymbolAddress returns for the current device (the
 // array's name is a host-side stand-in, not a device address).
@@ -929,21 +965,37 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
         } else {
             counted_separately = true;
-            // chunks of walks whose visit log fits kLogCap entries
+            // chunks of walks whose visit log fits kLogCap entries, and with the handle's buffers
+            // the requested number of chunks (by default kPipeChunks while a chunk keeps
+            // kPipeMinWalks walks, one full round of the persistent grid)
             int64_t wc = std::max<int64_t>(kWalkBlock, kLogCap / std::max<int32_t>(L, 1));
             wc = std::min<int64_t>(W, wc / kWalkBlock * kWalkBlock);
             const int want_blocks = g->cfg.walk_blocks > 0 ? g->cfg.walk_blocks : kPersistBlocks;
             const int wpl = g->cfg.walks_per_lane > 0 ? g->cfg.walks_per_lane : 1;
+            if (!ar.base) {
+                const int64_t want_ch =
+                    g->cfg.walk_chunks > 0 ? g->cfg.walk_chunks
+                                           : std::max<int64_t>(1, std::min<int64_t>(kPipeChunks, W / kPipeMinWalks));
+                const int64_t per = ((W + want_ch - 1) / want_ch + kWalkBlock - 1) / kWalkBlock * kWalkBlock;
+                wc = std::min<int64_t>(wc, std::max<int64_t>(kWalkBlock, per));
+            }
+            // With the handle's buffers and more than one chunk, the counting of chunk k runs on
+            // a second stream while chunk k + 1 walks: the logs and the per-block bucket counts
+            // are double-buffered (the walks are bound by the rate of random line fetches, the
+            // counting passes stream, so they share the memory system well).  A fixed region
+            // keeps one buffer set and runs everything in order on the caller's stream.
+            const bool overlap = !ar.base && W > wc;
+            const int nbuf = overlap ? 2 : 1;
             // scratch of the chunk loop for chunks of c walks: the visit and endpoint logs, the
             // bucket-ordered entries of the largest log (the visit log, or the start list) and
-            // the per-bucket counters with their scan
+            // the per-bucket counters (nbuf sets of per-block counts, one scan) with their scan
             const auto chunk_bytes = [&](int64_t c, size_t *lg, size_t *pt, size_t *cn) {
                 const int nb = (int)std::min<int64_t>(want_blocks, (c + kWalkBlock - 1) / kWalkBlock);
                 const int64_t nc = (int64_t)nbk * nb;
                 *lg = sizeof(int32_t) * (size_t)(std::max<int64_t>((int64_t)L * c, 1) + c);
                 *pt = sizeof(int32_t) * (size_t)std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * c, W);
-                *cn = sizeof(int64_t) * (size_t)(4 * nc + 2) + scan_tmp_bytes(nc);
-                return WalkArena::up(*lg) + WalkArena::up(*pt) + WalkArena::up(*cn);
+                *cn = sizeof(int64_t) * (size_t)(2 * nbuf * nc + nc + 2) + scan_tmp_bytes(nc);
+                return nbuf * WalkArena::up(*lg) + WalkArena::up(*pt) + WalkArena::up(*cn);
             };
             size_t lg_b = 0, pt_b = 0, cn_b = 0;
             if (ar.base)  // a fixed region: shorter chunks until the chunk scratch fits
@@ -953,15 +1005,16 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             const int nblk = (int)std::min<int64_t>(want_blocks, (wc + kWalkBlock - 1) / kWalkBlock);
             const int64_t ncnt = (int64_t)nbk * nblk;
             const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
-            int32_t *vlog = nullptr, *part = nullptr;
-            int64_t *cnt_v = nullptr;
-            SABA_TRY(ar.get(4, lg_b, &vlog));
+            const size_t lg_stride = WalkArena::up(lg_b) / sizeof(int32_t);
+            int32_t *vlog_all = nullptr, *part = nullptr;
+            int64_t *cnt_all = nullptr;
+            SABA_TRY(ar.get(4, (size_t)(nbuf - 1) * WalkArena::up(lg_b) + lg_b, &vlog_all));
             SABA_TRY(ar.get(5, pt_b, &part));
-            SABA_TRY(ar.get(6, cn_b, &cnt_v));
-            int32_t *elog = vlog + logn;
-            int64_t *cnt_e = cnt_v + ncnt;
-            int64_t *pos = cnt_e + ncnt;  // ncnt + 1 entries
+            SABA_TRY(ar.get(6, cn_b, &cnt_all));
+            int64_t *pos = cnt_all + 2 * nbuf * ncnt;  // ncnt + 1 entries
             void *ctmp = pos + ncnt + 2;
+            // the start-count phase uses the first counter set
+            int64_t *cnt_v = cnt_all;
             // walks per start vertex, counted like the visits: the start list read as a log of
             // up to 32 rows (per bucket and block in LDS, then bucket order, then a histogram
             // per bucket), then starts without neighbours cleared and flagged
@@ -978,47 +1031,73 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                                  kWalkBlock, 0, s>>>(g->vrec, n, counts, err);
             SABA_HIP_TRY(hipGetLastError());
             SABA_TRY(order_walks());
-            float walk_ms = 0.f, count_ms = 0.f;
-            for (int64_t w0 = 0; w0 < W; w0 += wc) {
+            hipStream_t sc = s;  // the counting stream
+            if (overlap) {
+                SABA_TRY(ensure_walk_pipeline(g));
+                sc = g->walk_aux;
+            }
+            const int64_t nchunks = (W + wc - 1) / wc;
+            EventList tev;  // per chunk: walk start / end on s, count start / end on sc
+            if (timing) SABA_TRY(tev.create(4 * nchunks));
+            for (int64_t k = 0; k < nchunks; ++k) {
+                const int64_t w0 = k * wc;
                 const int64_t this_wc = std::min<int64_t>(wc, W - w0);
-                if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[1], s));
+                const int bi = (int)(k % nbuf);
+                int32_t *vl = vlog_all + (size_t)bi * lg_stride;
+                int32_t *el = vl + logn;
+                auto *cv = reinterpret_cast<long long *>(cnt_all + (int64_t)bi * 2 * ncnt);
+                auto *ce = cv + ncnt;
+                // buffer bi is free once the counting of chunk k - 2 has read it
+                if (overlap && k >= 2) SABA_HIP_TRY(hipStreamWaitEvent(s, g->walk_ev[2 + bi], 0));
+                if (timing) SABA_HIP_TRY(hipEventRecord(tev.e[4 * k], s));
                 const size_t lds = sizeof(uint32_t) * 2 * nbk;
-                auto *cv = reinterpret_cast<long long *>(cnt_v);
-                auto *ce = reinterpret_cast<long long *>(cnt_e);
                 switch (sm) {
                     case SABA_SAMPLER_KEYED:
                         launch_log_sm<SABA_SAMPLER_KEYED>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, w0,
-                                                          this_wc, bsh, nbk, vlog, elog, cv, ce,
-                                                          dist);
+                                                          this_wc, bsh, nbk, vl, el, cv, ce, dist);
                         break;
                     case SABA_SAMPLER_KEYED_MOD:
                         launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
-                                                              w0, this_wc, bsh, nbk, vlog, elog,
-                                                              cv, ce, dist);
+                                                              w0, this_wc, bsh, nbk, vl, el, cv, ce,
+                                                              dist);
                         break;
                     case SABA_SAMPLER_STREAM_MOD:
                         launch_log_sm<SABA_SAMPLER_STREAM_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc,
-                                                               offs, w0, this_wc, bsh, nbk, vlog,
-                                                               elog, cv, ce, dist);
+                                                               offs, w0, this_wc, bsh, nbk, vl, el,
+                                                               cv, ce, dist);
                         break;
                     default:
                         launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
-                                                            w0, this_wc, bsh, nbk, vlog, elog, cv,
-                                                            ce, dist);
+                                                            w0, this_wc, bsh, nbk, vl, el, cv, ce,
+                                                            dist);
                 }
                 SABA_HIP_TRY(hipGetLastError());
-                if (timing) SABA_HIP_TRY(hipEventRecord(ev.e[2], s));
+                if (timing) SABA_HIP_TRY(hipEventRecord(tev.e[4 * k + 1], s));
+                if (overlap) {
+                    SABA_HIP_TRY(hipEventRecord(g->walk_ev[bi], s));
+                    SABA_HIP_TRY(hipStreamWaitEvent(sc, g->walk_ev[bi], 0));
+                }
+                if (timing) SABA_HIP_TRY(hipEventRecord(tev.e[4 * k + 2], sc));
                 if (L > 0)
-                    SABA_TRY(bucket_count(vlog, L, this_wc, offs, w0, nblk, bsh, nbk, cnt_v, pos,
-                                          ctmp, part, n, vi, s, (int64_t)L * this_wc));
-                SABA_TRY(bucket_count(elog, 1, this_wc, offs, w0, nblk, bsh, nbk, cnt_e, pos, ctmp,
-                                      part, n, ep, s, this_wc));
-                if (timing) {
-                    SABA_HIP_TRY(hipEventRecord(ev.e[3], s));
-                    SABA_HIP_TRY(hipEventSynchronize(ev.e[3]));
+                    SABA_TRY(bucket_count(vl, L, this_wc, offs, w0, nblk, bsh, nbk,
+                                          reinterpret_cast<int64_t *>(cv), pos, ctmp, part, n, vi,
+                                          sc, (int64_t)L * this_wc));
+                SABA_TRY(bucket_count(el, 1, this_wc, offs, w0, nblk, bsh, nbk,
+                                      reinterpret_cast<int64_t *>(ce), pos, ctmp, part, n, ep, sc,
+                                      this_wc));
+                if (timing) SABA_HIP_TRY(hipEventRecord(tev.e[4 * k + 3], sc));
+                if (overlap) SABA_HIP_TRY(hipEventRecord(g->walk_ev[2 + bi], sc));
+            }
+            // the caller's stream sees the last counting pass (and with it every earlier one)
+            if (overlap)
+                SABA_HIP_TRY(hipStreamWaitEvent(s, g->walk_ev[2 + (int)((nchunks - 1) % nbuf)], 0));
+            float walk_ms = 0.f, count_ms = 0.f;
+            if (timing) {
+                SABA_HIP_TRY(hipEventSynchronize(tev.e[4 * (nchunks - 1) + 3]));
+                for (int64_t k = 0; k < nchunks; ++k) {
                     float a = 0.f, b = 0.f;
-                    SABA_HIP_TRY(hipEventElapsedTime(&a, ev.e[1], ev.e[2]));
-                    SABA_HIP_TRY(hipEventElapsedTime(&b, ev.e[2], ev.e[3]));
+                    SABA_HIP_TRY(hipEventElapsedTime(&a, tev.e[4 * k], tev.e[4 * k + 1]));
+                    SABA_HIP_TRY(hipEventElapsedTime(&b, tev.e[4 * k + 2], tev.e[4 * k + 3]));
                     walk_ms += a;
                     count_ms += b;
                 }
@@ -1121,28 +1200,31 @@ extern "C" int saba_autotune_walks(saba_graph *gh, const saba_walk_params *sampl
     double best_ms = 1e300;
     const int wpls[] = {1, 2, 4};
     const int blocks[] = {1024, 2048, 4096, 8192};
+    const int chunks[] = {1, 4, 8};
     for (int wpl : wpls)
-        for (int nb : blocks) {
-            g->cfg = saved;
-            g->cfg.walks_per_lane = wpl;
-            g->cfg.walk_blocks = nb;
-            double ms = 0.0;
-            for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
-                saba_stats st{};
-                WalkArena ar;
-                ar.g = g;
-                const int rc = walks_impl(g, &p, ep, vi, &st, s, ar);
-                if (rc != SABA_OK) {
-                    g->cfg = saved;
-                    return rc;
+        for (int nb : blocks)
+            for (int ch : chunks) {
+                g->cfg = saved;
+                g->cfg.walks_per_lane = wpl;
+                g->cfg.walk_blocks = nb;
+                g->cfg.walk_chunks = ch;
+                double ms = 0.0;
+                for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                    saba_stats st{};
+                    WalkArena ar;
+                    ar.g = g;
+                    const int rc = walks_impl(g, &p, ep, vi, &st, s, ar);
+                    if (rc != SABA_OK) {
+                        g->cfg = saved;
+                        return rc;
+                    }
+                    if (rep > 0) ms += st.total_ms;  // the whole call: walks and counting passes
                 }
-                if (rep > 0) ms += st.total_ms;  // the whole call: walks and counting passes
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    pick = g->cfg;
+                }
             }
-            if (ms < best_ms) {
-                best_ms = ms;
-                pick = g->cfg;
-            }
-        }
     g->cfg = pick;
     if (best) *best = pick;
     return SABA_OK;

@@ -31,8 +31,18 @@ def test_walk_knobs_do_not_change_results(saba, orc):
             r = saba.walks(sg, t, 13, 9, group=8, spread=24)
             assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), (wpl, blocks)
             assert np.array_equal(r.visits.cpu().numpy(), vi_o), (wpl, blocks)
+    # visit-log chunks counted on the second stream while the next chunk walks (ragged last
+    # chunk; 2 chunks, an odd count, and more chunks than the double buffer)
+    for ch in (2, 3, 7, 64):
+        for wpl, blocks in ((2, 1024), (1, 64)):
+            saba.set_config(sg, walks_per_lane=wpl, walk_blocks=blocks, walk_chunks=ch)
+            r = saba.walks(sg, t, 13, 9, group=8, spread=24, time_kernels=True)
+            assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), (ch, wpl, blocks)
+            assert np.array_equal(r.visits.cpu().numpy(), vi_o), (ch, wpl, blocks)
+            assert r.stats["kernel_ms"] > 0 and r.stats["count_ms"] > 0
     best = saba.autotune_walks(sg, t, 13, 9)
     assert best["walks_per_lane"] in (1, 2, 4) and best["walk_blocks"] in (1024, 2048, 4096, 8192)
+    assert best["walk_chunks"] in (1, 4, 8)
     assert saba.get_config(sg) == best
     r = saba.walks(sg, t, 13, 9, group=8, spread=24)
     assert np.array_equal(r.visits.cpu().numpy(), vi_o)
@@ -94,7 +104,8 @@ def test_results_do_not_depend_on_the_stream(saba):
 
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
-    for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20}):
+    for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20},
+               {"walk_chunks": 65}, {"walk_chunks": -1}):
         with pytest.raises(saba.SabaError) as ei:
             saba.set_config(sg, **kw)
         assert ei.value.name == "SABA_E_INVALID"
