@@ -570,12 +570,9 @@ def _batch_graph(spec):
     else:
         side = max(2, int(round(n ** 0.5)))
         g = graphgen.largest_component(graphgen.grid_diagonals(side, side, 0.05, seed))
-    if kind == 2:
-        # grids mix so slowly (lambda within 1e-4 of 1) that every tau reaches the cap; any
-        # upper bound below 1 gives the same run, and 1 - 1e-9 bounds it for these sizes
-        lam = 1.0 - 1e-9
-    else:
-        lam = graphgen.spectral_lambda(g)
+    # grids: lambda is left to the device (saba_graph_lambda on the batched handle); the CPU
+    # eigensolver is slow to separate their eigenvalues near 1
+    lam = None if kind == 2 else graphgen.spectral_lambda(g)
     return g.row_ptr, g.col_idx, lam
 
 
@@ -614,10 +611,11 @@ def parallel_build(fn, items, label):
     return built
 
 
-def batch_workload(G=256, edges_per_graph=32):
+def batch_workload(G=256, edge_frac=0.01):
     """The batched workload's inputs: G graphs (kind k % 3, n uniform in [1e3, 2e5], seed
-    1000 + k), lambda per graph, eps per graph from {0.1, 0.2, 0.3}, and edges_per_graph
-    seeded query edges per graph (int32 [q, 2])."""
+    1000 + k), lambda per graph (None for the grids: see device_lambdas), eps per graph from
+    {0.1, 0.2, 0.3}, and a seeded fraction edge_frac of each graph's edges (at least one) as
+    its query (int32 [q, 2])."""
     import graphgen
     import numpy as np
     rng = np.random.default_rng(4)
@@ -629,62 +627,141 @@ def batch_workload(G=256, edges_per_graph=32):
     qs = []
     for g in graphs:
         ce = graphgen.canonical_edges(g)
-        pick = np.sort(rng.choice(g.m, min(g.m, edges_per_graph), replace=False))
+        q = max(1, int(round(edge_frac * g.m)))
+        pick = np.sort(rng.choice(g.m, min(g.m, q), replace=False))
         qs.append(np.ascontiguousarray(ce[pick]))
     return graphs, lams, epss, qs
+
+
+def device_lambdas(saba, mg, lams):
+    """lambda of the graphs the workload left to the device: the upper estimate
+    saba_graph_lambda returns for graph k of the batched handle (below 1)."""
+    out = list(lams)
+    for k, lam in enumerate(lams):
+        if lam is None:
+            r = saba.graph_lambda(mg, index=k, max_iters=1000)
+            out[k] = min(r["lambda_bound"], 1.0 - 1e-12)
+    return out
+
+
+def tuning_sample(reqs, every=16, edges=64):
+    """The autotuner's sample of a request list: every 16th request, its first 64 edges."""
+    return [{**r, "edges": r["edges"][:edges]} for r in reqs[::every]]
+
+
+def truncation_bound(g, q, lam, eps, tau_cap):
+    """Largest certified truncation error over the query edges q of graph g when tau is capped:
+    (1/d_u + 1/d_v) lam^(tau + 1) / (1 - lam) at tau = min(CalculateTau, tau_cap), and whether
+    every edge meets eps / 2 (Alg. 1's truncation budget)."""
+    import math
+    import numpy as np
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    w = 1.0 / deg[q[:, 0]] + 1.0 / deg[q[:, 1]]
+    # smallest tau with w lam^(tau+1) <= (eps/2)(1 - lam), from the log form
+    need = np.ceil(np.log((eps / 2.0) * (1.0 - lam) / w) / math.log(lam) - 1.0)
+    tau = np.minimum(np.maximum(need, 0.0), tau_cap)
+    bound = w * lam ** (tau + 1.0) / (1.0 - lam)
+    return float(bound.max()), bool(np.all(bound <= eps / 2.0 * (1.0 + 1e-9)))
 
 
 def bench_batch(args, saba, torch, np):
     """Batched estimation: 256 graphs of uneven size (n uniform in [1e3, 2e5]; one third each
     Erdos-Renyi with average degree 8, Chung-Lu with exponent 2.3, square grids with 5% random
-    diagonals), eps drawn from {0.1, 0.2, 0.3}, 32 random query edges per graph, tau capped at
-    128.  One saba_aesc_batch call on a multi-graph handle against one saba_aesc_query call per
-    graph; both must give identical results."""
+    diagonals), eps drawn from {0.1, 0.2, 0.3}, a seeded 1% of every graph's edges as its query,
+    tau capped at 128.  One saba_aesc_batch call on a multi-graph handle against one
+    saba_aesc_query call per graph; both must give identical results.  The grids mix so slowly
+    (lambda within 1e-3 of 1) that the cap leaves a truncation error far above eps: their
+    requests are reported apart as uncertified, and the certified throughput comes from a call
+    over the other requests alone."""
     G = args.batch_graphs
     t0 = time.perf_counter()
-    graphs, lams, epss, qnp = batch_workload(G, args.batch_edges)
+    graphs, lams0, epss, qnp = batch_workload(G, args.batch_frac)
     prep_s = time.perf_counter() - t0
     qs = [torch.from_numpy(q).cuda() for q in qnp]
     nq = sum(int(q.shape[0]) for q in qs)
-    # one call per graph (each graph resident in its own handle, uploaded beforehand)
-    handles = [saba.SabaGraph.from_graph(g, trusted=True) for g in graphs]
-    saba.aesc_query(handles[0], qs[0], epss[0], lams[0], 1, tau_cap=128)
-    torch.cuda.synchronize()
-    progress("batch workload: one call per graph")
-    t0 = time.perf_counter()
-    single = []
-    for k, (h, q, e, l) in enumerate(zip(handles, qs, epss, lams)):
-        single.append(saba.aesc_query(h, q, e, l, 1, tau_cap=128)[0])
-        if (k + 1) % 64 == 0:
-            progress(f"batch workload: {k + 1}/{G} single calls ({time.perf_counter() - t0:.1f} s)")
-    torch.cuda.synchronize()
-    t_single = time.perf_counter() - t0
-    progress("batch workload: one batched call")
-    del handles
     mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    t0 = time.perf_counter()
+    lams = device_lambdas(saba, mg, lams0)
+    lam_s = time.perf_counter() - t0
+    cert = [truncation_bound(g, q, l, e, 128) for g, q, l, e in zip(graphs, qnp, lams, epss)]
+    certified = [k for k in range(G) if cert[k][1]]
+    progress(f"batch workload: {nq} query edges, {len(certified)}/{G} requests certified at eps "
+             f"with tau <= 128 (device lambda of the grids in {lam_s:.1f} s)")
     reqs = [{"graph": k, "eps": epss[k], "lam": lams[k], "seed": 1, "edges": qs[k], "tau_cap": 128}
             for k in range(G)]
-    # the execution knobs (walk-pair and frontier-group grids) tuned on every 16th request;
-    # they do not change results
+    # one call per graph: each graph in its own handle, uploaded and warmed (its scratch
+    # sized by the same query) before its timed call, and freed afterwards, so the handles'
+    # scratch does not pile up; the times of the calls alone are summed
+    progress("batch workload: one call per graph")
+    single, single_s = {}, {}
+    t_wall = time.perf_counter()
+    for k in range(G):
+        h = saba.SabaGraph.from_graph(graphs[k], trusted=True)
+        saba.aesc_query(h, qs[k], epss[k], lams[k], 1, tau_cap=128)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        single[k] = saba.aesc_query(h, qs[k], epss[k], lams[k], 1, tau_cap=128)[0]
+        torch.cuda.synchronize()
+        single_s[k] = time.perf_counter() - t0
+        h.close()
+        if (k + 1) % 32 == 0:
+            progress(f"batch workload: {k + 1}/{G} single calls ({sum(single_s.values()):.1f} s "
+                     f"timed, {time.perf_counter() - t_wall:.0f} s wall)")
+    t_single = sum(single_s.values())
+    t_single_cert = sum(single_s[k] for k in certified)
+    # the execution knobs (walk-pair and frontier-group grids, static or queued walk-pair
+    # schedule) tuned on every 16th request, its first 64 edges; they do not change results
     progress("batch workload: autotuning the estimator grids")
     t0 = time.perf_counter()
-    tuned = saba.autotune_aesc(mg, reqs[::16])
+    tuned = saba.autotune_aesc(mg, tuning_sample(reqs))
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
-    progress(f"batch workload: tuned {tuned} in {tune_s:.1f} s; one batched call")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs, st = saba.aesc_batch(mg, reqs, time_kernels=True)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    same = all(bool(torch.equal(a, b)) for a, b in zip(single, outs))
+    progress(f"batch workload: tuned {tuned} in {tune_s:.1f} s; batched calls")
+
+    def batched(rs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, st = saba.aesc_batch(mg, rs, time_kernels=True)
+        torch.cuda.synchronize()
+        return outs, st, time.perf_counter() - t0
+
+    outs, st, t_batch = batched(reqs)
+    same = all(bool(torch.equal(single[k], outs[k])) for k in range(G))
     assert same, "batched results differ from single-graph results"
-    return {"workload": f"batch_{G}graphs_n1e3-2e5_er_cl_grid_q{args.batch_edges}",
+    outs_c, st_c, t_batch_cert = batched([reqs[k] for k in certified])
+    assert all(bool(torch.equal(single[k], o)) for k, o in zip(certified, outs_c))
+    # the two walk-pair schedules at the tuned grids
+    sched = {}
+    for wq in (0, 1):
+        saba.set_config(mg, **{**{k: v for k, v in tuned.items() if k != "reserved"},
+                               "est_walk_queue": wq})
+        _, st_q, t_q = batched(reqs)
+        sched["queue" if wq else "static"] = {"seconds": t_q, "walk_kernel_ms": st_q["kernel_ms"]}
+        progress(f"batch workload: {'queue' if wq else 'static'} schedule {t_q:.3f} s")
+    saba.set_config(mg, **{k: v for k, v in tuned.items() if k != "reserved"})
+    nq_cert = sum(int(qs[k].shape[0]) for k in certified)
+    kinds = {0: "erdos_renyi", 1: "chung_lu", 2: "grid"}
+    return {"workload": f"batch_{G}graphs_n1e3-2e5_er_cl_grid_q{args.batch_frac:g}",
             "graphs": G, "vertices": sum(g.n for g in graphs), "edges": sum(g.m for g in graphs),
-            "query_edges": nq, "prep_s": prep_s,
+            "query_edges": nq, "prep_s": prep_s, "device_lambda_s": lam_s,
             "single_calls_s": t_single, "single_edges_per_s": nq / t_single,
             "batched_s": t_batch, "batched_edges_per_s": nq / t_batch,
             "speedup": t_single / t_batch, "identical": same,
+            "certified": {"requests": len(certified), "query_edges": nq_cert,
+                          "kinds": sorted({kinds[k % 3] for k in certified}),
+                          "single_calls_s": t_single_cert,
+                          "batched_s": t_batch_cert, "batched_edges_per_s": nq_cert / t_batch_cert,
+                          "speedup": t_single_cert / t_batch_cert,
+                          "walk_steps": st_c["walk_steps"]},
+            "uncertified": {"requests": G - len(certified),
+                            "kinds": sorted({kinds[k % 3] for k in range(G) if not cert[k][1]}),
+                            "max_truncation_bound": max((cert[k][0] for k in range(G)
+                                                         if not cert[k][1]), default=0.0),
+                            "lambda_range": [min((lams[k] for k in range(G) if not cert[k][1]),
+                                                 default=0.0),
+                                             max((lams[k] for k in range(G) if not cert[k][1]),
+                                                 default=0.0)]},
+            "schedules": sched,
             "walk_steps": st["walk_steps"], "sources": st["sources"], "batches": st["batches"],
             "walk_kernel_ms": st["kernel_ms"], "tau_capped": bool(st["warnings"] & 1),
             "tuned": tuned, "autotune_s": tune_s}
@@ -979,7 +1056,8 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--paper-walks", type=int, default=2048,
                     help="walks per non-isolated vertex in --workload walks_paper")
-    ap.add_argument("--batch-edges", type=int, default=32)
+    ap.add_argument("--batch-frac", type=float, default=0.01,
+                    help="fraction of every graph's edges queried in --workload batch")
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--serve-mem-gib", type=float, default=32.0)
     ap.add_argument("--serve-max-batch", type=int, default=0)

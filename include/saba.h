@@ -227,6 +227,10 @@ typedef struct {
                                 passes of a chunk run on a second stream while the next chunk
                                 walks (0: 4 when each chunk still holds 2^19 walks, else as few
                                 as the 2^29-entry log allows; at most 64) */
+    int32_t est_walk_queue;  /* 1: the estimator's walk-pair launch takes its chunks from
+                                device work queues (one per XCD range of the chunk space);
+                                0: a fixed wavefront stride over the chunks */
+    int32_t reserved;
 } saba_exec_config;
 
 /* Options of saba_server_create; none of them changes a result. */
@@ -360,7 +364,8 @@ int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec
 /*
  * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
  * which may be NULL) under each candidate grid (512, 1024, 2048 or 4096 blocks for the
- * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels), times whole
+ * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels x the
+ * static or the work-queue walk-pair schedule), times whole
  * calls with HIP events, keeps the fastest in the handle and returns it in *best (may be
  * NULL).  The knobs do not change results; the sample's outputs hold its results on return.
  * Errors: those of saba_aesc_batch, SABA_E_INVALID for an empty sample.

@@ -863,7 +863,24 @@ __device__ __forceinline__ int32_t support_rank(const int32_t *__restrict__ F, i
     return lo;
 }
 
-template <bool kCount>
+// Work queue of the walk-pair launch (kQueue): the flat chunk space is cut into kXcds
+// contiguous ranges, one counter each.  A wavefront takes chunks from the range of its own
+// XCD first (consecutive chunks belong to one source, whose support bitmap and h values then
+// stay in that XCD's L2), then from the other ranges in turn.  The dequeue is wave-uniform by
+// construction: the lowest active lane takes the ticket and readfirstlane, which reads that
+// same lane, puts it in a scalar register, so every loop bound and cross-lane operation that
+// follows sees one value.  Each counter only grows, so every wavefront leaves every range.
+__device__ __forceinline__ int64_t wave_dequeue(unsigned long long *ctr) {
+    const unsigned long long act = __ballot(1);
+    const int leader = __builtin_ctzll(act);
+    unsigned long long v = 0;
+    if ((int)__lane_id() == leader) v = atomicAdd(ctr, 1ull);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <bool kCount, bool kQueue>
 __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int4 *__restrict__ nbr,
     const Slot *__restrict__ slots,
@@ -873,11 +890,11 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
     const double *__restrict__ hA, const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
     const uint32_t *__restrict__ bmB, double *__restrict__ partial,
     unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
-    Flags *__restrict__ fl, CountArgs ca) {
+    Flags *__restrict__ fl, CountArgs ca, unsigned long long *__restrict__ wq) {
     const int lane = __lane_id();
     const int64_t T = coff[nle];
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t c = xcd_block() * kWavesPerBlock + (threadIdx.x >> 6); c < T; c += nwaves) {
+    // chunk c: 64 walks of one instance edge, reduced over the wavefront in a fixed order
+    const auto chunk = [&](int64_t c) {
         const int64_t le = upper_index(coff, nle + 1, c);
         const int64_t b = upper_index(eb, nb + 1, le);
         const Slot sl = slots[b];
@@ -933,6 +950,22 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
             if (h0) atomicAdd(vis0 + ie, (unsigned long long)h0);
             if (h1) atomicAdd(vis1 + ie, (unsigned long long)h1);
         }
+    };
+    if (kQueue) {
+        const int xcd = (int)(blockIdx.x % kXcds);  // the dispatcher deals blocks round-robin
+        for (int r = 0; r < kXcds; ++r) {
+            const int q = (xcd + r) % kXcds;
+            const int64_t q0 = T * q / kXcds, q1 = T * (q + 1) / kXcds;
+            for (;;) {
+                const int64_t c = q0 + wave_dequeue(wq + q);
+                if (c >= q1) break;
+                chunk(c);
+            }
+        }
+    } else {
+        const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+        for (int64_t c = xcd_block() * kWavesPerBlock + (threadIdx.x >> 6); c < T; c += nwaves)
+            chunk(c);
     }
 }
 
@@ -1313,14 +1346,24 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
         const bool timing = tm && tm->on;
         if (timing) SABA_HIP_TRY(hipEventRecord(tm->a, s));
         const unsigned wgrid = grid_for(T, kWavesPerBlock, walk_blocks);
-        if (cx && cx->supp)
-            mc_walk_kernel<true><<<wgrid, kBlock, 0, s>>>(
-                g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle,
-                ea.tau, ea.nreq, hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, cx->ca);
-        else
-            mc_walk_kernel<false><<<wgrid, kBlock, 0, s>>>(
-                g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff, nle,
-                ea.tau, ea.nreq, hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, CountArgs{});
+        const bool queue = g->cfg.est_walk_queue == 1;
+        if (queue) SABA_HIP_TRY(hipMemsetAsync(fl->wq, 0, sizeof(fl->wq), s));
+#define SABA_MC_LAUNCH(C, Q, CA)                                                                  \
+    mc_walk_kernel<C, Q><<<wgrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, \
+                                                  bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq, \
+                                                  hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, \
+                                                  CA, fl->wq)
+        if (cx && cx->supp) {
+            if (queue)
+                SABA_MC_LAUNCH(true, true, cx->ca);
+            else
+                SABA_MC_LAUNCH(true, false, cx->ca);
+        } else if (queue) {
+            SABA_MC_LAUNCH(false, true, CountArgs{});
+        } else {
+            SABA_MC_LAUNCH(false, false, CountArgs{});
+        }
+#undef SABA_MC_LAUNCH
         SABA_HIP_TRY(hipGetLastError());
         if (timing) {
             SABA_HIP_TRY(hipEventRecord(tm->b, s));
@@ -1987,26 +2030,28 @@ extern "C" int saba_autotune_aesc(saba_graph *gh, const saba_aesc_request *sampl
     double best_ms = 1e300;
     const int walk_blocks[] = {512, 1024, 2048, 4096};
     const int push_blocks[] = {1024, 2048, 4096, 8192};
-    for (int wb : walk_blocks)
-        for (int pb : push_blocks) {
-            g->cfg = saved;
-            g->cfg.est_walk_blocks = wb;
-            g->cfg.est_push_blocks = pb;
-            double ms = 0.0;
-            for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
-                saba_stats st{};
-                const int rc = saba_aesc_batch(gh, sample, nreq, &o, &st, stream);
-                if (rc != SABA_OK) {
-                    g->cfg = saved;
-                    return rc;
+    for (int wq = 0; wq < 2; ++wq)
+        for (int wb : walk_blocks)
+            for (int pb : push_blocks) {
+                g->cfg = saved;
+                g->cfg.est_walk_blocks = wb;
+                g->cfg.est_push_blocks = pb;
+                g->cfg.est_walk_queue = wq;
+                double ms = 0.0;
+                for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                    saba_stats st{};
+                    const int rc = saba_aesc_batch(gh, sample, nreq, &o, &st, stream);
+                    if (rc != SABA_OK) {
+                        g->cfg = saved;
+                        return rc;
+                    }
+                    if (rep > 0) ms += st.total_ms;
                 }
-                if (rep > 0) ms += st.total_ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    pick = g->cfg;
+                }
             }
-            if (ms < best_ms) {
-                best_ms = ms;
-                pick = g->cfg;
-            }
-        }
     g->cfg = pick;
     if (best) *best = pick;
     return SABA_OK;

@@ -56,6 +56,7 @@ struct Flags {
     unsigned long long walk_steps;
     unsigned long long push_visits;
     unsigned long long walks;
+    unsigned long long wq[8];  // work-queue counters of the walk-pair launch, one per XCD range
 };
 
 // Device arrays a batch reads and writes, per instance edge unless noted.

@@ -95,7 +95,8 @@ def test_server_structs_match_the_c_compiler(tmp_path):
         "saba_batch_options": (b.BatchOptions, ["mem_budget", "batch_sources", "time_kernels"]),
         "saba_lambda_params": (b.LambdaParams, ["graph", "max_iters", "tol", "seed"]),
         "saba_exec_config": (b.ExecConfig, ["walks_per_lane", "walk_blocks", "est_walk_blocks",
-                                            "est_push_blocks", "walk_chunks"]),
+                                            "est_push_blocks", "walk_chunks",
+                                            "est_walk_queue", "reserved"]),
         "saba_lambda_result": (b.LambdaResult, ["lambda_bound", "residual", "iterations",
                                                 "converged"]),
         "saba_count_source": (b.CountSource, [f for f, _ in b.CountSource._fields_]),

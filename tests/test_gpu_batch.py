@@ -126,27 +126,60 @@ def test_batch_errors(saba, graphs):
 
 
 def test_256_graph_batch_full_size_sampled_edges_match_oracle(saba, orc):
-    """The batched benchmark's workload at full size (256 graphs, 26 million vertices, 32 query
-    edges each, tau capped at 128) in its launch configuration: one saba_aesc_batch call with
-    the grids autotuned on every 16th request.  Requests of several graphs of each kind equal the
-    same request run alone, and 8 edges of the median-size graph of each kind match the oracle
-    (Alg. 1 on that graph, those edges only)."""
+    """The batched benchmark's workload at full size (256 graphs, 26 million vertices, a seeded
+    1% of every graph's edges as its query, tau capped at 128, the grids' lambda from the
+    device) in its launch configuration: one saba_aesc_batch call with the knobs autotuned on
+    every 16th request.  Requests of several graphs of each kind equal the same request run
+    alone, and 8 edges of the median-size graph of each kind match the oracle (Alg. 1 on that
+    graph, those edges only)."""
     import torch
     import bench
     print("256-graph batch at full size: building the graphs", flush=True)
-    graphs, lams, epss, qnp = bench.batch_workload(256, 32)
+    graphs, lams0, epss, qnp = bench.batch_workload(256, 0.01)
     mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    print("256-graph batch: lambda of the grids on the device", flush=True)
+    lams = bench.device_lambdas(saba, mg, lams0)
+    assert all(0.0 < l < 1.0 for l in lams)
     reqs = [{"graph": k, "eps": epss[k], "lam": lams[k], "seed": 1,
              "edges": torch.from_numpy(qnp[k]).cuda(), "tau_cap": 128} for k in range(len(graphs))]
-    saba.autotune_aesc(mg, reqs[::16])
+    print("256-graph batch: autotuning on the benchmark's sample", flush=True)
+    saba.autotune_aesc(mg, bench.tuning_sample(reqs))
+    print(f"256-graph batch: one batched call over {sum(len(q) for q in qnp)} query edges",
+          flush=True)
     outs, _ = saba.aesc_batch(mg, reqs)
+    print("256-graph batch: requests alone", flush=True)
     for k in (0, 1, 2, 127, 128, 129, 253, 254, 255):
         alone = _alone(saba, graphs[k], lams[k], epss[k], 1, edges=qnp[k], tau_cap=128)
         assert np.array_equal(outs[k].cpu().numpy(), alone), k
-    sel = list(range(0, 32, 4))
     for kind in range(3):
         ks = [k for k in range(len(graphs)) if k % 3 == kind]
         k = sorted(ks, key=lambda j: graphs[j].n)[len(ks) // 2]
+        sel = np.linspace(0, len(qnp[k]) - 1, 8).astype(int)
         print(f"256-graph batch, oracle check: graph {k} kind {kind} n={graphs[k].n} eps={epss[k]}", flush=True)
         so, _ = orc.aesc(graphs[k], epss[k], lams[k], 1, query=qnp[k][sel], tau_cap=128)
         np.testing.assert_allclose(outs[k].cpu().numpy()[sel], so, rtol=1e-12, atol=1e-15)
+
+
+def test_small_grid_certified_only_with_enough_tau(saba):
+    """A small graph of the batched workload's grid generator (5 x 5 grid with 5% random
+    diagonals, not bipartite): at tau <= 128 the truncation bound exceeds eps / 2, so the
+    benchmark reports such requests as uncertified; with the cap raised above the largest
+    CalculateTau the estimates meet eps against exact SC."""
+    import bench
+    from oracle import exact_sc
+    g = graphgen.largest_component(graphgen.grid_diagonals(5, 5, 0.05, 1))
+    assert not graphgen.is_bipartite(g)
+    lam = graphgen.spectral_lambda(g)
+    ce = graphgen.canonical_edges(g)
+    eps = 0.3
+    bound, ok = bench.truncation_bound(g, ce, lam, eps, 128)
+    assert not ok and bound > eps / 2
+    bound, ok = bench.truncation_bound(g, ce, lam, eps, 1 << 20)
+    assert ok and bound <= eps / 2
+    sg = saba.SabaGraph.from_graph(g)
+    sc, st = saba.aesc(sg, eps, lam, 3, tau_cap=1 << 20)
+    assert not (st["warnings"] & 1)
+    ex = exact_sc.sc_pinv(g.row_ptr, g.col_idx, g.n)
+    err = np.abs(sc.cpu().numpy() - ex)
+    print(f"grid 5x5: lambda {lam:.5f} max tau {st['max_tau']} max error {err.max():.4f}", flush=True)
+    assert err.max() <= eps

@@ -54,10 +54,14 @@ def test_estimator_knobs_do_not_change_results(saba):
     lam = graphgen.spectral_lambda(g)
     sg = saba.SabaGraph.from_graph(g)
     ref, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
-    for wb, pb in ((1, 1), (3, 17), (512, 4096), (8192, 64)):
-        saba.set_config(sg, est_walk_blocks=wb, est_push_blocks=pb)
-        sc, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
-        assert torch.equal(sc, ref), (wb, pb)
+    for wq in (0, 1):
+        for wb, pb in ((1, 1), (3, 17), (512, 4096), (8192, 64)):
+            saba.set_config(sg, est_walk_blocks=wb, est_push_blocks=pb, est_walk_queue=wq)
+            sc, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
+            assert torch.equal(sc, ref), (wq, wb, pb)
+            # the queue counters are cleared per launch: a second call gives the same
+            sc, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64, batch_sources=333)
+            assert torch.equal(sc, ref), (wq, wb, pb, "batched")
 
 
 def test_estimator_autotuner(saba):
@@ -73,6 +77,7 @@ def test_estimator_autotuner(saba):
     best = saba.autotune_aesc(mg, reqs)
     assert best["est_walk_blocks"] in (512, 1024, 2048, 4096)
     assert best["est_push_blocks"] in (1024, 2048, 4096, 8192)
+    assert best["est_walk_queue"] in (0, 1)
     assert saba.get_config(mg) == best
     out, _ = saba.aesc_batch(mg, reqs)
     for a, b in zip(out, ref):
@@ -105,7 +110,7 @@ def test_results_do_not_depend_on_the_stream(saba):
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
     for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20},
-               {"walk_chunks": 65}, {"walk_chunks": -1}):
+               {"walk_chunks": 65}, {"walk_chunks": -1}, {"est_walk_queue": 2}):
         with pytest.raises(saba.SabaError) as ei:
             saba.set_config(sg, **kw)
         assert ei.value.name == "SABA_E_INVALID"
