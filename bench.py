@@ -224,13 +224,16 @@ def bench_walks(args, saba, torch, np):
 
 def side_walks(args, saba, torch, np, sg, src, L, seed, ep, vi):
     """The walk benchmark's other arrangements on the same starts: naive generation (one lane per
-    walk in list order, atomic counters) and the paper's grouped bouquets (G = 64, S = 20:
-    walks of a group share their path until their choices split, so a wavefront's reads
-    coalesce; the walks are then correlated within a group).  Same histograms as G = 1 only
-    for naive; G = 64 draws other walks."""
+    walk in list order, CSR reads, atomic counters), the same list order on the bouquet kernel's
+    data path (walk entries, visit log: the walk order alone differs from the headline), and
+    the paper's grouped bouquets (G = 64, S = 20: walks of a group share their path until their
+    choices split, so a wavefront's reads coalesce; the walks are then correlated within a
+    group).  Both naive orders give the headline's histograms; G = 64 draws other walks."""
     W = int(src.numel())
     rows = []
     for name, mode, G, S, reps in (("naive G=1", saba.SABA_WALK_NAIVE, 1, 0, 3),
+                                   ("naive order on walk entries + log G=1",
+                                    saba.SABA_WALK_NAIVE_LOG, 1, 0, 5),
                                    ("bouquet G=64 S=20", saba.SABA_WALK_BOUQUET, 64, 20, 10)):
         saba.walks(sg, src, L, seed, group=G, spread=S, mode=mode, endpoint=ep, visits=vi)
         torch.cuda.synchronize()
@@ -265,11 +268,13 @@ def bench_ablation(args, saba, torch, np):
     W, L = 1 << args.walks_log2, args.length
     src = torch.from_numpy(graphgen.uniform_sources(g, W, 1)).cuda()
     few = torch.from_numpy(np.repeat(graphgen.uniform_sources(g, 4096, 2), 256)).cuda()
-    NV, BQ = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET
+    NV, BQ, NL = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET, saba.SABA_WALK_NAIVE_LOG
     rows_def = [
         ("naive, Eq. (3) per-walk stream, modulo", NV, 2, 1, 0),
         ("naive, Eq. (4) keyed hash, modulo", NV, 1, 1, 0),
         ("naive, Eq. (5) keyed hash, scaled", NV, 0, 1, 0),
+        ("naive order on walk entries + log, Eq. (4) keyed hash, modulo", NL, 1, 1, 0),
+        ("naive order on walk entries + log, Eq. (5) keyed hash, scaled", NL, 0, 1, 0),
         ("bouquet, Eq. (4) keyed hash, modulo", BQ, 1, 1, 0),
         ("bouquet, Eq. (5) keyed hash, scaled (headline)", BQ, 0, 1, 0),
         ("bouquet, Eq. (5) keyed, SABA groups G=64 S=20", BQ, 0, 64, 20),
@@ -296,7 +301,7 @@ def bench_ablation(args, saba, torch, np):
         assert int(vi.sum().item()) == W * L
         h = saba.walks(sg, few, 15, 1, group=G, spread=S, mode=mode, sampler=sampler,
                        distinct=True).distinct.cpu().numpy()
-        rows.append({"name": name, "mode": "naive" if mode == NV else "bouquet",
+        rows.append({"name": name, "mode": {NV: "naive", BQ: "bouquet", NL: "naive_log"}[mode],
                      "sampler": sampler, "group": G, "spread": S, "ms_per_step": dt * 1e3,
                      "walk_steps_per_s": W * L / dt,
                      "distinct_mean": float((h * np.arange(9)).sum() / max(1, h.sum())),
@@ -323,8 +328,11 @@ def bench_walks_paper(args, saba, torch, np):
     pool = torch.from_numpy(np.flatnonzero(np.diff(g.row_ptr) > 0).astype(np.int32)).cuda()
     ep = torch.empty(g.n, dtype=torch.int64, device="cuda")
     vi = torch.empty(g.n, dtype=torch.int64, device="cuda")
-    NV, BQ = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET
-    arrangements = [("naive", NV, 1, 0), ("bouquet G=1", BQ, 1, 0),
+    NV, BQ, NL = saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET, saba.SABA_WALK_NAIVE_LOG
+    # naive-log: the naive order on the bouquet kernel's data path (walk entries, visit log),
+    # so that bouquet G=1 against it is the walk order alone
+    arrangements = [("naive", NV, 1, 0), ("naive order, walk entries + log", NL, 1, 0),
+                    ("bouquet G=1", BQ, 1, 0),
                     ("bouquet G=64 S=20", BQ, 64, 20), ("bouquet G=64 S=12", BQ, 64, 12)]
     rows = []
     for per_vertex, L in ((args.paper_walks, 15), (args.paper_walks, 5)):
@@ -348,6 +356,9 @@ def bench_walks_paper(args, saba, torch, np):
     for r in rows:
         base = next(x for x in rows if x["steps"] == r["steps"] and x["arrangement"] == "naive")
         r["speedup_vs_naive"] = base["seconds"] / r["seconds"]
+        nl = next(x for x in rows if x["steps"] == r["steps"]
+                  and x["arrangement"] == "naive order, walk entries + log")
+        r["speedup_vs_naive_order_same_data_path"] = nl["seconds"] / r["seconds"]
     return {"workload": f"rmat{args.scale}_ef16_every_vertex_x{args.paper_walks}_walks",
             "starts": int(pool.numel()), "rows": rows}
 

@@ -55,6 +55,9 @@ extern "C" {
 /* walk execution modes (results are identical in both) */
 #define SABA_WALK_NAIVE 0   /* one lane per walk, walks in the order the sources are given */
 #define SABA_WALK_BOUQUET 1 /* walks of one start vertex run side by side in a wavefront */
+#define SABA_WALK_NAIVE_LOG 2 /* the order of SABA_WALK_NAIVE on the bouquet kernel's data path
+                                 (16-byte walk entries, counting through the visit log): the
+                                 walk-order ablation */
 
 /* neighbour-choice functions of the walk benchmark (the paper's comparison, Sec. 3.3).  The
  * estimator always uses SABA_SAMPLER_KEYED. */
@@ -109,7 +112,7 @@ typedef struct {
     uint32_t seed;           /* walk seed */
     uint32_t group;          /* G >= 1: walks per key group (1 = independent walks) */
     uint32_t spread;         /* S: bit offset of the lane index inside key_lo; G << S <= 2^32 */
-    int32_t mode;            /* SABA_WALK_NAIVE or SABA_WALK_BOUQUET */
+    int32_t mode;            /* SABA_WALK_NAIVE, SABA_WALK_BOUQUET or SABA_WALK_NAIVE_LOG */
     int32_t time_kernels;    /* nonzero: fill saba_stats kernel_ms / total_ms (synchronises) */
     const int32_t *d_sources; /* [n_walks] start vertex of each walk (device); read only with
                                 SABA_SOURCES_EXPLICIT */
@@ -117,8 +120,8 @@ typedef struct {
     int32_t source_mode;     /* SABA_SOURCES_EXPLICIT (0) or SABA_SOURCES_UNIFORM */
     int64_t *d_distinct;     /* NULL, or [9] int64 (device): branching statistics (the Table 5
                                 experiment).  The walks are cut into consecutive vectors of 8
-                                in the order the mode runs them (naive: the order of
-                                d_sources; bouquet: by start vertex, then rank), a last partial
+                                in the order the mode runs them (naive and naive-log: the order
+                                of d_sources; bouquet: by start vertex, then rank), a last partial
                                 vector left out; d_distinct[k] receives the number of (vector,
                                 position l = 1..L) pairs with k distinct vertices.  Slower
                                 kernels are used while it is set; results are unchanged. */
@@ -413,7 +416,7 @@ int saba_graph_info(const saba_graph *g, saba_graph_info_t *out);
  *   Errors (SABA_E_INVALID; the outputs are then unspecified and the handle stays usable):
  *   a start outside 0 .. n-1 or on an isolated vertex, anywhere in the list; n_walks < 0,
  *   L < 0, G = 0, S > 31 or (G - 1) << S beyond 32 bits; an unknown mode, sampler or source
- *   mode; a null output or source array; n_walks >= 2^31 in naive order.  SABA_E_OVERFLOW:
+ *   mode; a null output or source array; n_walks >= 2^31 in either naive order.  SABA_E_OVERFLOW:
  *   n_walks * max(L, 1) >= 2^62, or n_walks >= 2^32 (a walk key holds a 32-bit index, so
  *   more walks from one start would repeat earlier ones).
  */

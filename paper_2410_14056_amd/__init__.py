@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     SABA_SOURCES_UNIFORM,
     SABA_WALK_BOUQUET,
     SABA_WALK_NAIVE,
+    SABA_WALK_NAIVE_LOG,
     SabaError,
     SabaGraph,
     SabaServer,

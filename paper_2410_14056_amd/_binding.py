@@ -20,6 +20,7 @@ SABA_DEVICE_PTRS = 1
 SABA_TRUSTED = 2
 SABA_WALK_NAIVE = 0
 SABA_WALK_BOUQUET = 1
+SABA_WALK_NAIVE_LOG = 2
 SABA_SAMPLER_KEYED = 0
 SABA_SAMPLER_KEYED_MOD = 1
 SABA_SAMPLER_STREAM_MOD = 2

@@ -89,7 +89,7 @@ struct Graph {
     // random sector instead of two (the vertex record, then the adjacency entry).
     int4 *nbr = nullptr;
     // reusable scratch of the synchronous calls
-    DevBuf walk_scratch[8];
+    DevBuf walk_scratch[12];
     // the walk call's second stream and its buffer hand-over events (walks done x2, counting
     // done x2), created on first use
     hipStream_t walk_aux = nullptr;

@@ -293,10 +293,35 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_atomic_kernel(
 // 16-byte walk entries (one random read per step).  Walk w0 + i writes its position l to
 // vlog[(l - 1) * wc + i] and its end vertex to elog[i]; the block counts its visits and ends
 // per vertex bucket and writes the counts bucket-major: cnt[b * gridDim.x + blockIdx.x].
-template <int SM, bool CNT, int WPL>
+//
+// kList (the walk-order ablation): the walks are taken in list order instead, walk w starting
+// at lsrc[w] with rank lrank[w] among the walks of its start; a walk whose start is out of
+// range or isolated (the call then fails) writes -1 everywhere, which the counting drops.
+template <bool kList>
+__device__ __forceinline__ bool log_walk_start(const int2 *__restrict__ vrec,
+                                               const int32_t *__restrict__ bsrc,
+                                               const int64_t *__restrict__ offs,
+                                               const int32_t *__restrict__ lsrc,
+                                               const uint32_t *__restrict__ lrank, int32_t n,
+                                               int64_t w, int32_t *s, uint64_t *r) {
+    if (kList) {
+        const int32_t v = lsrc[w];
+        if (v < 0 || v >= n || vrec[v].y == 0) return false;
+        *s = v;
+        *r = lrank[w];
+        return true;
+    }
+    *s = bsrc[w];
+    *r = (uint64_t)(w - offs[*s]);
+    return true;
+}
+
+template <int SM, bool CNT, int WPL, bool kList>
 __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
     const int2 *__restrict__ vrec, const int4 *__restrict__ nbr,
-    const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs, int32_t n, int64_t w0,
+    const int32_t *__restrict__ bsrc, const int64_t *__restrict__ offs,
+    const int32_t *__restrict__ lsrc, const uint32_t *__restrict__ lrank, int64_t nlist,
+    int32_t n, int64_t w0,
     int64_t wc, int32_t L, uint32_t seed, uint32_t G, uint32_t S, int bsh, int32_t nbk,
     int32_t *__restrict__ vlog, int32_t *__restrict__ elog, long long *__restrict__ cnt_v,
     long long *__restrict__ cnt_e, unsigned long long *__restrict__ distinct) {
@@ -306,7 +331,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
     for (int i = threadIdx.x; i < 2 * nbk; i += kWalkBlock) lds_cnt[i] = 0;
     if (CNT && threadIdx.x < 9) lhist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t valid = min(wc, offs[n] - w0);
+    const int64_t valid = min(wc, (kList ? nlist : offs[n]) - w0);
     // The block runs the 256-walk tiles blockIdx.x, blockIdx.x + gridDim.x, ... (the tiles the
     // scatter pass assigns to it); with WPL walks per lane it takes WPL of its tiles at a time
     // and steps their walks side by side, so WPL independent reads are in flight per lane.
@@ -315,20 +340,26 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
         const int64_t i = tile * kWalkBlock + threadIdx.x;
         if (!CNT) {
             int64_t ii[WPL];
-            bool act[WPL];
+            bool act[WPL], bad[WPL];
             Walker wk[WPL];
             WalkPos p[WPL];
 #pragma unroll
             for (int k = 0; k < WPL; ++k) {
                 ii[k] = (tile + (int64_t)k * gridDim.x) * kWalkBlock + threadIdx.x;
                 act[k] = ii[k] < valid;
+                bad[k] = false;
                 p[k] = WalkPos{0, 0, 0};
                 if (act[k]) {
-                    const int64_t w = w0 + ii[k];
-                    const int32_t s = bsrc[w];
-                    wk[k] = walker_init<SM>(
-                        walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
-                    p[k] = walk_pos(vrec, s);
+                    int32_t s = 0;
+                    uint64_t r = 0;
+                    if (log_walk_start<kList>(vrec, bsrc, offs, lsrc, lrank, n, w0 + ii[k], &s,
+                                              &r)) {
+                        wk[k] = walker_init<SM>(walk_key(seed, (uint32_t)s, 0u, 0u, r, G, S));
+                        p[k] = walk_pos(vrec, s);
+                    } else {
+                        act[k] = false;
+                        bad[k] = true;
+                    }
                 }
             }
             for (int32_t l = 1; l <= L; ++l) {
@@ -341,6 +372,8 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
                     if (act[k]) {
                         __builtin_nontemporal_store(p[k].v, vlog + (int64_t)(l - 1) * wc + ii[k]);
                         atomicAdd(cv + (p[k].v >> bsh), 1u);
+                    } else if (kList && bad[k]) {
+                        vlog[(int64_t)(l - 1) * wc + ii[k]] = -1;
                     }
             }
 #pragma unroll
@@ -348,31 +381,40 @@ __global__ __launch_bounds__(kWalkBlock) void walk_bouquet_log_kernel(
                 if (act[k]) {
                     __builtin_nontemporal_store(p[k].v, elog + ii[k]);
                     atomicAdd(ce + (p[k].v >> bsh), 1u);
+                } else if (kList && bad[k]) {
+                    elog[ii[k]] = -1;
                 }
         } else {
             // every lane steps (idle ones in place) so the 8-lane groups stay converged
-            const bool act = i < valid;
+            bool act = i < valid;
+            const bool in = act;
             const bool full = (i & ~7ll) + 8 <= valid;
             Walker wk{};
             WalkPos p{0, 0, 0};
             if (act) {
-                const int64_t w = w0 + i;
-                const int32_t s = bsrc[w];
-                wk = walker_init<SM>(
-                    walk_key(seed, (uint32_t)s, 0u, 0u, (uint64_t)(w - offs[s]), G, S));
-                p = walk_pos(vrec, s);
+                int32_t s = 0;
+                uint64_t r = 0;
+                act = log_walk_start<kList>(vrec, bsrc, offs, lsrc, lrank, n, w0 + i, &s, &r);
+                if (act) {
+                    wk = walker_init<SM>(walk_key(seed, (uint32_t)s, 0u, 0u, r, G, S));
+                    p = walk_pos(vrec, s);
+                }
             }
             for (int32_t l = 1; l <= L; ++l) {
                 if (act) {
                     p = walker_step_nbr<SM>(nbr, p, (uint32_t)p.v, (uint32_t)l, wk);
                     vlog[(int64_t)(l - 1) * wc + i] = p.v;
                     atomicAdd(cv + (p.v >> bsh), 1u);
+                } else if (kList && in) {
+                    vlog[(int64_t)(l - 1) * wc + i] = -1;
                 }
                 distinct8_count(p.v, full, lhist);
             }
             if (act) {
                 elog[i] = p.v;
                 atomicAdd(ce + (p.v >> bsh), 1u);
+            } else if (kList && in) {
+                elog[i] = -1;
             }
         }
     }
@@ -660,16 +702,16 @@ static void launch_atomic_sm(bool cnt, unsigned blocks, hipStream_t s, const Gra
             vi, dist);
 }
 
-template <int SM>
-static void launch_log_sm(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s,
-                          const Graph *g, const saba_walk_params *p, const int32_t *bsrc,
-                          const int64_t *offs, int64_t w0, int64_t wc, int bsh, int32_t nbk,
-                          int32_t *vlog, int32_t *elog, long long *cnt_v, long long *cnt_e,
-                          unsigned long long *dist) {
+template <int SM, bool LIST>
+static void launch_log_sm2(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s,
+                           const Graph *g, const saba_walk_params *p, const int32_t *bsrc,
+                           const int64_t *offs, const uint32_t *lrank, int64_t w0, int64_t wc,
+                           int bsh, int32_t nbk, int32_t *vlog, int32_t *elog, long long *cnt_v,
+                           long long *cnt_e, unsigned long long *dist) {
 #define SABA_LOG_LAUNCH(C, W)                                                                   \
-    walk_bouquet_log_kernel<SM, C, W><<<nblk, kWalkBlock, lds, s>>>(                             \
-        g->vrec, g->nbr, bsrc, offs, g->n, w0, wc, p->length, p->seed, p->group, p->spread, bsh, \
-        nbk, vlog, elog, cnt_v, cnt_e, dist)
+    walk_bouquet_log_kernel<SM, C, W, LIST><<<nblk, kWalkBlock, lds, s>>>(                       \
+        g->vrec, g->nbr, bsrc, offs, p->d_sources, lrank, p->n_walks, g->n, w0, wc, p->length,  \
+        p->seed, p->group, p->spread, bsh, nbk, vlog, elog, cnt_v, cnt_e, dist)
     if (cnt)
         SABA_LOG_LAUNCH(true, 1);
     else if (wpl >= 4)
@@ -679,6 +721,21 @@ static void launch_log_sm(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s
     else
         SABA_LOG_LAUNCH(false, 1);
 #undef SABA_LOG_LAUNCH
+}
+
+// lrank != null: the walks in list order (the naive-log ablation)
+template <int SM>
+static void launch_log_sm(bool cnt, int wpl, int nblk, size_t lds, hipStream_t s,
+                          const Graph *g, const saba_walk_params *p, const int32_t *bsrc,
+                          const int64_t *offs, const uint32_t *lrank, int64_t w0, int64_t wc,
+                          int bsh, int32_t nbk, int32_t *vlog, int32_t *elog, long long *cnt_v,
+                          long long *cnt_e, unsigned long long *dist) {
+    if (lrank)
+        launch_log_sm2<SM, true>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, lrank, w0, wc, bsh, nbk,
+                                 vlog, elog, cnt_v, cnt_e, dist);
+    else
+        launch_log_sm2<SM, false>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, lrank, w0, wc, bsh,
+                                  nbk, vlog, elog, cnt_v, cnt_e, dist);
 }
 
 // Uniform sources: walk j starts at pool[floor(h_j npool / 2^32)] with
@@ -808,9 +865,10 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         (p->source_mode != SABA_SOURCES_EXPLICIT && p->source_mode != SABA_SOURCES_UNIFORM) ||
         (W > 0 && p->source_mode == SABA_SOURCES_EXPLICIT && !p->d_sources) || !d_endpoint ||
         !d_visits ||
-        (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET) || p->sampler < 0 ||
+        (p->mode != SABA_WALK_NAIVE && p->mode != SABA_WALK_BOUQUET &&
+         p->mode != SABA_WALK_NAIVE_LOG) || p->sampler < 0 ||
         p->sampler > SABA_SAMPLER_LITERAL ||
-        (p->mode == SABA_WALK_NAIVE && W >= ((int64_t)1 << 31))) {
+        (p->mode != SABA_WALK_BOUQUET && W >= ((int64_t)1 << 31))) {
         set_error("invalid walk parameters");
         return SABA_E_INVALID;
     }
@@ -937,6 +995,11 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         int bsh = 12;
         while (bsh < kMaxBucketShift && (((int64_t)n + (1 << bsh) - 1) >> bsh) > kMaxBuckets) ++bsh;
         const int32_t nbk = (int32_t)(((int64_t)n + (1 << bsh) - 1) >> bsh);
+        const bool list = p->mode == SABA_WALK_NAIVE_LOG;
+        if (list && nbk > kMaxBuckets) {
+            set_error("the naive-log order needs at most 2^25 vertices (the bucketed count)");
+            return SABA_E_INVALID;
+        }
         if (nbk > kMaxBuckets) {
             source_count_kernel<<<cblocks, kWalkBlock, 0, s>>>(p->d_sources, W, g->vrec, n, counts,
                                                                 err);
@@ -1031,6 +1094,29 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                                  kWalkBlock, 0, s>>>(g->vrec, n, counts, err);
             SABA_HIP_TRY(hipGetLastError());
             SABA_TRY(order_walks());
+            // naive-log order: the rank of each walk among the walks of its start, in list
+            // order (a stable sort of the list by start, then the position within the start)
+            uint32_t *lrank = nullptr;
+            if (list) {
+                int32_t *sorted_src = nullptr;
+                uint32_t *iota = nullptr;
+                void *sort_tmp = nullptr;
+                SABA_TRY(ar.get(8, sizeof(int32_t) * (size_t)W, &sorted_src));
+                SABA_TRY(ar.get(9, sizeof(uint32_t) * 2 * (size_t)W, &iota));
+                SABA_TRY(ar.get(10, sizeof(uint32_t) * (size_t)W, &lrank));
+                size_t sort_bytes = 0;
+                SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, p->d_sources,
+                                                                sorted_src, iota, iota + W, (int)W,
+                                                                0, 32, s));
+                SABA_TRY(ar.get(11, std::max<size_t>(sort_bytes, 1), &sort_tmp));
+                iota_kernel<<<cblocks, kWalkBlock, 0, s>>>(iota, W);
+                SABA_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, p->d_sources,
+                                                                sorted_src, iota, iota + W, (int)W,
+                                                                0, 32, s));
+                list_rank_kernel<<<cblocks, kWalkBlock, 0, s>>>(sorted_src, iota + W, W, offs,
+                                                                 g->vrec, n, lrank);
+                SABA_HIP_TRY(hipGetLastError());
+            }
             hipStream_t sc = s;  // the counting stream
             if (overlap) {
                 SABA_TRY(ensure_walk_pipeline(g));
@@ -1053,21 +1139,21 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                 const size_t lds = sizeof(uint32_t) * 2 * nbk;
                 switch (sm) {
                     case SABA_SAMPLER_KEYED:
-                        launch_log_sm<SABA_SAMPLER_KEYED>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, w0,
+                        launch_log_sm<SABA_SAMPLER_KEYED>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, lrank, w0,
                                                           this_wc, bsh, nbk, vl, el, cv, ce, dist);
                         break;
                     case SABA_SAMPLER_KEYED_MOD:
-                        launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
+                        launch_log_sm<SABA_SAMPLER_KEYED_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, lrank,
                                                               w0, this_wc, bsh, nbk, vl, el, cv, ce,
                                                               dist);
                         break;
                     case SABA_SAMPLER_STREAM_MOD:
                         launch_log_sm<SABA_SAMPLER_STREAM_MOD>(cnt, wpl, nblk, lds, s, g, p, bsrc,
-                                                               offs, w0, this_wc, bsh, nbk, vl, el,
+                                                               offs, lrank, w0, this_wc, bsh, nbk, vl, el,
                                                                cv, ce, dist);
                         break;
                     default:
-                        launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs,
+                        launch_log_sm<SABA_SAMPLER_LITERAL>(cnt, wpl, nblk, lds, s, g, p, bsrc, offs, lrank,
                                                             w0, this_wc, bsh, nbk, vl, el, cv, ce,
                                                             dist);
                 }

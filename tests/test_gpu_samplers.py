@@ -44,13 +44,13 @@ def test_sampler_histograms_and_branching_match_oracle(saba, orc, gname, sampler
     d_bq = orc.distinct8(g, few, L, seed, G=G, S=S, sampler=sampler, order=1)
     t = torch.from_numpy(np.ascontiguousarray(src, dtype=np.int32)).cuda()
     tf = torch.from_numpy(np.ascontiguousarray(few, dtype=np.int32)).cuda()
-    for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+    for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET, saba.SABA_WALK_NAIVE_LOG):
         for distinct in (False, True):
             r = saba.walks(sg, t, L, seed, group=G, spread=S, mode=mode, sampler=sampler,
                            distinct=distinct)
             assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), (mode, distinct)
             assert np.array_equal(r.visits.cpu().numpy(), vi_o), (mode, distinct)
-            if distinct and mode == saba.SABA_WALK_NAIVE:
+            if distinct and mode != saba.SABA_WALK_BOUQUET:  # both naive orders: list order
                 assert np.array_equal(r.distinct.cpu().numpy(), d_naive)
     r = saba.walks(sg, tf, L, seed, group=G, spread=S, mode=saba.SABA_WALK_BOUQUET,
                    sampler=sampler, distinct=True)

@@ -18,6 +18,11 @@ def saba():
     return saba
 
 
+def _modes(saba):
+    """Naive order, bouquet order, and naive order on the bouquet kernel's data path."""
+    return (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET, saba.SABA_WALK_NAIVE_LOG)
+
+
 def _run(saba, sg, src, L, seed, G, S, mode):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(src, dtype=np.int32)).cuda()
@@ -41,7 +46,7 @@ def test_walks_match_oracle(saba, orc, gname, L, G, S):
     sg = saba.SabaGraph.from_graph(g)
     src = graphgen.uniform_sources(g, 12345, 5)  # ragged: not a multiple of the block
     ep_o, vi_o = orc.walks_histogram(g, src, L, seed=77, G=G, S=S)
-    for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+    for mode in _modes(saba):
         ep, vi = _run(saba, sg, src, L, 77, G, S, mode)
         assert np.array_equal(ep, ep_o), mode
         assert np.array_equal(vi, vi_o), mode
@@ -57,7 +62,7 @@ def test_uniform_sources_on_the_device_match_oracle(saba, orc, gname, G, S):
     W, L, seed = 100003, 9, 21
     print(f"uniform sources graph={gname} W={W} G={G}", flush=True)
     ep_o, vi_o = orc.walks_histogram(g, orc.uniform_sources(g, W, seed), L, seed=seed, G=G, S=S)
-    for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+    for mode in _modes(saba):
         r = saba.walks(sg, None, L, seed, group=G, spread=S, mode=mode, n_walks=W)
         assert np.array_equal(r.endpoint.cpu().numpy(), ep_o), mode
         assert np.array_equal(r.visits.cpu().numpy(), vi_o), mode
@@ -92,7 +97,7 @@ def test_walks_empty_and_invalid(saba):
     r = saba.walks(sg, torch.zeros(0, dtype=torch.int32, device="cuda"), 5, 1)
     assert r.endpoint.sum().item() == 0 and r.visits.sum().item() == 0
     for bad in ([3], [4], [-1]):
-        for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+        for mode in _modes(saba):
             with pytest.raises(saba.SabaError) as ei:
                 saba.walks(sg, torch.tensor(bad, dtype=torch.int32, device="cuda"), 5, 1, mode=mode)
             assert ei.value.name == "SABA_E_INVALID"
@@ -138,11 +143,13 @@ def test_rmat20_full_size(saba, orc, rmat20):
     threads = min(16, os.cpu_count() or 1)
     res = {}
     for G, S in ((1, 0), (64, 20)):
-        for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+        for mode in _modes(saba):
             r = saba.walks(sg, src, L, 1, group=G, spread=S, mode=mode)
             res[(G, mode)] = (r.endpoint.cpu().numpy(), r.visits.cpu().numpy())
         a, b = res[(G, saba.SABA_WALK_NAIVE)], res[(G, saba.SABA_WALK_BOUQUET)]
+        c = res[(G, saba.SABA_WALK_NAIVE_LOG)]
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(c[0], b[0]) and np.array_equal(c[1], b[1])
         assert a[0].sum() == W and a[1].sum() == W * L
         deg = np.diff(g.row_ptr)
         assert np.all(a[1][deg == 0] == 0)
@@ -170,7 +177,7 @@ def test_skewed_starts_match_oracle(saba, orc):
     for L in (7, 64):
         print(f"skewed starts L={L} W={src.size}", flush=True)
         ep_o, vi_o = orc.walks_histogram(g, src, L, seed=5)
-        for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+        for mode in _modes(saba):
             ep, vi = _run(saba, sg, src, L, 5, 1, 0, mode)
             assert np.array_equal(ep, ep_o), (L, mode)
             assert np.array_equal(vi, vi_o), (L, mode)
@@ -190,7 +197,7 @@ def test_invalid_start_in_long_list(saba, orc):
             src = good.copy()
             src[at] = bad
             t = torch.from_numpy(src).cuda()
-            for mode in (saba.SABA_WALK_NAIVE, saba.SABA_WALK_BOUQUET):
+            for mode in _modes(saba):
                 with pytest.raises(saba.SabaError) as ei:
                     saba.walks(sg, t, 9, 2, mode=mode)
                 assert ei.value.name == "SABA_E_INVALID", (bad, at, mode)
