@@ -167,8 +167,7 @@ def bench_walks(args, saba, torch, np):
     probe = saba.probe_random_reads(26, 256) if mode == saba.SABA_WALK_BOUQUET else None
     k_ms = float(np.mean(kms))
     call_ms = float(np.mean(tms))
-    log_cap = 1 << 29  # visit-log entries per chunk (library constant)
-    chunks = -(-W * L // log_cap) if mode == saba.SABA_WALK_BOUQUET else 1
+    chunks = int(r.stats["batches"])  # walk-kernel launches per call (visit-log chunks)
     per_launch_steps = W * L // chunks
     bouquet = mode == saba.SABA_WALK_BOUQUET
     kbytes = WALK_KERNEL_BYTES_PER_STEP if bouquet else WALK_STEP_BYTES

@@ -96,7 +96,8 @@ typedef struct {
     int64_t walk_steps;       /* steps taken by those walks */
     int64_t push_edge_visits; /* adjacency entries read by the estimator's deterministic levels */
     int64_t sources;          /* sources processed by the estimator */
-    int64_t batches;          /* source batches */
+    int64_t batches;          /* source batches (estimator); walk-kernel launches, one per
+                                 visit-log chunk (walk calls) */
     int32_t max_tau;          /* largest truncation length */
     int32_t max_ttau;         /* largest deterministic level count */
     int32_t warnings;         /* bit 0: some tau was capped at tau_cap */

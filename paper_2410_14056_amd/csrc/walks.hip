@@ -916,6 +916,7 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
     if (cnt) SABA_HIP_TRY(hipMemsetAsync(p->d_distinct, 0, sizeof(int64_t) * 9, s));
     const int sm = p->sampler;
     bool counted_separately = false;
+    int64_t launches = W > 0 ? 1 : 0;  // walk-kernel launches (visit-log chunks)
 
     if (W > 0 && p->mode == SABA_WALK_NAIVE) {
         // rank of each walk among the walks of its start vertex, in list order
@@ -1123,6 +1124,7 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                 sc = g->walk_aux;
             }
             const int64_t nchunks = (W + wc - 1) / wc;
+            launches = nchunks;
             EventList tev;  // per chunk: walk start / end on s, count start / end on sc
             if (timing) SABA_TRY(tev.create(4 * nchunks));
             for (int64_t k = 0; k < nchunks; ++k) {
@@ -1207,6 +1209,7 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
         *st = saba_stats{};
         st->walks = W;
         st->walk_steps = W * (int64_t)L;
+        st->batches = launches;
         if (timing) {
             float a = 0.f, b = 0.f;
             if (W > 0 && !counted_separately) SABA_HIP_TRY(hipEventElapsedTime(&a, ev.e[1], ev.e[2]));
