@@ -70,8 +70,9 @@ def kernel_source_sha(files=("saba_internal.hpp", "walks.hip")) -> str:
 
 
 def estimator_traffic(walk_steps: int, launches: int):
-    """HBM bytes per launch of the walk-pair kernel from the committed counter runs, if they
-    were taken on the current estimator source with the same query; else None."""
+    """Fabric bytes per launch of the walk-pair kernel from the committed counter runs, if they
+    were taken on the current estimator source with the same query (same walk steps); else
+    None.  The runs give bytes per walk step; a launch averages walk_steps / launches steps."""
     try:
         with open(EST_COUNTERS) as f:
             c = json.load(f)
@@ -80,14 +81,15 @@ def estimator_traffic(walk_steps: int, launches: int):
     if c.get("kernel_source_sha") != kernel_source_sha(("saba_internal.hpp", "estimator.hpp",
                                                         "aesc.hip")):
         return None
-    if c.get("walk_steps") != walk_steps or c.get("dispatches") != launches:
+    if c.get("walk_steps") != walk_steps or launches <= 0:
         return None
-    return float(c["hbm_bytes_total"]) / launches
+    return float(c["fabric_bytes_per_step"]) * walk_steps / launches
 
 
-def measured_traffic(walks: int, steps: int, chunks: int):
-    """HBM bytes per launch of the walk kernel from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source with this workload; else None."""
+def measured_traffic(walks: int, steps: int, steps_per_launch: int):
+    """Fabric bytes per launch of the walk kernel from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source with this workload; else None.  The runs give
+    bytes per walk step (one line per step whatever the chunk size)."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -95,9 +97,9 @@ def measured_traffic(walks: int, steps: int, chunks: int):
         return None
     if c.get("kernel_source_sha") != kernel_source_sha():
         return None
-    if c.get("walks") != walks or c.get("length") != steps or c.get("chunks") != chunks:
+    if c.get("walks") != walks or c.get("length") != steps:
         return None
-    return float(c["hbm_bytes_per_dispatch"])
+    return float(c["fabric_bytes_per_step"]) * steps_per_launch
 
 
 def host_threads() -> int:
@@ -193,7 +195,7 @@ def bench_walks(args, saba, torch, np):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(W, L, chunks) if bouquet else None,
+            "traffic": measured_traffic(W, L, per_launch_steps) if bouquet else None,
             "traffic_basis": TRAFFIC_BASIS,
             "kernel": "walk_bouquet_log_kernel" if bouquet else "walk_naive_kernel",
             "kernel_ms_per_launch": k_ms / chunks,
