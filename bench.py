@@ -316,9 +316,18 @@ def bench_ablation(args, saba, torch, np):
     base = rows[0]["walk_steps_per_s"]
     for r in rows:
         r["speedup_vs_first"] = r["walk_steps_per_s"] / base
+    # the grouped schedule an autotuner picks under a correlation budget (least mean distinct
+    # vertices per 8-walk vector, measured on the same workload)
+    tuned = []
+    for budget in (7.5, 6.0, 4.0, 2.0, 1.0):
+        progress(f"ablation: bouquet autotuner at budget {budget}")
+        b = saba.autotune_bouquet(sg, src, L, 1, budget)
+        tuned.append({"min_distinct": budget, "group": b["group"], "spread": b["spread"],
+                      "distinct_mean": b["distinct_mean"], "ms_per_step": b["ms"],
+                      "walk_steps_per_s": W * L / (b["ms"] * 1e-3)})
     return {"workload": f"rmat{args.scale}_ef16_walks_2^{args.walks_log2}x{L}_samplers",
             "branching_workload": f"rmat{args.scale}: 4096 uniform sources x 256 walks x 15 steps",
-            "rows": rows}
+            "rows": rows, "autotuned_schedules": tuned}
 
 
 def bench_walks_paper(args, saba, torch, np):

@@ -366,6 +366,30 @@ int saba_autotune_walks(saba_graph *g, const saba_walk_params *sample, saba_exec
                         void *stream);
 
 /*
+ * Grouped-bouquet autotuner (Sec. 3.3): among the key schedules (G, S) whose walks stay within
+ * a stated correlation budget, the fastest on the caller's walk sample (bouquet mode, its
+ * sources, length and seed).  G > 1 changes which walks are drawn (walks of a group share
+ * their path until their choices split), so, unlike the execution knobs, the schedule is
+ * returned to the caller and not kept in the handle.  The budget min_distinct is the least
+ * mean number of distinct vertices per vector of 8 consecutive walks, at every position,
+ * measured on the sample (the branching statistic of saba_walks): about 7.7 for independent
+ * walks (G = 1, which is always a candidate), 1 for walks that move together.  Candidates:
+ * G = 1, and G in {8, 64, 256} with S = 4, 8, ..., 28 and (G - 1) << S < 2^32.  Each is timed
+ * as a whole call (one warm-up, two timed).  *best: the schedule, its distinct mean and its
+ * time per call.  Errors: SABA_E_INVALID (NULL sample or best, budget outside [1, 8]), and
+ * those of saba_walks.  Only G = 1 carries the estimator's eps guarantee.
+ */
+typedef struct {
+    uint32_t group;
+    uint32_t spread;
+    double distinct_mean;
+    double ms;
+} saba_bouquet_choice;
+
+int saba_autotune_bouquet(saba_graph *g, const saba_walk_params *sample, double min_distinct,
+                          saba_bouquet_choice *best, void *stream);
+
+/*
  * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
  * which may be NULL) under each candidate grid (512, 1024, 2048 or 4096 blocks for the
  * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels x the

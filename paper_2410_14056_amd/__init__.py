@@ -24,6 +24,7 @@ from ._binding import (  # noqa: F401
     aesc_edge_stats,
     aesc_query,
     autotune_aesc,
+    autotune_bouquet,
     autotune_walks,
     fail_allocation,
     get_config,

@@ -160,6 +160,14 @@ class CountSource(ctypes.Structure):
                 ("hist_off", ctypes.c_int64)]
 
 
+class BouquetChoice(ctypes.Structure):
+    _fields_ = [("group", ctypes.c_uint32), ("spread", ctypes.c_uint32),
+                ("distinct_mean", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ExecConfig(ctypes.Structure):
     _fields_ = [("walks_per_lane", ctypes.c_int32), ("walk_blocks", ctypes.c_int32),
                 ("est_walk_blocks", ctypes.c_int32), ("est_push_blocks", ctypes.c_int32),
@@ -177,7 +185,8 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_server_wait", "saba_server_stats", "saba_server_destroy", "saba_graph_lambda",
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
            "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc",
-           "saba_debug_fail_allocation", "saba_aesc_counts", "saba_walks_noalloc"]
+           "saba_debug_fail_allocation", "saba_aesc_counts", "saba_walks_noalloc",
+           "saba_autotune_bouquet"]
 
 _lib = None
 
@@ -216,6 +225,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.saba_graph_get_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_graph_set_config.argtypes = [P, ctypes.POINTER(ExecConfig)]
     L.saba_autotune_walks.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.POINTER(ExecConfig), P]
+    L.saba_autotune_bouquet.argtypes = [P, ctypes.POINTER(WalkParams), ctypes.c_double,
+                                        ctypes.POINTER(BouquetChoice), P]
     L.saba_autotune_aesc.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions),
                                      ctypes.POINTER(ExecConfig), P]
     L.saba_debug_fail_allocation.argtypes = [i32]
@@ -391,6 +402,20 @@ def set_config(graph: SabaGraph, walks_per_lane: int = 0, walk_blocks: int = 0,
     c = ExecConfig(int(walks_per_lane), int(walk_blocks), int(est_walk_blocks),
                    int(est_push_blocks), int(walk_chunks), int(est_walk_queue), 0)
     _check(load().saba_graph_set_config(graph.handle, ctypes.byref(c)))
+
+
+def autotune_bouquet(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int,
+                     min_distinct: float, stream=None) -> dict:
+    """saba_autotune_bouquet: the fastest key schedule (G, S) on this sample whose walks keep at
+    least min_distinct distinct vertices per 8-walk vector on average (not kept in the handle:
+    the schedule changes which walks are drawn)."""
+    assert sources.is_cuda and sources.dtype == torch.int32 and sources.is_contiguous()
+    p = WalkParams(sources.numel(), int(length), seed & 0xFFFFFFFF, 1, 0, SABA_WALK_BOUQUET, 0,
+                   sources.data_ptr(), SABA_SAMPLER_KEYED, SABA_SOURCES_EXPLICIT, None)
+    b = BouquetChoice()
+    _check(load().saba_autotune_bouquet(graph.handle, ctypes.byref(p), float(min_distinct),
+                                        ctypes.byref(b), _stream_ptr(stream)))
+    return b.as_dict()
 
 
 def autotune_walks(graph: SabaGraph, sources: torch.Tensor, length: int, seed: int,

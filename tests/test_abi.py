@@ -100,6 +100,7 @@ def test_server_structs_match_the_c_compiler(tmp_path):
         "saba_lambda_result": (b.LambdaResult, ["lambda_bound", "residual", "iterations",
                                                 "converged"]),
         "saba_count_source": (b.CountSource, [f for f, _ in b.CountSource._fields_]),
+        "saba_bouquet_choice": (b.BouquetChoice, [f for f, _ in b.BouquetChoice._fields_]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saba.h"', "int main(void) {"]
     for cname, (_, fields) in checks.items():

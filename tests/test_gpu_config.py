@@ -114,3 +114,27 @@ def test_config_rejects_bad_values(saba):
         with pytest.raises(saba.SabaError) as ei:
             saba.set_config(sg, **kw)
         assert ei.value.name == "SABA_E_INVALID"
+
+
+def test_bouquet_autotuner_respects_the_budget(saba):
+    """saba_autotune_bouquet returns the fastest (G, S) whose 8-walk vectors keep at least the
+    budget of distinct vertices on the sample; the returned mean is the branching statistic of
+    the same walks, and the schedule is not kept in the handle."""
+    import torch
+    g = graphgen.rmat(12, 16, 0.57, 0.19, 0.19, 2)
+    sg = saba.SabaGraph.from_graph(g)
+    src = torch.from_numpy(np.repeat(graphgen.uniform_sources(g, 512, 3), 256).astype(np.int32)).cuda()
+    before = saba.get_config(sg)
+    picks = {}
+    for budget in (7.5, 4.0, 1.0):
+        b = saba.autotune_bouquet(sg, src, 12, 5, budget)
+        assert b["distinct_mean"] >= budget and b["ms"] > 0
+        r = saba.walks(sg, src, 12, 5, group=b["group"], spread=b["spread"], distinct=True)
+        h = r.distinct.cpu().numpy()
+        assert abs((h * np.arange(9)).sum() / h.sum() - b["distinct_mean"]) < 1e-12
+        picks[budget] = b
+    assert saba.get_config(sg) == before
+    # a looser budget admits every schedule a tighter one does
+    assert picks[1.0]["distinct_mean"] <= 8.0
+    with pytest.raises(saba.SabaError):
+        saba.autotune_bouquet(sg, src, 12, 5, 9.0)
