@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsaba.so")
-SOURCES = ["graph.hip", "walks.hip", "aesc.hip", "server.hip", "spectral.hip", "probe.hip"]
+SOURCES = ["graph.hip", "walks.hip", "aesc.hip", "server.hip", "spectral.hip", "probe.hip", "tune.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
