@@ -319,7 +319,7 @@ def bench_ablation(args, saba, torch, np):
     # the grouped schedule an autotuner picks under a correlation budget (least mean distinct
     # vertices per 8-walk vector, measured on the same workload)
     tuned = []
-    for budget in (7.5, 6.0, 4.0, 2.0, 1.0):
+    for budget in (() if args.no_tune else (7.5, 6.0, 4.0, 2.0, 1.0)):
         progress(f"ablation: bouquet autotuner at budget {budget}")
         b = saba.autotune_bouquet(sg, src, L, 1, budget)
         tuned.append({"min_distinct": budget, "group": b["group"], "spread": b["spread"],
@@ -1106,6 +1106,8 @@ def main():
     ap.add_argument("--omega", type=int, default=0,
                     help="eigenpairs of the all-edges estimator run (aesc_full)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="ablation: skip the grouped-bouquet autotuner (counter runs)")
     ap.add_argument("--no-full", action="store_true",
                     help="skip the all-edges estimator pass of the default run")
     ap.add_argument("--no-serve", action="store_true",
