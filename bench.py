@@ -552,9 +552,11 @@ def bench_omega(args, saba, torch, np):
 
 
 def bench_aesc_full(args, saba, torch, np):
-    """All edges of the 10^6-vertex Chung-Lu graph at eps = 0.1: the edges in canonical order
-    cut into 40 query calls (each result equals the all-edges call's entry), one progress line
-    per call (the last calls, edges between low-degree vertices, carry most of the walks)."""
+    """All edges of the 10^6-vertex Chung-Lu graph at eps = 0.1.  omega = 0: the sources in 100
+    consecutive ranges (saba_aesc_sources, one progress line per range; each source's levels
+    run once), then saba_aesc_combine, which gives saba_aesc's output bit for bit.  omega > 0
+    (the eigenpair tail belongs to the undirected edge): the canonical edges in 40 query calls,
+    each equal to the all-edges call's entries."""
     import graphgen
     g, lam1, _ = chung_lu_1e6()
     omega = args.omega
@@ -562,25 +564,40 @@ def bench_aesc_full(args, saba, torch, np):
     lam = lam1 if omega == 0 else 0.0
     sg = saba.SabaGraph.from_graph(g, trusted=True)
     ce = graphgen.canonical_edges(g)
-    parts = np.array_split(np.arange(g.m), 40)
     saba.aesc_query(sg, torch.from_numpy(np.ascontiguousarray(ce[:64])).cuda(), args.aesc_eps, lam, 1,
                     omega=omega)
     torch.cuda.synchronize()
     steps = 0
-    sums = 0.0
     t0 = time.perf_counter()
-    for k, idx in enumerate(parts):
-        q = torch.from_numpy(np.ascontiguousarray(ce[idx])).cuda()
-        sc, st = saba.aesc_query(sg, q, args.aesc_eps, lam, 1, omega=omega)
+    if omega == 0:
+        gd = torch.empty(g.nnz, dtype=torch.float64, device="cuda")
+        nr = 100
+        bounds = np.linspace(0, g.n, nr + 1).astype(int)
+        for k in range(nr):
+            st = saba.aesc_sources(sg, gd, int(bounds[k]), int(bounds[k + 1]), args.aesc_eps, lam, 1)
+            torch.cuda.synchronize()
+            steps += st["walk_steps"]
+            progress(f"aesc full: {k + 1}/{nr} source ranges, {time.perf_counter() - t0:.1f} s")
+        sc = saba.aesc_combine(sg, gd)
         torch.cuda.synchronize()
-        steps += st["walk_steps"]
-        sums += float(sc.sum().item())
-        progress(f"aesc full: {k + 1}/{len(parts)} parts, {time.perf_counter() - t0:.1f} s")
+        sums = float(sc.sum().item())
+        form = f"{nr} source ranges (saba_aesc_sources) and saba_aesc_combine"
+    else:
+        parts = np.array_split(np.arange(g.m), 40)
+        sums = 0.0
+        for k, idx in enumerate(parts):
+            q = torch.from_numpy(np.ascontiguousarray(ce[idx])).cuda()
+            sc, st = saba.aesc_query(sg, q, args.aesc_eps, lam, 1, omega=omega)
+            torch.cuda.synchronize()
+            steps += st["walk_steps"]
+            sums += float(sc.sum().item())
+            progress(f"aesc full: {k + 1}/{len(parts)} parts, {time.perf_counter() - t0:.1f} s")
+        form = "40 query calls over the canonical edges"
     dt = time.perf_counter() - t0
     return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_all_edges"
             + (f"_omega{omega}" if omega else ""), "edges": g.m, "n": g.n,
             "lambda": lam, "omega": omega, "seconds": dt, "edges_per_s": g.m / dt,
-            "walk_steps": steps, "sum_sc": sums, "n_minus_1": g.n - 1}
+            "walk_steps": steps, "sum_sc": sums, "n_minus_1": g.n - 1, "form": form}
 
 
 def _batch_graph(spec):

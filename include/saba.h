@@ -504,6 +504,27 @@ int saba_aesc_edge_stats(saba_graph *g, const saba_aesc_params *p, double *d_sc,
                          void *stream);
 
 /*
+ * The directed estimates of the edges out of a range of sources (Alg. 1's outer loop over the
+ * sources src_begin .. src_end - 1): d_g[e] = g(s, col_idx[e]) for every CSR position e of
+ * those rows (d_g is the caller's device array over all nnz positions; other entries are not
+ * touched), exactly the entry saba_aesc_edge_stats writes.  A caller covers the sources in
+ * pieces (for memory or progress) and forms SC with saba_aesc_combine; each source's
+ * deterministic levels run once.  Errors: SABA_E_INVALID (range outside 0 .. n, an empty
+ * range, omega > 0: the eigenpair tail belongs to the undirected edge, use saba_aesc), and
+ * saba_aesc's errors.
+ */
+int saba_aesc_sources(saba_graph *g, const saba_aesc_params *p, int32_t src_begin,
+                      int32_t src_end, double *d_g, saba_stats *stats, void *stream);
+
+/*
+ * Spanning centrality of all edges from directed estimates (Alg. 1's final combine):
+ * d_sc[i] = d_g[e] + d_g[rev(e)] for the i-th canonical edge (u < v, lexicographic), e its CSR
+ * position u -> v.  d_g[nnz] and d_sc[m] are device arrays; with d_g from saba_aesc_sources
+ * over all sources, d_sc equals saba_aesc's output bit for bit (omega = 0).
+ */
+int saba_aesc_combine(saba_graph *g, const double *d_g, double *d_sc, void *stream);
+
+/*
  * Integer visit counts of the walk pairs of Alg. 1 (its inner loop) for a list of sources,
  * for parity checks: the statistic X of a pair is sum_b h(W^s[b]) - sum_b h(W^t[b]) over
  * positions b = 1..L, so the Monte-Carlo sum of a directed edge (s, t) is

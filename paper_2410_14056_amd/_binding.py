@@ -186,7 +186,7 @@ EXPORTS = ["saba_version", "saba_last_error", "saba_graph_create", "saba_graph_c
            "saba_graph_get_config", "saba_graph_set_config", "saba_autotune_walks",
            "saba_probe_random_reads", "saba_graph_spectrum", "saba_autotune_aesc",
            "saba_debug_fail_allocation", "saba_aesc_counts", "saba_walks_noalloc",
-           "saba_autotune_bouquet"]
+           "saba_autotune_bouquet", "saba_aesc_sources", "saba_aesc_combine"]
 
 _lib = None
 
@@ -215,6 +215,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(Stats), P]
     L.saba_aesc_counts.argtypes = [P, ctypes.POINTER(AescParams), P, i32, P, P, P, P, P, P, P,
                                    P, P, P, ctypes.POINTER(Stats), P]
+    L.saba_aesc_sources.argtypes = [P, ctypes.POINTER(AescParams), i32, i32, P,
+                                    ctypes.POINTER(Stats), P]
+    L.saba_aesc_combine.argtypes = [P, P, P, P]
     L.saba_aesc_batch.argtypes = [P, P, i32, ctypes.POINTER(BatchOptions), ctypes.POINTER(Stats), P]
     L.saba_server_create.argtypes = [P, ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
     L.saba_server_submit.argtypes = [P, ctypes.POINTER(ServerRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -521,6 +524,26 @@ def aesc_edge_stats(graph: SabaGraph, eps: float, lam: float, seed: int, device=
         _ptr(out["nreq"]), _ptr(out["D"]), _ptr(out["MC"]), _ptr(out["vis0"]), _ptr(out["vis1"]),
         _ptr(out["g"]), ctypes.byref(st), _stream_ptr(stream)))
     return out, st.as_dict()
+
+
+def aesc_sources(graph: SabaGraph, g: torch.Tensor, src_begin: int, src_end: int, eps: float,
+                 lam: float, seed: int, stream=None, **kw) -> dict:
+    """saba_aesc_sources: directed estimates of the edges out of sources [src_begin, src_end),
+    written into g (float64 [nnz], device) at their CSR positions; returns the stats."""
+    assert g.is_cuda and g.dtype == torch.float64 and g.numel() == graph.nnz
+    p = _aesc_params(eps, lam, seed, **kw)
+    st = Stats()
+    _check(load().saba_aesc_sources(graph.handle, ctypes.byref(p), int(src_begin), int(src_end),
+                                    _ptr(g), ctypes.byref(st), _stream_ptr(stream)))
+    return st.as_dict()
+
+
+def aesc_combine(graph: SabaGraph, g: torch.Tensor, stream=None) -> torch.Tensor:
+    """saba_aesc_combine: SC of all edges in canonical order from directed estimates g."""
+    assert g.is_cuda and g.dtype == torch.float64 and g.numel() == graph.nnz
+    sc = torch.empty(graph.nnz // 2, dtype=torch.float64, device=g.device)
+    _check(load().saba_aesc_combine(graph.handle, _ptr(g), _ptr(sc), _stream_ptr(stream)))
+    return sc
 
 
 def aesc_counts(graph: SabaGraph, sources, eps: float, lam: float, seed: int, device="cuda",

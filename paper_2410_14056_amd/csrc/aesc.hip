@@ -1724,6 +1724,10 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
                       "returned for the same parameters");
             return SABA_E_INVALID;
         }
+        // a source list that is an ascending run of vertices exports its per-edge values with
+        // one copy per array: its instances, and their edges, are consecutive in that order
+        bool run = true;
+        for (size_t k = 1; k < K && run; ++k) run = cj->src[k] == cj->src[0] + (int32_t)k;
         int64_t so = 0, eo = 0, ho = 0;
         for (size_t k = 0; k < K; ++k) {
             const int64_t i = inst_of(0, cj->src[k]);
@@ -1741,19 +1745,23 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             eo += d;
             ho += 2 * (int64_t)d * sz[i];
             const Exports &x = cj->edges;
-            const int64_t e0 = iebase[i], o = c.edge_off;
+            int64_t e0 = iebase[i], o = c.edge_off, cnt = d;
+            if (run) {  // everything in one copy, at the first source
+                if (k > 0) continue;
+                cnt = iebase[inst_of(0, cj->src[K - 1]) + 1] - e0;
+            }
             auto cp = [&](void *dst, const void *src, size_t bytes) -> int {
                 if (dst && bytes)
                     SABA_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
                 return SABA_OK;
             };
-            SABA_TRY(cp(x.tau ? x.tau + o : nullptr, ea.tau + e0, sizeof(int32_t) * d));
-            SABA_TRY(cp(x.nreq ? x.nreq + o : nullptr, ea.nreq + e0, sizeof(int64_t) * d));
-            SABA_TRY(cp(x.D ? x.D + o : nullptr, ea.D + e0, sizeof(double) * d));
-            SABA_TRY(cp(x.MC ? x.MC + o : nullptr, ea.MC + e0, sizeof(double) * d));
-            SABA_TRY(cp(x.vis0 ? x.vis0 + o : nullptr, ea.vis0 + e0, sizeof(int64_t) * d));
-            SABA_TRY(cp(x.vis1 ? x.vis1 + o : nullptr, ea.vis1 + e0, sizeof(int64_t) * d));
-            SABA_TRY(cp(x.g ? x.g + o : nullptr, ea.g + e0, sizeof(double) * d));
+            SABA_TRY(cp(x.tau ? x.tau + o : nullptr, ea.tau + e0, sizeof(int32_t) * cnt));
+            SABA_TRY(cp(x.nreq ? x.nreq + o : nullptr, ea.nreq + e0, sizeof(int64_t) * cnt));
+            SABA_TRY(cp(x.D ? x.D + o : nullptr, ea.D + e0, sizeof(double) * cnt));
+            SABA_TRY(cp(x.MC ? x.MC + o : nullptr, ea.MC + e0, sizeof(double) * cnt));
+            SABA_TRY(cp(x.vis0 ? x.vis0 + o : nullptr, ea.vis0 + e0, sizeof(int64_t) * cnt));
+            SABA_TRY(cp(x.vis1 ? x.vis1 + o : nullptr, ea.vis1 + e0, sizeof(int64_t) * cnt));
+            SABA_TRY(cp(x.g ? x.g + o : nullptr, ea.g + e0, sizeof(double) * cnt));
         }
     }
 
@@ -1977,6 +1985,57 @@ extern "C" int saba_aesc_counts(saba_graph *gh, const saba_aesc_params *p,
     reqs[0].p = *p;
     reqs[0].q = 0;
     return aesc_run(g, reqs, opts_of(p), nullptr, st, static_cast<hipStream_t>(stream), &cj);
+}
+
+extern "C" int saba_aesc_sources(saba_graph *gh, const saba_aesc_params *p, int32_t src_begin,
+                                 int32_t src_end, double *d_g, saba_stats *st, void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!p || !d_g) {
+        set_error("params or output is NULL");
+        return SABA_E_INVALID;
+    }
+    SABA_TRY(single_graph(G(gh)));
+    Graph *g = G(gh);
+    if (src_begin < 0 || src_end > g->n || src_begin >= src_end) {
+        set_error("the source range must satisfy 0 <= begin < end <= n");
+        return SABA_E_INVALID;
+    }
+    if (p->omega != 0) {
+        set_error("the source-range form keeps no eigenpair tail: use saba_aesc for omega > 0");
+        return SABA_E_INVALID;
+    }
+    CountJob cj;
+    std::vector<saba_count_source> layout((size_t)(src_end - src_begin));
+    cj.src.resize(layout.size());
+    for (int32_t v = src_begin; v < src_end; ++v) {
+        cj.src[v - src_begin] = v;
+        layout[v - src_begin].source = v;
+    }
+    cj.layout = layout.data();
+    cj.edges.g = d_g + g->h_row_ptr[src_begin];
+    std::vector<Request> reqs(1);
+    reqs[0].p = *p;
+    reqs[0].q = 0;
+    return aesc_run(g, reqs, opts_of(p), nullptr, st, static_cast<hipStream_t>(stream), &cj);
+}
+
+extern "C" int saba_aesc_combine(saba_graph *gh, const double *d_g, double *d_sc, void *stream) {
+    clear_error();
+    SABA_TRY(check_graph(gh));
+    if (!d_g || !d_sc) {
+        set_error("input or output is NULL");
+        return SABA_E_INVALID;
+    }
+    SABA_TRY(single_graph(G(gh)));
+    Graph *g = G(gh);
+    const int64_t m = g->nnz / 2;
+    if (m > 0) {
+        finalize_all_kernel<<<grid_for(m, 256, 1 << 16), 256, 0, static_cast<hipStream_t>(stream)>>>(
+            g->canon, g->rev, 0, m, 0, 0, d_g, d_sc);
+        SABA_HIP_TRY(hipGetLastError());
+    }
+    return SABA_OK;
 }
 
 extern "C" int saba_aesc_batch(saba_graph *gh, const saba_aesc_request *reqs, int32_t nreq,

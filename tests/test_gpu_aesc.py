@@ -216,3 +216,24 @@ def test_chung_lu_1e6_query_sampled_edges_match_oracle(saba, orc):
     np.testing.assert_allclose(sq.cpu().numpy()[pick], so, rtol=RTOL, atol=1e-15)
     assert st["sources"] > 0 and st["walk_steps"] > 0
 
+
+
+def test_source_ranges_and_combine_equal_all_edges(saba):
+    """saba_aesc_sources over ragged pieces of the source range writes exactly the directed
+    estimates of the all-edges run, and saba_aesc_combine turns them into saba_aesc's output,
+    bit for bit (each source's levels run once, in whichever piece holds it)."""
+    import torch
+    g, lam = _graph(300, 1200, 3)
+    sg = saba.SabaGraph.from_graph(g)
+    ref, _ = saba.aesc(sg, 0.1, lam, 5)
+    full, _ = saba.aesc_edge_stats(sg, 0.1, lam, seed=5)
+    gd = torch.full((g.nnz,), float("nan"), dtype=torch.float64, device="cuda")
+    for a, b, kw in ((0, 1, {}), (1, 97, {"batch_sources": 7}), (97, g.n, {})):
+        st = saba.aesc_sources(sg, gd, a, b, 0.1, lam, 5, **kw)
+        assert st["sources"] == b - a
+    assert torch.equal(gd, full["g"])
+    assert torch.equal(saba.aesc_combine(sg, gd), ref)
+    for a, b, kw in ((5, 5, {}), (-1, 3, {}), (0, g.n + 1, {}), (0, 3, {"omega": 4})):
+        with pytest.raises(saba.SabaError) as ei:
+            saba.aesc_sources(sg, gd, a, b, 0.1, lam, 5, **kw)
+        assert ei.value.name == "SABA_E_INVALID"
