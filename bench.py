@@ -416,6 +416,20 @@ def bench_aesc(args, saba, torch, np):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert bool(torch.isfinite(sc).all().item())
+    # the same query with every batch in order on one stream (the default overlaps the levels
+    # of batch k + 1 with the walk pairs of batch k): identical results; its pools are grown
+    # on the tuning sample first
+    cfg = saba.get_config(sg)
+    saba.set_config(sg, **{**cfg, "est_batch_streams": 1})
+    saba.aesc_query(sg, sample, args.aesc_eps, lam, 1, mem_budget=int(args.aesc_mem_gib * (1 << 30)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sc1, st1 = saba.aesc_query(sg, qt, args.aesc_eps, lam, 1, time_kernels=True,
+                               mem_budget=int(args.aesc_mem_gib * (1 << 30)))
+    torch.cuda.synchronize()
+    d1 = time.perf_counter() - t1
+    saba.set_config(sg, **cfg)
+    assert torch.equal(sc, sc1), "in-order batches differ from overlapped batches"
     walk_s = st["kernel_ms"] * 1e-3
     achieved = AESC_STEP_BYTES * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
     line = AESC_STEP_BYTES_LINE * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
@@ -433,7 +447,9 @@ def bench_aesc(args, saba, torch, np):
         "push_edge_visits": st["push_edge_visits"],
         "sources": st["sources"],
         "max_tau": st["max_tau"], "max_ttau": st["max_ttau"],
-        "tuned": tuned, "autotune_s": tune_s,
+        "tuned": tuned, "autotune_s": tune_s, "batches": st["batches"],
+        "in_order": {"seconds": d1, "edges_per_s": k / d1, "batches": st1["batches"],
+                     "walk_kernel_ms": st1["kernel_ms"], "identical": True},
         "roofline": {"bound": "hbm", "kernel": "mc_walk_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": estimator_traffic(st["walk_steps"], st["batches"]),
@@ -774,12 +790,11 @@ def bench_batch(args, saba, torch, np):
     # the two walk-pair schedules at the tuned grids
     sched = {}
     for wq in (0, 1):
-        saba.set_config(mg, **{**{k: v for k, v in tuned.items() if k != "reserved"},
-                               "est_walk_queue": wq})
+        saba.set_config(mg, **{**tuned, "est_walk_queue": wq})
         _, st_q, t_q = batched(reqs)
         sched["queue" if wq else "static"] = {"seconds": t_q, "walk_kernel_ms": st_q["kernel_ms"]}
         progress(f"batch workload: {'queue' if wq else 'static'} schedule {t_q:.3f} s")
-    saba.set_config(mg, **{k: v for k, v in tuned.items() if k != "reserved"})
+    saba.set_config(mg, **tuned)
     nq_cert = sum(int(qs[k].shape[0]) for k in certified)
     kinds = {0: "erdos_renyi", 1: "chung_lu", 2: "grid"}
     return {"workload": f"batch_{G}graphs_n1e3-2e5_er_cl_grid_q{args.batch_frac:g}",

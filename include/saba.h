@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define SABA_ABI_VERSION 4
+#define SABA_ABI_VERSION 5
 
 /* status codes */
 #define SABA_OK 0
@@ -142,7 +142,8 @@ typedef struct {
     int32_t push_all;      /* nonzero: deterministic levels up to tau, no walks */
     int32_t batch_sources; /* sources per batch (0: chosen from mem_budget); no effect on results */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
-    int64_t mem_budget;    /* bytes of per-batch scratch (0: the smaller of 32 GiB and 40% of free memory) */
+    int64_t mem_budget;    /* bytes of batch scratch (0: the smaller of 32 GiB and 40% of free memory);
+                              with two batch streams each pool set holds half of it */
     int32_t omega;         /* eigenpairs used (Alg. 1's omega), 0 <= omega <= 64.  0: the plain
                               truncated series with tau from lambda.  omega > 0: the library
                               finds the omega nontrivial eigenpairs of N of largest |theta|
@@ -171,7 +172,8 @@ typedef struct {
 
 /* Execution options of saba_aesc_batch; none of them changes a result. */
 typedef struct {
-    int64_t mem_budget;    /* bytes of per-batch scratch (0: the smaller of 32 GiB and 40% of free memory) */
+    int64_t mem_budget;    /* bytes of batch scratch (0: the smaller of 32 GiB and 40% of free memory);
+                              with two batch streams each pool set holds half of it */
     int32_t batch_sources; /* cap on instances per batch (0: from mem_budget) */
     int32_t time_kernels;  /* nonzero: fill kernel_ms / total_ms in saba_stats */
 } saba_batch_options;
@@ -234,7 +236,12 @@ typedef struct {
     int32_t est_walk_queue;  /* 1: the estimator's walk-pair launch takes its chunks from
                                 device work queues (one per XCD range of the chunk space);
                                 0: a fixed wavefront stride over the chunks */
-    int32_t reserved;
+    int32_t est_batch_streams; /* streams of the synchronous estimator calls: 2 (and 0) = two
+                                  pool sets of half the memory budget each, the deterministic
+                                  levels of batch k + 1 on the handle's second stream while the
+                                  walk pairs of batch k run on the caller's stream; 1 = every
+                                  batch in order on the caller's stream.  The counts export
+                                  (saba_aesc_counts) always runs in order */
 } saba_exec_config;
 
 /* Options of saba_server_create; none of them changes a result. */

@@ -172,7 +172,7 @@ class ExecConfig(ctypes.Structure):
     _fields_ = [("walks_per_lane", ctypes.c_int32), ("walk_blocks", ctypes.c_int32),
                 ("est_walk_blocks", ctypes.c_int32), ("est_push_blocks", ctypes.c_int32),
                 ("walk_chunks", ctypes.c_int32), ("est_walk_queue", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("est_batch_streams", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -399,11 +399,12 @@ def get_config(graph: SabaGraph) -> dict:
 
 def set_config(graph: SabaGraph, walks_per_lane: int = 0, walk_blocks: int = 0,
                est_walk_blocks: int = 0, est_push_blocks: int = 0, walk_chunks: int = 0,
-               est_walk_queue: int = 0):
+               est_walk_queue: int = 0, est_batch_streams: int = 0):
     """saba_graph_set_config: execution knobs of the handle (0 = default); never changes a
     result."""
     c = ExecConfig(int(walks_per_lane), int(walk_blocks), int(est_walk_blocks),
-                   int(est_push_blocks), int(walk_chunks), int(est_walk_queue), 0)
+                   int(est_push_blocks), int(walk_chunks), int(est_walk_queue),
+                   int(est_batch_streams))
     _check(load().saba_graph_set_config(graph.handle, ctypes.byref(c)))
 
 

@@ -1256,11 +1256,12 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs,
     return SABA_OK;
 }
 
-int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
-              const std::vector<int64_t> &heb, int64_t ie0, int64_t nle, int64_t maxgn,
-              int64_t hubcap, BatchTiming *tm, hipStream_t s, const CountExport *cx) {
+int batch_levels(const Graph *g, Workspace &ws, const EdgeArrays &ea,
+                 const std::vector<Slot> &hslots, const std::vector<int64_t> &heb, int64_t ie0,
+                 int64_t nle, int64_t maxgn, int64_t hubcap, hipStream_t s, BatchPlan *plan) {
     auto &E = ws.b;
     const int32_t nb = (int32_t)hslots.size();
+    *plan = BatchPlan{};
     if (nb == 0) return SABA_OK;
     if (nb > 65535) {
         set_error("a batch holds at most 65535 instances");
@@ -1281,7 +1282,6 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     Flags *fl = ea.fl;
     // execution knobs of the handle (none changes a result)
     const unsigned push_blocks = g->cfg.est_push_blocks > 0 ? g->cfg.est_push_blocks : kPushGrid;
-    const unsigned walk_blocks = g->cfg.est_walk_blocks > 0 ? g->cfg.est_walk_blocks : kWalkGrid;
     ws.clean = false;  // until the batch has cleared everything it touched
 
     SABA_HIP_TRY(hipMemcpyAsync(d_slots, hslots.data(), sizeof(Slot) * nb, hipMemcpyHostToDevice,
@@ -1294,7 +1294,6 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
         ea.vis0, ea.vis1, hubs, fl);
     SABA_HIP_TRY(hipGetLastError());
     const unsigned ysplit = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, maxgn / 4096));
-    const dim3 grid(ysplit, (unsigned)nb);
     for (int32_t level = 0;; ++level) {
         const int cur = level & 1;
         double *hcur = cur ? hB : hA, *hnext = cur ? hA : hB;
@@ -1341,10 +1340,34 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
         return SABA_E_OVERFLOW;  // the pools stay marked dirty: re-zeroed before the next use
     }
     SABA_TRY(E[B_PART].ensure(sizeof(double) * std::max<int64_t>(T, 1)));
+    plan->nb = nb;
+    plan->ie0 = ie0;
+    plan->nle = nle;
+    plan->T = T;
+    plan->ysplit = ysplit;
+    return SABA_OK;
+}
+
+int batch_walks(const Graph *g, Workspace &ws, const EdgeArrays &ea, const BatchPlan &plan,
+                hipEvent_t t0, hipEvent_t t1, hipStream_t s, const CountExport *cx) {
+    auto &E = ws.b;
+    const int32_t nb = plan.nb;
+    if (nb == 0) return SABA_OK;
+    const int64_t ie0 = plan.ie0, nle = plan.nle, T = plan.T;
+    double *hA = E[B_HA].as<double>(), *hB = E[B_HB].as<double>();
+    int32_t *FA = E[B_FA].as<int32_t>(), *FB = E[B_FB].as<int32_t>();
+    uint32_t *bmA = E[B_BMA].as<uint32_t>(), *bmB = E[B_BMB].as<uint32_t>();
+    Slot *d_slots = E[B_SLOT].as<Slot>();
+    int64_t *d_eb = E[B_EB].as<int64_t>();
+    BatchState *bs = E[B_BSTATE].as<BatchState>();
+    int64_t *coff = E[B_COFF].as<int64_t>();
     double *partial = E[B_PART].as<double>();
+    Flags *fl = ea.fl;
+    const unsigned walk_blocks = g->cfg.est_walk_blocks > 0 ? g->cfg.est_walk_blocks : kWalkGrid;
+    const dim3 grid(plan.ysplit, (unsigned)nb);
     if (T > 0) {
-        const bool timing = tm && tm->on;
-        if (timing) SABA_HIP_TRY(hipEventRecord(tm->a, s));
+        const bool timing = t0 && t1;
+        if (timing) SABA_HIP_TRY(hipEventRecord(t0, s));
         const unsigned wgrid = grid_for(T, kWavesPerBlock, walk_blocks);
         const bool queue = g->cfg.est_walk_queue == 1;
         if (queue) SABA_HIP_TRY(hipMemsetAsync(fl->wq, 0, sizeof(fl->wq), s));
@@ -1365,13 +1388,7 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
         }
 #undef SABA_MC_LAUNCH
         SABA_HIP_TRY(hipGetLastError());
-        if (timing) {
-            SABA_HIP_TRY(hipEventRecord(tm->b, s));
-            SABA_HIP_TRY(hipEventSynchronize(tm->b));
-            float ms = 0.f;
-            SABA_HIP_TRY(hipEventElapsedTime(&ms, tm->a, tm->b));
-            tm->walk_ms += ms;
-        }
+        if (timing) SABA_HIP_TRY(hipEventRecord(t1, s));
     }
     edge_reduce_kernel<<<grid_for(nle, kBlock, 1 << 16), kBlock, 0, s>>>(
         g->vrec, d_slots, nb, d_eb, ie0, coff, nle, ea.want, ea.nreq, ea.D, partial, ea.MC, ea.g);
@@ -1381,6 +1398,23 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
     clear_final_kernel<<<grid, kBlock, 0, s>>>(d_slots, bs, hA, hB, bmA, bmB, FA, FB);
     SABA_HIP_TRY(hipGetLastError());
     ws.clean = true;
+    return SABA_OK;
+}
+
+int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::vector<Slot> &hslots,
+              const std::vector<int64_t> &heb, int64_t ie0, int64_t nle, int64_t maxgn,
+              int64_t hubcap, BatchTiming *tm, hipStream_t s, const CountExport *cx) {
+    BatchPlan plan;
+    SABA_TRY(batch_levels(g, ws, ea, hslots, heb, ie0, nle, maxgn, hubcap, s, &plan));
+    const bool timing = tm && tm->on && plan.T > 0;
+    SABA_TRY(batch_walks(g, ws, ea, plan, timing ? tm->a : nullptr, timing ? tm->b : nullptr, s,
+                         cx));
+    if (timing) {
+        SABA_HIP_TRY(hipEventSynchronize(tm->b));
+        float ms = 0.f;
+        SABA_HIP_TRY(hipEventElapsedTime(&ms, tm->a, tm->b));
+        tm->walk_ms += ms;
+    }
     return SABA_OK;
 }
 
@@ -1424,6 +1458,28 @@ static bool same_params(const Request &a, const Request &b) {
            x.seed == y.seed && x.group == y.group && x.spread == y.spread &&
            x.tau_cap == y.tau_cap && x.tilde_tau_max == y.tilde_tau_max &&
            (x.push_all != 0) == (y.push_all != 0);
+}
+
+// The estimator's second stream (default priority) and its hand-over events, created once per
+// handle.
+static int ensure_est_pipeline(Graph *g) {
+    if (g->est_aux) return SABA_OK;
+    for (auto &e : g->est_ev)
+        if (!e) SABA_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipStream_t st = nullptr;
+    SABA_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    g->est_aux = st;
+    return SABA_OK;
+}
+
+static void merge_flags(Flags &a, const Flags &b) {
+    a.err |= b.err;
+    a.max_tau = std::max(a.max_tau, b.max_tau);
+    a.max_ttau = std::max(a.max_ttau, b.max_ttau);
+    a.warnings |= b.warnings;
+    a.walk_steps += b.walk_steps;
+    a.push_visits += b.push_visits;
+    a.walks += b.walks;
 }
 
 static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const Exports *ex,
@@ -1567,21 +1623,23 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         }
     }
 
-    BatchTiming tm;
-    tm.on = st && opt.time_kernels;
+    const bool timing = st && opt.time_kernels;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // walk-pair launch bounds of every batch (timing), read once the call has finished
+    std::vector<hipEvent_t> wev;
     struct EvGuard {
-        hipEvent_t *e[4];
+        hipEvent_t *e[2];
+        std::vector<hipEvent_t> *v;
         ~EvGuard() {
             for (auto *x : e)
                 if (*x) (void)hipEventDestroy(*x);
+            for (auto x : *v)
+                if (x) (void)hipEventDestroy(x);
         }
-    } evguard{{&ev0, &ev1, &tm.a, &tm.b}};
-    if (tm.on) {
+    } evguard{{&ev0, &ev1}, &wev};
+    if (timing) {
         SABA_HIP_TRY(hipEventCreate(&ev0));
         SABA_HIP_TRY(hipEventCreate(&ev1));
-        SABA_HIP_TRY(hipEventCreate(&tm.a));
-        SABA_HIP_TRY(hipEventCreate(&tm.b));
         SABA_HIP_TRY(hipEventRecord(ev0, s));
     }
 
@@ -1600,6 +1658,9 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
     const int64_t budget = opt.mem_budget > 0
                                ? opt.mem_budget
                                : std::min<int64_t>(32ll << 30, (int64_t)(0.4 * (double)freeb));
+    // two pool sets (levels of the next batch beside the walk pairs of this one) share it
+    const int lanes = (!cj && g->cfg.est_batch_streams != 1) ? 2 : 1;
+    const int64_t lane_budget = budget / lanes;
     std::vector<SlotSize> ssz(P);
     for (int32_t k = 0; k < P; ++k) ssz[k] = slot_size(g, pgraph[k]);
     struct Batch {
@@ -1612,7 +1673,7 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         int64_t bytes = 0;
         while (bt.i1 < ns) {
             const SlotSize &z = ssz[inst_p[bt.i1]];
-            if (bt.i1 > bt.i0 && (bytes + z.bytes > budget || bt.i1 - bt.i0 >= 65535 ||
+            if (bt.i1 > bt.i0 && (bytes + z.bytes > lane_budget || bt.i1 - bt.i0 >= 65535 ||
                                   (opt.batch_sources > 0 && bt.i1 - bt.i0 >= opt.batch_sources)))
                 break;
             bytes += z.bytes;
@@ -1633,6 +1694,21 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         i = bt.i1;
     }
     SABA_TRY(ensure_pools(ws, maxh, maxbm, maxsb, maxhubs, maxnb, maxne, s));
+    const bool overlap = lanes == 2 && batches.size() >= 2;
+    Workspace *wsl[2] = {&ws, &g->est2};
+    EdgeArrays eal[2] = {ea, ea};
+    hipStream_t slev = s;  // stream of the levels phases
+    if (overlap) {
+        SABA_TRY(ensure_est_pipeline(g));
+        SABA_TRY(ensure_pools(g->est2, maxh, maxbm, maxsb, maxhubs, maxnb, maxne, s));
+        SABA_TRY(g->est2.b[B_FLAGS].ensure(sizeof(Flags)));
+        eal[1].fl = g->est2.b[B_FLAGS].as<Flags>();
+        SABA_HIP_TRY(hipMemsetAsync(eal[1].fl, 0, sizeof(Flags), s));
+        slev = g->est_aux;
+        // the levels stream starts after the set-up above
+        SABA_HIP_TRY(hipEventRecord(g->est_ev[0], s));
+        SABA_HIP_TRY(hipStreamWaitEvent(slev, g->est_ev[0], 0));
+    }
 
     // counts export: per-instance support offsets and histogram offsets in the caller's layout
     CountExport cx;
@@ -1674,9 +1750,19 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         }
     }
 
+    // Batch k uses pool set k mod 2 when the phases overlap: its levels run on slev once the walk
+    // pairs of batch k - 2 (the same pool set) are done, and its walk pairs on s once its levels
+    // are; the levels of batch k + 1 then run beside them.  Batches write disjoint instance
+    // edges and instances, so the results are those of the batches in order.
+    const auto drain = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (slev != s) (void)hipStreamSynchronize(slev);
+    };
     std::vector<Slot> hslots;
     std::vector<int64_t> heb;
-    for (const Batch &bt : batches) {
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const Batch &bt = batches[bi];
+        const int lane = overlap ? (int)(bi & 1) : 0;
         const int32_t nb = (int32_t)(bt.i1 - bt.i0);
         const int64_t ie0 = iebase[bt.i0];
         hslots.resize(nb);
@@ -1704,8 +1790,34 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             heb[b] = iebase[i] - ie0;
         }
         heb[nb] = bt.ne;
-        SABA_TRY(run_batch(g, ws, ea, hslots, heb, ie0, bt.ne, maxgn, bt.hubs, &tm, s,
-                           cj ? &cx : nullptr));
+        int rc = SABA_OK;
+        if (overlap && bi >= 2)
+            rc = SABA_HIP_STATUS(hipStreamWaitEvent(slev, g->est_ev[2 + lane], 0));
+        BatchPlan plan;
+        if (rc == SABA_OK)
+            rc = batch_levels(g, *wsl[lane], eal[lane], hslots, heb, ie0, bt.ne, maxgn, bt.hubs,
+                              slev, &plan);
+        if (rc == SABA_OK && overlap) {
+            rc = SABA_HIP_STATUS(hipEventRecord(g->est_ev[lane], slev));
+            if (rc == SABA_OK) rc = SABA_HIP_STATUS(hipStreamWaitEvent(s, g->est_ev[lane], 0));
+        }
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (rc == SABA_OK && timing && plan.T > 0) {
+            wev.push_back(nullptr);
+            rc = SABA_HIP_STATUS(hipEventCreate(&wev.back()));
+            t0 = wev.back();
+            wev.push_back(nullptr);
+            if (rc == SABA_OK) rc = SABA_HIP_STATUS(hipEventCreate(&wev.back()));
+            t1 = wev.back();
+        }
+        if (rc == SABA_OK)
+            rc = batch_walks(g, *wsl[lane], eal[lane], plan, t0, t1, s, cj ? &cx : nullptr);
+        if (rc == SABA_OK && overlap)
+            rc = SABA_HIP_STATUS(hipEventRecord(g->est_ev[2 + lane], s));
+        if (rc != SABA_OK) {
+            drain();  // nothing of this call stays in flight on the handle's pools
+            return rc;
+        }
     }
     if (cj) {
         // layout of the caller's arrays in list order, then the per-edge outputs
@@ -1819,10 +1931,13 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
             SABA_HIP_TRY(hipGetLastError());
         }
     }
-    if (tm.on) SABA_HIP_TRY(hipEventRecord(ev1, s));
-    Flags hf;
+    if (timing) SABA_HIP_TRY(hipEventRecord(ev1, s));
+    Flags hf, hf1{};
     SABA_HIP_TRY(hipMemcpyAsync(&hf, ea.fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
+    if (overlap)
+        SABA_HIP_TRY(hipMemcpyAsync(&hf1, eal[1].fl, sizeof(Flags), hipMemcpyDeviceToHost, s));
     SABA_HIP_TRY(hipStreamSynchronize(s));
+    if (overlap) merge_flags(hf, hf1);
     if (st) {
         *st = saba_stats{};
         st->walks = (int64_t)hf.walks;
@@ -1833,10 +1948,15 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
         st->max_tau = hf.max_tau;
         st->max_ttau = hf.max_ttau;
         st->warnings = hf.warnings;
-        if (tm.on) {
-            float tot = 0.f;
+        if (timing) {
+            float tot = 0.f, walk_ms = 0.f;
             SABA_HIP_TRY(hipEventElapsedTime(&tot, ev0, ev1));
-            st->kernel_ms = tm.walk_ms;
+            for (size_t i = 0; i + 1 < wev.size(); i += 2) {
+                float ms = 0.f;
+                SABA_HIP_TRY(hipEventElapsedTime(&ms, wev[i], wev[i + 1]));
+                walk_ms += ms;
+            }
+            st->kernel_ms = walk_ms;
             st->total_ms = tot;
         }
     }

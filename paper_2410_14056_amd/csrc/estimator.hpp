@@ -133,4 +133,22 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
               const std::vector<int64_t> &eb, int64_t ie0, int64_t nle, int64_t maxgn,
               int64_t hubs, BatchTiming *tm, hipStream_t s, const CountExport *cx = nullptr);
 
+// The two phases of run_batch, for callers that overlap the phases of consecutive batches on
+// two streams with two workspaces.  batch_levels uploads the slots and runs the deterministic
+// levels and the walk-pair counts on stream s; it returns with s drained (it reads the chunk
+// total back).  batch_walks queues the walk pairs, the per-edge reduction and the clears of the
+// same workspace on its stream, which must first wait for the levels phase; until they have
+// run, the workspace may not be handed to another batch.  t0/t1 (may be null) are recorded
+// around the walk-pair launch.
+struct BatchPlan {
+    int32_t nb = 0;
+    int64_t ie0 = 0, nle = 0, T = 0;  // T: 64-walk chunks of the walk-pair launch
+    unsigned ysplit = 1;
+};
+int batch_levels(const Graph *g, Workspace &ws, const EdgeArrays &ea,
+                 const std::vector<Slot> &hslots, const std::vector<int64_t> &eb, int64_t ie0,
+                 int64_t nle, int64_t maxgn, int64_t hubs, hipStream_t s, BatchPlan *plan);
+int batch_walks(const Graph *g, Workspace &ws, const EdgeArrays &ea, const BatchPlan &plan,
+                hipEvent_t t0, hipEvent_t t1, hipStream_t s, const CountExport *cx = nullptr);
+
 }  // namespace saba

@@ -285,6 +285,10 @@ static void destroy_graph(Graph *g) {
         if (e) (void)hipEventDestroy(e);
     if (g->walk_aux) (void)hipStreamDestroy(g->walk_aux);
     g->est.release();
+    g->est2.release();
+    for (auto &e : g->est_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->est_aux) (void)hipStreamDestroy(g->est_aux);
     for (auto &sp : g->spectra) sp->dev.release();
     delete g;
 }
@@ -501,7 +505,8 @@ extern "C" int saba_graph_set_config(saba_graph *gh, const saba_exec_config *cfg
         cfg->walk_blocks < 0 || cfg->walk_blocks > (1 << 16) || cfg->est_walk_blocks < 0 ||
         cfg->est_walk_blocks > (1 << 16) || cfg->est_push_blocks < 0 ||
         cfg->est_push_blocks > (1 << 16) || cfg->walk_chunks < 0 || cfg->walk_chunks > 64 ||
-        (cfg->est_walk_queue != 0 && cfg->est_walk_queue != 1) || cfg->reserved != 0) {
+        (cfg->est_walk_queue != 0 && cfg->est_walk_queue != 1) || cfg->est_batch_streams < 0 ||
+        cfg->est_batch_streams > 2) {
         set_error("invalid execution configuration");
         return SABA_E_INVALID;
     }

@@ -27,6 +27,16 @@ void clear_error();
         }                                                                                    \
     } while (0)
 
+// The library status of a HIP call's result (the message is set on failure), for code that has
+// to clean up before it returns.
+#define SABA_HIP_STATUS(expr)                                                                \
+    ([&]() -> int {                                                                          \
+        hipError_t _e = (expr);                                                              \
+        if (_e == hipSuccess) return SABA_OK;                                                \
+        ::saba::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                \
+        return SABA_E_HIP;                                                                   \
+    }())
+
 #define SABA_TRY(expr)                 \
     do {                               \
         int _rc = (expr);              \
@@ -95,6 +105,12 @@ struct Graph {
     hipStream_t walk_aux = nullptr;
     hipEvent_t walk_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     Workspace est;
+    // the synchronous estimator's second pool set and stream: the deterministic levels of one
+    // batch run there while the walk pairs of the previous batch run on the caller's stream;
+    // events: levels done x2, walk pairs done x2 (one per pool set), created on first use
+    Workspace est2;
+    hipStream_t est_aux = nullptr;
+    hipEvent_t est_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     saba_exec_config cfg{};  // execution knobs (0 = default)
     // lambda of each graph computed on the device for requests that leave it to the library
     std::mutex lam_mu;

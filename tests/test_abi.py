@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_loads_and_reports_version():
     import paper_2410_14056_amd as saba
     lib = saba.load()
-    assert lib.saba_version() == 4
+    assert lib.saba_version() == 5
     for name in saba.EXPORTS:
         assert hasattr(lib, name)
     assert set(saba.EXPORTS) == set(declared())
@@ -96,7 +96,7 @@ def test_server_structs_match_the_c_compiler(tmp_path):
         "saba_lambda_params": (b.LambdaParams, ["graph", "max_iters", "tol", "seed"]),
         "saba_exec_config": (b.ExecConfig, ["walks_per_lane", "walk_blocks", "est_walk_blocks",
                                             "est_push_blocks", "walk_chunks",
-                                            "est_walk_queue", "reserved"]),
+                                            "est_walk_queue", "est_batch_streams"]),
         "saba_lambda_result": (b.LambdaResult, ["lambda_bound", "residual", "iterations",
                                                 "converged"]),
         "saba_count_source": (b.CountSource, [f for f, _ in b.CountSource._fields_]),

@@ -64,6 +64,39 @@ def test_estimator_knobs_do_not_change_results(saba):
             assert torch.equal(sc, ref), (wq, wb, pb, "batched")
 
 
+def test_batch_streams_do_not_change_results(saba):
+    """Two pool sets with the levels of the next batch on a second stream give the results
+    and the per-call totals of the batches run in order: even and odd batch counts, one
+    batch (nothing to overlap), a query, a source range, and the walk-pair timing."""
+    import torch
+    g = graphgen.largest_component(graphgen.chung_lu(3000, 8, 2.3, 5))
+    lam = graphgen.spectral_lambda(g)
+    sg = saba.SabaGraph.from_graph(g)
+    keys = ("walks", "walk_steps", "push_edge_visits", "sources", "batches", "max_tau",
+            "max_ttau", "warnings")
+    ce = graphgen.canonical_edges(g)
+    pick = np.random.default_rng(8).choice(g.m, 300, replace=False)
+    q = torch.from_numpy(np.ascontiguousarray(ce[pick])).cuda()
+    for bsrc in (0, 250, 333, 1500):
+        outs = {}
+        for streams in (1, 2, 0):
+            saba.set_config(sg, est_walk_queue=1, est_batch_streams=streams)
+            sc, st = saba.aesc(sg, 0.2, lam, 4, tau_cap=64, batch_sources=bsrc,
+                               time_kernels=True)
+            qs, qst = saba.aesc_query(sg, q, 0.2, lam, 4, tau_cap=64, batch_sources=bsrc)
+            gs = torch.zeros(sg.nnz, dtype=torch.float64, device="cuda")
+            saba.aesc_sources(sg, gs, 100, 2100, 0.2, lam, 4, tau_cap=64, batch_sources=bsrc)
+            assert st["kernel_ms"] > 0 and st["total_ms"] >= st["kernel_ms"]
+            outs[streams] = (sc, {k: st[k] for k in keys}, qs, {k: qst[k] for k in keys}, gs)
+        for streams in (2, 0):
+            a, b = outs[1], outs[streams]
+            assert torch.equal(a[0], b[0]), (bsrc, streams)
+            assert a[1] == b[1], (bsrc, streams)
+            assert torch.equal(a[2], b[2]) and a[3] == b[3], (bsrc, streams, "query")
+            assert torch.equal(a[4], b[4]), (bsrc, streams, "sources")
+    saba.set_config(sg)
+
+
 def test_estimator_autotuner(saba):
     """saba_autotune_aesc picks a candidate grid, keeps it in the handle, and the sample's
     outputs and later results equal the untuned ones."""
@@ -110,7 +143,8 @@ def test_results_do_not_depend_on_the_stream(saba):
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
     for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20},
-               {"walk_chunks": 65}, {"walk_chunks": -1}, {"est_walk_queue": 2}):
+               {"walk_chunks": 65}, {"walk_chunks": -1}, {"est_walk_queue": 2},
+               {"est_batch_streams": 3}, {"est_batch_streams": -1}):
         with pytest.raises(saba.SabaError) as ei:
             saba.set_config(sg, **kw)
         assert ei.value.name == "SABA_E_INVALID"
