@@ -236,12 +236,12 @@ typedef struct {
     int32_t est_walk_queue;  /* 1: the estimator's walk-pair launch takes its chunks from
                                 device work queues (one per XCD range of the chunk space);
                                 0: a fixed wavefront stride over the chunks */
-    int32_t est_batch_streams; /* streams of the synchronous estimator calls: 2 (and 0) = two
-                                  pool sets of half the memory budget each, the deterministic
-                                  levels of batch k + 1 on the handle's second stream while the
-                                  walk pairs of batch k run on the caller's stream; 1 = every
-                                  batch in order on the caller's stream.  The counts export
-                                  (saba_aesc_counts) always runs in order */
+    int32_t est_batch_streams; /* streams of the synchronous estimator calls: 1 (and 0) = every
+                                  batch in order on the caller's stream; 2 = two pool sets of
+                                  half the memory budget each, the deterministic levels of
+                                  batch k + 1 on the handle's second stream while the walk
+                                  pairs of batch k run on the caller's stream.  The counts
+                                  export (saba_aesc_counts) always runs in order */
 } saba_exec_config;
 
 /* Options of saba_server_create; none of them changes a result. */
@@ -400,7 +400,7 @@ int saba_autotune_bouquet(saba_graph *g, const saba_walk_params *sample, double 
  * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
  * which may be NULL) under each candidate grid (512, 1024, 2048 or 4096 blocks for the
  * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels x the
- * static or the work-queue walk-pair schedule), times whole
+ * static or the work-queue walk-pair schedule x one or two batch streams), times whole
  * calls with HIP events, keeps the fastest in the handle and returns it in *best (may be
  * NULL).  The knobs do not change results; the sample's outputs hold its results on return.
  * Errors: those of saba_aesc_batch, SABA_E_INVALID for an empty sample.

@@ -1659,7 +1659,7 @@ static int aesc_run(Graph *g, std::vector<Request> &reqs, const Opts &opt, const
                                ? opt.mem_budget
                                : std::min<int64_t>(32ll << 30, (int64_t)(0.4 * (double)freeb));
     // two pool sets (levels of the next batch beside the walk pairs of this one) share it
-    const int lanes = (!cj && g->cfg.est_batch_streams != 1) ? 2 : 1;
+    const int lanes = (!cj && g->cfg.est_batch_streams == 2) ? 2 : 1;
     const int64_t lane_budget = budget / lanes;
     std::vector<SlotSize> ssz(P);
     for (int32_t k = 0; k < P; ++k) ssz[k] = slot_size(g, pgraph[k]);
@@ -2209,28 +2209,30 @@ extern "C" int saba_autotune_aesc(saba_graph *gh, const saba_aesc_request *sampl
     double best_ms = 1e300;
     const int walk_blocks[] = {512, 1024, 2048, 4096};
     const int push_blocks[] = {1024, 2048, 4096, 8192};
-    for (int wq = 0; wq < 2; ++wq)
-        for (int wb : walk_blocks)
-            for (int pb : push_blocks) {
-                g->cfg = saved;
-                g->cfg.est_walk_blocks = wb;
-                g->cfg.est_push_blocks = pb;
-                g->cfg.est_walk_queue = wq;
-                double ms = 0.0;
-                for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
-                    saba_stats st{};
-                    const int rc = saba_aesc_batch(gh, sample, nreq, &o, &st, stream);
-                    if (rc != SABA_OK) {
-                        g->cfg = saved;
-                        return rc;
+    for (int streams = 1; streams <= 2; ++streams)
+        for (int wq = 0; wq < 2; ++wq)
+            for (int wb : walk_blocks)
+                for (int pb : push_blocks) {
+                    g->cfg = saved;
+                    g->cfg.est_walk_blocks = wb;
+                    g->cfg.est_push_blocks = pb;
+                    g->cfg.est_walk_queue = wq;
+                    g->cfg.est_batch_streams = streams;
+                    double ms = 0.0;
+                    for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                        saba_stats st{};
+                        const int rc = saba_aesc_batch(gh, sample, nreq, &o, &st, stream);
+                        if (rc != SABA_OK) {
+                            g->cfg = saved;
+                            return rc;
+                        }
+                        if (rep > 0) ms += st.total_ms;
                     }
-                    if (rep > 0) ms += st.total_ms;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        pick = g->cfg;
+                    }
                 }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    pick = g->cfg;
-                }
-            }
     g->cfg = pick;
     if (best) *best = pick;
     return SABA_OK;

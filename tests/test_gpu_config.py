@@ -89,7 +89,7 @@ def test_batch_streams_do_not_change_results(saba):
             assert st["kernel_ms"] > 0 and st["total_ms"] >= st["kernel_ms"]
             outs[streams] = (sc, {k: st[k] for k in keys}, qs, {k: qst[k] for k in keys}, gs)
         for streams in (2, 0):
-            a, b = outs[1], outs[streams]
+            a, b = outs[1], outs[streams]  # 0: the default, in order
             assert torch.equal(a[0], b[0]), (bsrc, streams)
             assert a[1] == b[1], (bsrc, streams)
             assert torch.equal(a[2], b[2]) and a[3] == b[3], (bsrc, streams, "query")
@@ -111,6 +111,7 @@ def test_estimator_autotuner(saba):
     assert best["est_walk_blocks"] in (512, 1024, 2048, 4096)
     assert best["est_push_blocks"] in (1024, 2048, 4096, 8192)
     assert best["est_walk_queue"] in (0, 1)
+    assert best["est_batch_streams"] in (1, 2)
     assert saba.get_config(mg) == best
     out, _ = saba.aesc_batch(mg, reqs)
     for a, b in zip(out, ref):
