@@ -237,3 +237,55 @@ def test_source_ranges_and_combine_equal_all_edges(saba):
         with pytest.raises(saba.SabaError) as ei:
             saba.aesc_sources(sg, gd, a, b, 0.1, lam, 5, **kw)
         assert ei.value.name == "SABA_E_INVALID"
+
+
+def test_source_ranges_resume_on_a_new_handle(saba, tmp_path):
+    """Checkpoint and resume: the directed estimates of a first source range, saved to disk,
+    are completed by a later range on a new handle (another process could do the same), and
+    the combined SC equals the all-edges call bit for bit."""
+    import torch
+    g, lam = _graph(300, 1200, 11)
+    ck = tmp_path / "g_part.npy"
+    sg = saba.SabaGraph.from_graph(g)
+    gd = torch.zeros(g.nnz, dtype=torch.float64, device="cuda")
+    saba.aesc_sources(sg, gd, 0, 123, 0.15, lam, 9)
+    np.save(ck, gd.cpu().numpy())
+    del sg
+    sg2 = saba.SabaGraph.from_graph(g)
+    gd2 = torch.from_numpy(np.load(ck)).cuda()
+    saba.aesc_sources(sg2, gd2, 123, g.n, 0.15, lam, 9)
+    ref, _ = saba.aesc(sg2, 0.15, lam, 9)
+    assert torch.equal(saba.aesc_combine(sg2, gd2), ref)
+
+
+def test_bridges_and_foster(saba, orc):
+    """A non-bipartite core with a pendant path and a star: every bridge has SC = 1 exactly
+    (checked on the pseudoinverse), and its estimate lies within eps of 1; the estimates equal
+    the oracle's, every one is within eps of the exact value, and their sum is within eps * m
+    of Foster's n - 1."""
+    base = graphgen.largest_component(graphgen.er_gnm(120, 420, 7))
+    n0 = base.n
+    rows = np.repeat(np.arange(n0), np.diff(base.row_ptr))
+    keep = rows < base.col_idx
+    extra = [(0, n0), (n0, n0 + 1), (n0 + 1, n0 + 2), (n0 + 2, n0 + 3)]  # pendant path
+    extra += [(1, n0 + 4 + i) for i in range(4)]                              # star at vertex 1
+    u = np.concatenate([rows[keep], [a for a, _ in extra]])
+    v = np.concatenate([base.col_idx[keep], [b for _, b in extra]])
+    g = graphgen.canonical_csr(u, v, n0 + 8)
+    lam = graphgen.spectral_lambda(g)
+    eps = 0.1
+    sc, _ = saba.aesc(saba.SabaGraph.from_graph(g), eps, lam, 3)
+    sc = sc.cpu().numpy()
+    so, _ = orc.aesc(g, eps, lam, seed=3)
+    np.testing.assert_allclose(sc, so, rtol=RTOL, atol=1e-15)
+    ex = exact_sc.sc_pinv(g.row_ptr, g.col_idx, g.n)
+    ce = graphgen.canonical_edges(g)
+    added = np.array([[min(a, b), max(a, b)] for a, b in extra])
+    is_added = np.array([any((e == a).all() for a in added) for e in ce])
+    assert is_added.sum() == len(extra)
+    np.testing.assert_allclose(ex[is_added], 1.0, atol=1e-9)
+    bridges = np.abs(ex - 1.0) < 1e-9
+    assert np.all(np.abs(sc[bridges] - 1.0) <= eps)
+    assert abs(ex.sum() - (g.n - 1)) < 1e-6
+    assert np.all(np.abs(sc - ex) <= eps)
+    assert abs(sc.sum() - (g.n - 1)) <= eps * g.m
