@@ -448,7 +448,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
 constexpr int kSortRowsLog = 32, kSortRowsRow = 16;
 
 // Scatter the log entries of the same blocks/tiles as the walk kernel into bucket order.
-// Block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...].  Each
+// Block k's entries of bucket b go to part[pos[b * gridDim.x + k] + 0, 1, ...], each stored
+// as its 16-bit offset within the bucket (x & (2^bsh - 1); bsh <= 14), since the bucket of a
+// position is known from pos: half the bytes of the vertex id for the scatter's stores and
+// the histogram's loads.  Each
 // group of kSortRows rows x 256 walks is first sorted by bucket in LDS, so every bucket
 // leaves the block as one contiguous run.  The walks with a valid start are
 // w0 .. min(w0 + wc, offs[n]) - 1, as in the walk kernel; other entries are not read.  With
@@ -459,7 +462,7 @@ template <int kSortRows, bool CHECK>
 __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
     const int32_t *__restrict__ vlog, int32_t rows, int64_t wc, const int64_t *__restrict__ offs,
     int32_t n, int64_t w0, int bsh, int32_t nbk, const int64_t *__restrict__ pos,
-    int32_t *__restrict__ part, int64_t limit) {
+    uint16_t *__restrict__ part, int64_t limit) {
     extern __shared__ unsigned char lds_raw[];
     int64_t *gpos = reinterpret_cast<int64_t *>(lds_raw);           // [nbk] global cursor
     uint32_t *lcnt = reinterpret_cast<uint32_t *>(gpos + nbk);       // [nbk] counts / cursors
@@ -534,10 +537,11 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_scatter_kernel(
             }
             __syncthreads();
             const uint32_t total = loff[nbk];
+            const int32_t lmask = (1 << bsh) - 1;
             for (uint32_t j = threadIdx.x; j < total; j += kWalkBlock) {
                 const int32_t x = keys[j];
                 const int32_t b = x >> bsh;
-                part[gpos[b] + (j - loff[b])] = x;
+                part[gpos[b] + (j - loff[b])] = (uint16_t)(x & lmask);
             }
             __syncthreads();
             for (int b = threadIdx.x; b < nbk; b += kWalkBlock) gpos[b] += loff[b + 1] - loff[b];
@@ -556,18 +560,22 @@ static size_t scatter_lds_bytes(int32_t nbk, int sort_rows) {
            sizeof(int32_t) * sort_rows * kWalkBlock + sizeof(uint32_t) * 4 + 16;
 }
 
-// Histogram of the bucket-ordered entries: block j counts part[j*slice, (j+1)*slice) bucket
-// by bucket in LDS and adds the nonzero bins to out.  Bucket b starts at pos[b * nblk].  The
-// entries are read 16 bytes at a time, kHistUnroll reads in flight per thread, so the stream
-// is not bound by the latency of one read per LDS update.
+// Histogram of the bucket-ordered entries (16-bit offsets within their bucket): block j counts
+// part[j*slice, (j+1)*slice) bucket by bucket in LDS and adds the nonzero bins to out.  Bucket
+// b starts at pos[b * nblk].  The entries are read 16 bytes (8 entries) at a time, kHistUnroll
+// reads in flight per thread, so the stream is not bound by the latency of one read per LDS
+// update.
 constexpr int kHistUnroll = 4;
 
-__device__ __forceinline__ void hist_add(uint32_t *lds_h, int32_t x, int32_t mask) {
-    atomicAdd(lds_h + (x & mask), 1u);
+__device__ __forceinline__ void hist_add(uint32_t *lds_h, uint32_t x) { atomicAdd(lds_h + x, 1u); }
+
+__device__ __forceinline__ void hist_add2(uint32_t *lds_h, uint32_t two) {
+    hist_add(lds_h, two & 0xFFFFu);
+    hist_add(lds_h, two >> 16);
 }
 
 __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
-    const int32_t *__restrict__ part, const int64_t *__restrict__ pos, int nblk, int bsh,
+    const uint16_t *__restrict__ part, const int64_t *__restrict__ pos, int nblk, int bsh,
     int32_t nbk, int64_t slice, int32_t n, unsigned long long *__restrict__ out) {
     extern __shared__ uint32_t lds_h[];
     const int32_t bins = 1 << bsh;
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
         else
             hi = mid;
     }
-    const nbr_vec4 *part4 = reinterpret_cast<const nbr_vec4 *>(part);  // 4 int32 entries
+    const nbr_vec4 *part8 = reinterpret_cast<const nbr_vec4 *>(part);  // 8 entries per 16 bytes
     for (int32_t b = lo; b < nbk; ++b) {
         const int64_t bs = pos[(int64_t)b * nblk];
         const int64_t be = pos[(int64_t)(b + 1) * nblk];
@@ -593,26 +601,25 @@ __global__ __launch_bounds__(kWalkBlock) void bucket_hist_kernel(
         for (int i = threadIdx.x; i < bins; i += kWalkBlock) lds_h[i] = 0;
         __syncthreads();
         // entries a .. z: an unaligned head and tail one by one, whole 16-byte words between
-        const int64_t q0 = (a + 3) >> 2, q1 = z >> 2;
+        const int64_t q0 = (a + 7) >> 3, q1 = z >> 3;
         if (q0 >= q1) {
-            for (int64_t i = a + threadIdx.x; i < z; i += kWalkBlock)
-                hist_add(lds_h, part[i], bins - 1);
+            for (int64_t i = a + threadIdx.x; i < z; i += kWalkBlock) hist_add(lds_h, part[i]);
         } else {
-            if (a + threadIdx.x < 4 * q0) hist_add(lds_h, part[a + threadIdx.x], bins - 1);
-            if (4 * q1 + threadIdx.x < z) hist_add(lds_h, part[4 * q1 + threadIdx.x], bins - 1);
+            if (a + threadIdx.x < 8 * q0) hist_add(lds_h, part[a + threadIdx.x]);
+            if (8 * q1 + threadIdx.x < z) hist_add(lds_h, part[8 * q1 + threadIdx.x]);
             for (int64_t q = q0 + threadIdx.x; q < q1; q += kHistUnroll * kWalkBlock) {
                 nbr_vec4 x[kHistUnroll];
 #pragma unroll
                 for (int u = 0; u < kHistUnroll; ++u)
                     if (q + u * kWalkBlock < q1)
-                        x[u] = __builtin_nontemporal_load(part4 + q + u * kWalkBlock);
+                        x[u] = __builtin_nontemporal_load(part8 + q + u * kWalkBlock);
 #pragma unroll
                 for (int u = 0; u < kHistUnroll; ++u)
                     if (q + u * kWalkBlock < q1) {
-                        hist_add(lds_h, x[u].x, bins - 1);
-                        hist_add(lds_h, x[u].y, bins - 1);
-                        hist_add(lds_h, x[u].z, bins - 1);
-                        hist_add(lds_h, x[u].w, bins - 1);
+                        hist_add2(lds_h, (uint32_t)x[u].x);
+                        hist_add2(lds_h, (uint32_t)x[u].y);
+                        hist_add2(lds_h, (uint32_t)x[u].z);
+                        hist_add2(lds_h, (uint32_t)x[u].w);
                     }
             }
         }
@@ -642,7 +649,7 @@ static int64_t hist_slice(int64_t bound) {
 // Bucketed count of one log (rows x wc entries, `valid` walks per row) into out.
 static int bucket_count(const int32_t *vlog, int32_t rows, int64_t wc, const int64_t *offs,
                         int64_t w0, int nblk, int bsh, int32_t nbk, int64_t *cnt, int64_t *pos,
-                        void *scan_tmp, int32_t *part, int32_t n, unsigned long long *out,
+                        void *scan_tmp, uint16_t *part, int32_t n, unsigned long long *out,
                         hipStream_t s, int64_t limit, bool check = false) {
     const int64_t ncnt = (int64_t)nbk * nblk;
     SABA_TRY(scan_i64(cnt, pos, ncnt, scan_tmp, s));
@@ -1057,7 +1064,7 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
                 const int nb = (int)std::min<int64_t>(want_blocks, (c + kWalkBlock - 1) / kWalkBlock);
                 const int64_t nc = (int64_t)nbk * nb;
                 *lg = sizeof(int32_t) * (size_t)(std::max<int64_t>((int64_t)L * c, 1) + c);
-                *pt = sizeof(int32_t) * (size_t)std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * c, W);
+                *pt = sizeof(uint16_t) * (size_t)std::max<int64_t>((int64_t)std::max<int32_t>(L, 1) * c, W);
                 *cn = sizeof(int64_t) * (size_t)(2 * nbuf * nc + nc + 2) + scan_tmp_bytes(nc);
                 return nbuf * WalkArena::up(*lg) + WalkArena::up(*pt) + WalkArena::up(*cn);
             };
@@ -1070,7 +1077,8 @@ static int walks_impl(Graph *g, const saba_walk_params *p, int64_t *d_endpoint,
             const int64_t ncnt = (int64_t)nbk * nblk;
             const int64_t logn = std::max<int64_t>((int64_t)L * wc, 1);
             const size_t lg_stride = WalkArena::up(lg_b) / sizeof(int32_t);
-            int32_t *vlog_all = nullptr, *part = nullptr;
+            int32_t *vlog_all = nullptr;
+            uint16_t *part = nullptr;
             int64_t *cnt_all = nullptr;
             SABA_TRY(ar.get(4, (size_t)(nbuf - 1) * WalkArena::up(lg_b) + lg_b, &vlog_all));
             SABA_TRY(ar.get(5, pt_b, &part));
