@@ -570,18 +570,21 @@ def bench_omega(args, saba, torch, np):
             "lambda": lam["lambda"], "rows": rows, "grouped": grouped}
 
 
-def bench_aesc_full(args, saba, torch, np):
+def bench_aesc_full(args, saba, torch, np, tuned=None):
     """All edges of the 10^6-vertex Chung-Lu graph at eps = 0.1.  omega = 0: the sources in 100
     consecutive ranges (saba_aesc_sources, one progress line per range; each source's levels
     run once), then saba_aesc_combine, which gives saba_aesc's output bit for bit.  omega > 0
     (the eigenpair tail belongs to the undirected edge): the canonical edges in 40 query calls,
-    each equal to the all-edges call's entries."""
+    each equal to the all-edges call's entries.  Execution knobs: those the 1% query leg tuned
+    on this graph when given, else the staged walk-pair schedule (no knob changes a result)."""
     import graphgen
     g, lam1, _ = chung_lu_1e6()
     omega = args.omega
     # omega > 0: the radius of the rest of the spectrum comes from the library
     lam = lam1 if omega == 0 else 0.0
     sg = saba.SabaGraph.from_graph(g, trusted=True)
+    knobs = dict(tuned) if tuned else {"est_walk_queue": 2}
+    saba.set_config(sg, **knobs)
     ce = graphgen.canonical_edges(g)
     saba.aesc_query(sg, torch.from_numpy(np.ascontiguousarray(ce[:64])).cuda(), args.aesc_eps, lam, 1,
                     omega=omega)
@@ -616,7 +619,8 @@ def bench_aesc_full(args, saba, torch, np):
     return {"workload": "chung_lu_n1e6_k10_b2.5_lcc_eps0.1_all_edges"
             + (f"_omega{omega}" if omega else ""), "edges": g.m, "n": g.n,
             "lambda": lam, "omega": omega, "seconds": dt, "edges_per_s": g.m / dt,
-            "walk_steps": steps, "sum_sc": sums, "n_minus_1": g.n - 1, "form": form}
+            "walk_steps": steps, "sum_sc": sums, "n_minus_1": g.n - 1, "form": form,
+            "knobs": saba.get_config(sg)}
 
 
 def _batch_graph(spec):
@@ -790,13 +794,13 @@ def bench_batch(args, saba, torch, np):
     assert same, "batched results differ from single-graph results"
     outs_c, st_c, t_batch_cert = batched([reqs[k] for k in certified])
     assert all(bool(torch.equal(single[k], o)) for k, o in zip(certified, outs_c))
-    # the two walk-pair schedules at the tuned grids
+    # the three walk-pair schedules at the tuned grids
     sched = {}
-    for wq in (0, 1):
+    for wq, name in ((0, "static"), (1, "queue"), (2, "staged")):
         saba.set_config(mg, **{**tuned, "est_walk_queue": wq})
         _, st_q, t_q = batched(reqs)
-        sched["queue" if wq else "static"] = {"seconds": t_q, "walk_kernel_ms": st_q["kernel_ms"]}
-        progress(f"batch workload: {'queue' if wq else 'static'} schedule {t_q:.3f} s")
+        sched[name] = {"seconds": t_q, "walk_kernel_ms": st_q["kernel_ms"]}
+        progress(f"batch workload: {name} schedule {t_q:.3f} s")
     saba.set_config(mg, **tuned)
     nq_cert = sum(int(qs[k].shape[0]) for k in certified)
     kinds = {0: "erdos_renyi", 1: "chung_lu", 2: "grid"}
@@ -1253,7 +1257,7 @@ def main():
             if "cpu_baseline" in a:
                 out["cpu_baseline"] = a["cpu_baseline"]
     if args.workload == "all" and not args.no_full:
-        f = bench_aesc_full(args, saba, torch, np)
+        f = bench_aesc_full(args, saba, torch, np, tuned=out.get("aesc", {}).get("tuned"))
         out["aesc_all_edges"] = f
         progress(f"aesc all edges done: {f['edges_per_s']:.0f} edges/s, sum {f['sum_sc']:.1f} "
                  f"(n - 1 = {f['n_minus_1']})")

@@ -233,9 +233,13 @@ typedef struct {
                                 passes of a chunk run on a second stream while the next chunk
                                 walks (0: 4 when each chunk still holds 2^19 walks, else as few
                                 as the 2^29-entry log allows; at most 64) */
-    int32_t est_walk_queue;  /* 1: the estimator's walk-pair launch takes its chunks from
-                                device work queues (one per XCD range of the chunk space);
-                                0: a fixed wavefront stride over the chunks */
+    int32_t est_walk_queue;  /* the estimator's walk-pair schedule.  0: a fixed wavefront stride
+                                over the chunks; 1: device work queues, one per XCD range of
+                                the chunk space; 2: staged tiles, blocks of 1024 threads take
+                                up to 32 chunks of one source at a time from per-XCD queues
+                                and test support membership against the source's bitmap
+                                copied into LDS (falls back to 1 when the largest graph's
+                                bitmap exceeds a block's LDS, and for saba_aesc_counts) */
     int32_t est_batch_streams; /* streams of the synchronous estimator calls: 1 (and 0) = every
                                   batch in order on the caller's stream; 2 = two pool sets of
                                   half the memory budget each, the deterministic levels of
@@ -400,7 +404,8 @@ int saba_autotune_bouquet(saba_graph *g, const saba_walk_params *sample, double 
  * Autotuner of the estimator: runs the requests `sample` (as saba_aesc_batch, with `opt`,
  * which may be NULL) under each candidate grid (512, 1024, 2048 or 4096 blocks for the
  * walk-pair kernel x 1024, 2048, 4096 or 8192 blocks for the frontier-group kernels x the
- * static or the work-queue walk-pair schedule x one or two batch streams), times whole
+ * static, the work-queue or the staged walk-pair schedule (whose grid follows from its LDS, so
+ * it is tried at one walk-pair grid) x one or two batch streams), times whole
  * calls with HIP events, keeps the fastest in the handle and returns it in *best (may be
  * NULL).  The knobs do not change results; the sample's outputs hold its results on return.
  * Errors: those of saba_aesc_batch, SABA_E_INVALID for an empty sample.

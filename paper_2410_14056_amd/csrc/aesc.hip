@@ -880,77 +880,102 @@ __device__ __forceinline__ int64_t wave_dequeue(unsigned long long *ctr) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <bool kCount, bool kQueue>
-__global__ __launch_bounds__(kBlock) void mc_walk_kernel(
-    const int2 *__restrict__ vrec, const int32_t *__restrict__ col, const int4 *__restrict__ nbr,
-    const Slot *__restrict__ slots,
-    const PSet *__restrict__ psets, const BatchState *__restrict__ bs, int32_t nb,
-    const int64_t *__restrict__ eb, int64_t ie0, const int64_t *__restrict__ coff, int64_t nle,
-    const int32_t *__restrict__ tau, const long long *__restrict__ nreq,
-    const double *__restrict__ hA, const double *__restrict__ hB, const uint32_t *__restrict__ bmA,
-    const uint32_t *__restrict__ bmB, double *__restrict__ partial,
-    unsigned long long *__restrict__ vis0, unsigned long long *__restrict__ vis1,
-    Flags *__restrict__ fl, CountArgs ca, unsigned long long *__restrict__ wq) {
+// Arguments of the walk-pair kernels.
+struct McArgs {
+    const int2 *vrec;
+    const int32_t *col;
+    const int4 *nbr;
+    const Slot *slots;
+    const PSet *psets;
+    const BatchState *bs;
+    int32_t nb;
+    const int64_t *eb;
+    int64_t ie0;
+    const int64_t *coff;
+    int64_t nle;
+    const int32_t *tau;
+    const long long *nreq;
+    const double *hA, *hB;
+    const uint32_t *bmA, *bmB;
+    double *partial;
+    unsigned long long *vis0, *vis1;
+    CountArgs ca;
+};
+
+// The support bitmap of the slot a block has staged in LDS (mc_walk_staged_kernel).
+extern __shared__ uint32_t mc_stage[];
+
+// Chunk c of the walk pairs: 64 walks of one instance edge, reduced over the wavefront in a
+// fixed order.  kLds: the support test reads the bitmap staged in LDS (the caller has staged
+// the chunk's slot), else the slot's bitmap in global memory.
+template <bool kCount, bool kLds>
+__device__ __forceinline__ void mc_chunk(const McArgs &a, int64_t c) {
     const int lane = __lane_id();
-    const int64_t T = coff[nle];
-    // chunk c: 64 walks of one instance edge, reduced over the wavefront in a fixed order
-    const auto chunk = [&](int64_t c) {
-        const int64_t le = upper_index(coff, nle + 1, c);
-        const int64_t b = upper_index(eb, nb + 1, le);
-        const Slot sl = slots[b];
-        const PSet ps = psets[sl.p];
-        const int2 rs = vrec[sl.v];
-        const int32_t i = (int32_t)(le - eb[b]);
-        const int64_t ie = ie0 + le;
-        const int32_t t = col[rs.x + i];
-        const long long nr = nreq[ie];
-        const int32_t L = tau[ie] - bs[b].ttau;
-        const int fb = bs[b].finalbuf;
-        const double *h = (fb ? hB : hA) + sl.hoff;
-        const uint32_t *bm = (fb ? bmB : bmA) + sl.bmoff;
-        const long long j = (c - coff[le]) * kChunk + lane;
-        const bool active = j < 2 * nr;
-        const int side = j >= nr ? 1 : 0;
-        const long long k = j - side * nr;
-        double acc = 0.0;
-        long long hits = 0;
-        const int32_t *F = nullptr;
-        int32_t fsz = 0;
-        int64_t hrow = -1;
-        if (kCount) {
-            F = (fb ? ca.FB : ca.FA) + sl.hoff;
-            fsz = bs[b].fsz[fb];
-            // a support that differs from the layout's is not counted (the export flags it)
-            const int64_t h0 = ca.hoff[sl.inst];
-            if (h0 >= 0 && ca.expect[sl.inst] == fsz) hrow = h0 + ((int64_t)i * 2 + side) * fsz;
-        }
-        if (active) {
-            const int32_t sloc = sl.v - sl.goff, tloc = t - sl.goff;
-            Walker wk = walker_init<SABA_SAMPLER_KEYED>(walk_key(
-                ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side, (uint64_t)k, ps.G, ps.S));
-            WalkPos p = walk_pos(vrec, side ? t : sl.v);
-            for (int32_t l = 1; l <= L; ++l) {
-                // the hash sees the graph's own vertex ids
-                p = walker_step_nbr_nt<SABA_SAMPLER_KEYED>(nbr, p, (uint32_t)(p.v - sl.goff),
-                                                           (uint32_t)l, wk);
-                const int32_t xl = p.v - sl.goff;
-                if (bm[xl >> 5] & (1u << (xl & 31))) {  // h_ttau is zero off its support
-                    acc += h[xl];  // cached: the hubs' values are read again and again
-                    hits += 1;
-                    if (kCount && hrow >= 0)
-                        atomicAdd(ca.hist + hrow + support_rank(F, fsz, p.v), 1ull);
-                }
+    const int64_t le = upper_index(a.coff, a.nle + 1, c);
+    const int64_t b = upper_index(a.eb, a.nb + 1, le);
+    const Slot sl = a.slots[b];
+    const PSet ps = a.psets[sl.p];
+    const int2 rs = a.vrec[sl.v];
+    const int32_t i = (int32_t)(le - a.eb[b]);
+    const int64_t ie = a.ie0 + le;
+    const int32_t t = a.col[rs.x + i];
+    const long long nr = a.nreq[ie];
+    const int32_t L = a.tau[ie] - a.bs[b].ttau;
+    const int fb = a.bs[b].finalbuf;
+    const double *h = (fb ? a.hB : a.hA) + sl.hoff;
+    const uint32_t *bm = (fb ? a.bmB : a.bmA) + sl.bmoff;
+    const long long j = (c - a.coff[le]) * kChunk + lane;
+    const bool active = j < 2 * nr;
+    const int side = j >= nr ? 1 : 0;
+    const long long k = j - side * nr;
+    double acc = 0.0;
+    long long hits = 0;
+    const int32_t *F = nullptr;
+    int32_t fsz = 0;
+    int64_t hrow = -1;
+    if (kCount) {
+        F = (fb ? a.ca.FB : a.ca.FA) + sl.hoff;
+        fsz = a.bs[b].fsz[fb];
+        // a support that differs from the layout's is not counted (the export flags it)
+        const int64_t h0 = a.ca.hoff[sl.inst];
+        if (h0 >= 0 && a.ca.expect[sl.inst] == fsz) hrow = h0 + ((int64_t)i * 2 + side) * fsz;
+    }
+    if (active) {
+        const int32_t sloc = sl.v - sl.goff, tloc = t - sl.goff;
+        Walker wk = walker_init<SABA_SAMPLER_KEYED>(walk_key(
+            ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side, (uint64_t)k, ps.G, ps.S));
+        WalkPos p = walk_pos(a.vrec, side ? t : sl.v);
+        for (int32_t l = 1; l <= L; ++l) {
+            // the hash sees the graph's own vertex ids
+            p = walker_step_nbr_nt<SABA_SAMPLER_KEYED>(a.nbr, p, (uint32_t)(p.v - sl.goff),
+                                                       (uint32_t)l, wk);
+            const int32_t xl = p.v - sl.goff;
+            uint32_t word;
+            if constexpr (kLds)
+                word = mc_stage[xl >> 5];
+            else
+                word = bm[xl >> 5];
+            if (word & (1u << (xl & 31))) {  // h_ttau is zero off its support
+                acc += h[xl];  // cached: the hubs' values are read again and again
+                hits += 1;
+                if (kCount && hrow >= 0)
+                    atomicAdd(a.ca.hist + hrow + support_rank(F, fsz, p.v), 1ull);
             }
         }
-        const double sum = wave_sum_d(active ? (side ? -acc : acc) : 0.0);
-        const long long h0 = wave_sum_ll(active && !side ? hits : 0);
-        const long long h1 = wave_sum_ll(active && side ? hits : 0);
-        if (lane == 0) {
-            partial[c] = sum;
-            if (h0) atomicAdd(vis0 + ie, (unsigned long long)h0);
-            if (h1) atomicAdd(vis1 + ie, (unsigned long long)h1);
-        }
-    };
+    }
+    const double sum = wave_sum_d(active ? (side ? -acc : acc) : 0.0);
+    const long long h0 = wave_sum_ll(active && !side ? hits : 0);
+    const long long h1 = wave_sum_ll(active && side ? hits : 0);
+    if (lane == 0) {
+        a.partial[c] = sum;
+        if (h0) atomicAdd(a.vis0 + ie, (unsigned long long)h0);
+        if (h1) atomicAdd(a.vis1 + ie, (unsigned long long)h1);
+    }
+}
+
+template <bool kCount, bool kQueue>
+__global__ __launch_bounds__(kBlock) void mc_walk_kernel(McArgs a, unsigned long long *__restrict__ wq) {
+    const int64_t T = a.coff[a.nle];
     if (kQueue) {
         const int xcd = (int)(blockIdx.x % kXcds);  // the dispatcher deals blocks round-robin
         for (int r = 0; r < kXcds; ++r) {
@@ -959,13 +984,88 @@ __global__ __launch_bounds__(kBlock) void mc_walk_kernel(
             for (;;) {
                 const int64_t c = q0 + wave_dequeue(wq + q);
                 if (c >= q1) break;
-                chunk(c);
+                mc_chunk<kCount, false>(a, c);
             }
         }
     } else {
         const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
         for (int64_t c = xcd_block() * kWavesPerBlock + (threadIdx.x >> 6); c < T; c += nwaves)
-            chunk(c);
+            mc_chunk<kCount, false>(a, c);
+    }
+}
+
+// Tiles of the staged walk-pair launch: the chunks of slot b, [coff[eb[b]], coff[eb[b + 1]]),
+// cut into tiles of up to kStageTile chunks; ntile[b] tiles.
+constexpr int kStageBlock = 1024;  // threads of a staged block (16 wavefronts)
+constexpr size_t kStageStatic = 256;  // room for the staged kernel's own LDS variables
+constexpr int kMaxThreadsPerCu = 2048;
+constexpr int kStageTile = 32;     // chunks per tile (two per wavefront)
+constexpr int kStageMin = 16;      // a tile of fewer chunks is not worth staging the bitmap
+__global__ __launch_bounds__(kBlock) void stage_tiles_kernel(const int64_t *__restrict__ eb,
+                                                             int32_t nb,
+                                                             const int64_t *__restrict__ coff,
+                                                             int64_t *__restrict__ ntile) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int64_t nch = coff[eb[b + 1]] - coff[eb[b]];
+    ntile[b] = (nch + kStageTile - 1) / kStageTile;
+}
+
+// The walk pairs with each slot's support bitmap staged in LDS.  A block takes a tile (chunks of
+// one slot) from the work queue of its XCD's range of tiles, then from the other ranges; when
+// the tile's slot differs from the staged one and the tile holds at least kStageMin chunks, the
+// block copies the slot's bitmap into LDS; its wavefronts then take the tile's chunks one at a
+// time from an LDS counter.  The support test of a step then reads LDS, so it no longer waits
+// in line with the walk-entry and h loads.  A chunk's walks, sums and counts are those of the
+// other walk-pair schedules.
+__global__ __launch_bounds__(kStageBlock) void mc_walk_staged_kernel(
+    McArgs a, const int64_t *__restrict__ toff, unsigned long long *__restrict__ tq) {
+    __shared__ int64_t s_tile;
+    __shared__ unsigned int s_next;
+    const int32_t nb = a.nb;
+    const int64_t TT = toff[nb];
+    int64_t staged = -1;  // slot whose bitmap the LDS holds (block-uniform)
+    const int xcd = (int)(blockIdx.x % kXcds);
+    for (int r = 0; r < kXcds; ++r) {
+        const int q = (xcd + r) % kXcds;
+        const int64_t q0 = TT * q / kXcds, q1 = TT * (q + 1) / kXcds;
+        for (;;) {
+            if (threadIdx.x == 0) {
+                s_tile = q0 + (int64_t)atomicAdd(tq + q, 1ull);
+                s_next = 0;
+            }
+            __syncthreads();
+            const int64_t u = s_tile;
+            if (u >= q1) {
+                __syncthreads();  // s_tile is read by every thread before it is rewritten
+                break;
+            }
+            const int64_t b = upper_index(toff, nb + 1, u);
+            const int64_t cb0 = a.coff[a.eb[b]], cb1 = a.coff[a.eb[b + 1]];
+            const int64_t c0 = cb0 + (u - toff[b]) * kStageTile;
+            const int64_t c1 = min(cb1, c0 + kStageTile);
+            const bool stage = c1 - c0 >= kStageMin;
+            if (stage && b != staged) {
+                const Slot sl = a.slots[b];
+                const uint32_t *bm = (a.bs[b].finalbuf ? a.bmB : a.bmA) + sl.bmoff;
+                const int32_t words = (sl.gn + 31) >> 5;
+                for (int32_t w = threadIdx.x; w < words; w += kStageBlock) mc_stage[w] = bm[w];
+                staged = b;
+                __syncthreads();
+            }
+            for (;;) {
+                unsigned int v = 0;
+                const unsigned long long act = __ballot(1);
+                if ((int)__lane_id() == __builtin_ctzll(act)) v = atomicAdd(&s_next, 1u);
+                const int64_t c = c0 + (int64_t)__builtin_amdgcn_readfirstlane(v);
+                if (c >= c1) break;
+                if (stage)
+                    mc_chunk<false, true>(a, c);
+                else
+                    mc_chunk<false, false>(a, c);
+            }
+            __syncthreads();  // the tile is done before s_tile, s_next and the LDS are rewritten
+        }
     }
 }
 
@@ -1240,6 +1340,7 @@ int ensure_pools(Workspace &ws, int64_t h, int64_t bm, int64_t sb, int64_t hubs,
     SABA_TRY(E[B_EB].ensure(sizeof(int64_t) * (nb + 1)));
     SABA_TRY(E[B_BSTATE].ensure(sizeof(BatchState) * nb));
     SABA_TRY(E[B_GOFS].ensure(sizeof(int64_t) * 2 * (nb + 1)));
+    SABA_TRY(E[B_TILES].ensure(sizeof(int64_t) * (2 * nb + 1)));
     SABA_TRY(E[B_HUBS].ensure(sizeof(int2) * 2 * std::max<int64_t>(hubs, 1)));
     SABA_TRY(E[B_CHUNKS].ensure(sizeof(long long) * ne));
     SABA_TRY(E[B_COFF].ensure(sizeof(int64_t) * (ne + 1)));
@@ -1345,6 +1446,7 @@ int batch_levels(const Graph *g, Workspace &ws, const EdgeArrays &ea,
     plan->nle = nle;
     plan->T = T;
     plan->ysplit = ysplit;
+    plan->maxgn = maxgn;
     return SABA_OK;
 }
 
@@ -1367,26 +1469,52 @@ int batch_walks(const Graph *g, Workspace &ws, const EdgeArrays &ea, const Batch
     const dim3 grid(plan.ysplit, (unsigned)nb);
     if (T > 0) {
         const bool timing = t0 && t1;
-        if (timing) SABA_HIP_TRY(hipEventRecord(t0, s));
-        const unsigned wgrid = grid_for(T, kWavesPerBlock, walk_blocks);
-        const bool queue = g->cfg.est_walk_queue == 1;
-        if (queue) SABA_HIP_TRY(hipMemsetAsync(fl->wq, 0, sizeof(fl->wq), s));
-#define SABA_MC_LAUNCH(C, Q, CA)                                                                  \
-    mc_walk_kernel<C, Q><<<wgrid, kBlock, 0, s>>>(g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, \
-                                                  bs, nb, d_eb, ie0, coff, nle, ea.tau, ea.nreq, \
-                                                  hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1, fl, \
-                                                  CA, fl->wq)
-        if (cx && cx->supp) {
-            if (queue)
-                SABA_MC_LAUNCH(true, true, cx->ca);
-            else
-                SABA_MC_LAUNCH(true, false, cx->ca);
-        } else if (queue) {
-            SABA_MC_LAUNCH(false, true, CountArgs{});
-        } else {
-            SABA_MC_LAUNCH(false, false, CountArgs{});
+        const bool counts = cx && cx->supp;
+        const McArgs ma{g->vrec, g->col_idx, g->nbr, d_slots, ea.psets, bs, nb, d_eb, ie0, coff,
+                        nle, ea.tau, ea.nreq, hA, hB, bmA, bmB, partial, ea.vis0, ea.vis1,
+                        counts ? cx->ca : CountArgs{}};
+        // the staged schedule needs the largest graph's support bitmap to fit a block's LDS
+        int max_lds = 0;
+        SABA_HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                           g->device));
+        const size_t stage_lds = sizeof(uint32_t) * (size_t)((plan.maxgn + 31) / 32);
+        const bool staged = g->cfg.est_walk_queue == 2 && !counts &&
+                            stage_lds + kStageStatic <= (size_t)max_lds;
+        const bool queue = g->cfg.est_walk_queue >= 1 && !staged;
+        int64_t *ntile = E[B_TILES].as<int64_t>(), *toff = ntile + nb;
+        if (staged) {
+            stage_tiles_kernel<<<grid_for(nb, kBlock), kBlock, 0, s>>>(d_eb, nb, coff, ntile);
+            SABA_HIP_TRY(hipGetLastError());
+            SABA_TRY(scan_i64(ntile, toff, nb, E[B_SCAN].ptr, s));
+            SABA_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&mc_walk_staged_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)stage_lds));
         }
-#undef SABA_MC_LAUNCH
+        if (staged || queue) SABA_HIP_TRY(hipMemsetAsync(fl->wq, 0, sizeof(fl->wq), s));
+        if (timing) SABA_HIP_TRY(hipEventRecord(t0, s));
+        if (staged) {
+            // as many blocks as the compute units hold at once (the LDS bounds them)
+            const int per_cu = (int)std::max<size_t>(
+                1, std::min<size_t>(kMaxThreadsPerCu / kStageBlock,
+                                    (size_t)max_lds / (stage_lds + kStageStatic)));
+            int cus = 0;
+            SABA_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                               g->device));
+            mc_walk_staged_kernel<<<(unsigned)(std::max(cus, 1) * per_cu), kStageBlock,
+                                    stage_lds, s>>>(ma, toff, fl->wq);
+        } else {
+            const unsigned wgrid = grid_for(T, kWavesPerBlock, walk_blocks);
+            if (counts) {
+                if (queue)
+                    mc_walk_kernel<true, true><<<wgrid, kBlock, 0, s>>>(ma, fl->wq);
+                else
+                    mc_walk_kernel<true, false><<<wgrid, kBlock, 0, s>>>(ma, fl->wq);
+            } else if (queue) {
+                mc_walk_kernel<false, true><<<wgrid, kBlock, 0, s>>>(ma, fl->wq);
+            } else {
+                mc_walk_kernel<false, false><<<wgrid, kBlock, 0, s>>>(ma, fl->wq);
+            }
+        }
         SABA_HIP_TRY(hipGetLastError());
         if (timing) SABA_HIP_TRY(hipEventRecord(t1, s));
     }
@@ -2210,9 +2338,10 @@ extern "C" int saba_autotune_aesc(saba_graph *gh, const saba_aesc_request *sampl
     const int walk_blocks[] = {512, 1024, 2048, 4096};
     const int push_blocks[] = {1024, 2048, 4096, 8192};
     for (int streams = 1; streams <= 2; ++streams)
-        for (int wq = 0; wq < 2; ++wq)
+        for (int wq = 0; wq <= 2; ++wq)
             for (int wb : walk_blocks)
                 for (int pb : push_blocks) {
+                    if (wq == 2 && wb != walk_blocks[0]) continue;  // its grid follows the LDS
                     g->cfg = saved;
                     g->cfg.est_walk_blocks = wb;
                     g->cfg.est_push_blocks = pb;

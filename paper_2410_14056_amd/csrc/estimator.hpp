@@ -19,7 +19,7 @@ namespace saba {
 enum {
     B_PSET, B_SLOT, B_EB, B_BSTATE, B_WANT, B_TAU, B_D, B_NREQ, B_MC, B_VIS0, B_VIS1, B_G,
     B_TTAU, B_HA, B_HB, B_FA, B_FB, B_BMA, B_BMB, B_SLOTBM, B_CHUNKS, B_COFF, B_PART, B_SCAN,
-    B_FLAGS, B_PAIRS, B_MAP, B_GOFS, B_HUBS, B_COUNT
+    B_FLAGS, B_PAIRS, B_MAP, B_GOFS, B_HUBS, B_TILES, B_COUNT
 };
 static_assert(B_COUNT <= 32, "Workspace holds 32 buffers");
 
@@ -143,6 +143,7 @@ int run_batch(const Graph *g, Workspace &ws, const EdgeArrays &ea, const std::ve
 struct BatchPlan {
     int32_t nb = 0;
     int64_t ie0 = 0, nle = 0, T = 0;  // T: 64-walk chunks of the walk-pair launch
+    int64_t maxgn = 1;                // vertices of the batch's largest graph
     unsigned ysplit = 1;
 };
 int batch_levels(const Graph *g, Workspace &ws, const EdgeArrays &ea,

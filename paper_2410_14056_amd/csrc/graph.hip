@@ -505,7 +505,7 @@ extern "C" int saba_graph_set_config(saba_graph *gh, const saba_exec_config *cfg
         cfg->walk_blocks < 0 || cfg->walk_blocks > (1 << 16) || cfg->est_walk_blocks < 0 ||
         cfg->est_walk_blocks > (1 << 16) || cfg->est_push_blocks < 0 ||
         cfg->est_push_blocks > (1 << 16) || cfg->walk_chunks < 0 || cfg->walk_chunks > 64 ||
-        (cfg->est_walk_queue != 0 && cfg->est_walk_queue != 1) || cfg->est_batch_streams < 0 ||
+        cfg->est_walk_queue < 0 || cfg->est_walk_queue > 2 || cfg->est_batch_streams < 0 ||
         cfg->est_batch_streams > 2) {
         set_error("invalid execution configuration");
         return SABA_E_INVALID;

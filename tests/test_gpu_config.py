@@ -54,7 +54,7 @@ def test_estimator_knobs_do_not_change_results(saba):
     lam = graphgen.spectral_lambda(g)
     sg = saba.SabaGraph.from_graph(g)
     ref, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
-    for wq in (0, 1):
+    for wq in (0, 1, 2):  # stride, queues, staged tiles (support bitmaps in LDS)
         for wb, pb in ((1, 1), (3, 17), (512, 4096), (8192, 64)):
             saba.set_config(sg, est_walk_blocks=wb, est_push_blocks=pb, est_walk_queue=wq)
             sc, _ = saba.aesc(sg, 0.2, lam, 4, tau_cap=64)
@@ -77,10 +77,10 @@ def test_batch_streams_do_not_change_results(saba):
     ce = graphgen.canonical_edges(g)
     pick = np.random.default_rng(8).choice(g.m, 300, replace=False)
     q = torch.from_numpy(np.ascontiguousarray(ce[pick])).cuda()
-    for bsrc in (0, 250, 333, 1500):
+    for bsrc, wq in ((0, 1), (250, 2), (333, 1), (1500, 2)):
         outs = {}
         for streams in (1, 2, 0):
-            saba.set_config(sg, est_walk_queue=1, est_batch_streams=streams)
+            saba.set_config(sg, est_walk_queue=wq, est_batch_streams=streams)
             sc, st = saba.aesc(sg, 0.2, lam, 4, tau_cap=64, batch_sources=bsrc,
                                time_kernels=True)
             qs, qst = saba.aesc_query(sg, q, 0.2, lam, 4, tau_cap=64, batch_sources=bsrc)
@@ -110,7 +110,7 @@ def test_estimator_autotuner(saba):
     best = saba.autotune_aesc(mg, reqs)
     assert best["est_walk_blocks"] in (512, 1024, 2048, 4096)
     assert best["est_push_blocks"] in (1024, 2048, 4096, 8192)
-    assert best["est_walk_queue"] in (0, 1)
+    assert best["est_walk_queue"] in (0, 1, 2)
     assert best["est_batch_streams"] in (1, 2)
     assert saba.get_config(mg) == best
     out, _ = saba.aesc_batch(mg, reqs)
@@ -144,7 +144,7 @@ def test_results_do_not_depend_on_the_stream(saba):
 def test_config_rejects_bad_values(saba):
     sg = saba.SabaGraph.from_graph(graphgen.toy_graph())
     for kw in ({"walks_per_lane": 3}, {"walk_blocks": -1}, {"est_push_blocks": 1 << 20},
-               {"walk_chunks": 65}, {"walk_chunks": -1}, {"est_walk_queue": 2},
+               {"walk_chunks": 65}, {"walk_chunks": -1}, {"est_walk_queue": 3},
                {"est_batch_streams": 3}, {"est_batch_streams": -1}):
         with pytest.raises(saba.SabaError) as ei:
             saba.set_config(sg, **kw)
