@@ -69,10 +69,11 @@ def kernel_source_sha(files=("saba_internal.hpp", "walks.hip")) -> str:
     return h.hexdigest()[:16]
 
 
-def estimator_traffic(walk_steps: int, launches: int):
+def estimator_traffic(walk_steps: int, launches: int, kernel: str):
     """Fabric bytes per launch of the walk-pair kernel from the committed counter runs, if they
-    were taken on the current estimator source with the same query (same walk steps); else
-    None.  The runs give bytes per walk step; a launch averages walk_steps / launches steps."""
+    were taken on the current estimator source with the same kernel and query (same walk
+    steps); else None.  The runs give bytes per walk step; a launch averages walk_steps /
+    launches steps."""
     try:
         with open(EST_COUNTERS) as f:
             c = json.load(f)
@@ -80,6 +81,8 @@ def estimator_traffic(walk_steps: int, launches: int):
         return None
     if c.get("kernel_source_sha") != kernel_source_sha(("saba_internal.hpp", "estimator.hpp",
                                                         "aesc.hip")):
+        return None
+    if c.get("kernel") != kernel:
         return None
     if c.get("walk_steps") != walk_steps or launches <= 0:
         return None
@@ -433,6 +436,8 @@ def bench_aesc(args, saba, torch, np):
     assert bool(torch.isfinite(sc).all().item())
     assert torch.equal(sc, sc1), "results differ between the batch-stream settings"
     walk_s = st["kernel_ms"] * 1e-3
+    # the walk-pair kernel of the tuned schedule (the staged one keeps the support bitmap in LDS)
+    mc_kernel = "mc_walk_staged_kernel" if cfg["est_walk_queue"] == 2 else "mc_walk_kernel"
     achieved = AESC_STEP_BYTES * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
     line = AESC_STEP_BYTES_LINE * st["walk_steps"] / walk_s / 1e9 if walk_s > 0 else 0.0
     out = {
@@ -453,9 +458,9 @@ def bench_aesc(args, saba, torch, np):
         "other_batch_streams": {"est_batch_streams": other, "seconds": d1,
                                 "edges_per_s": k / d1, "batches": st1["batches"],
                                 "walk_kernel_ms": st1["kernel_ms"], "identical": True},
-        "roofline": {"bound": "hbm", "kernel": "mc_walk_kernel", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": mc_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": estimator_traffic(st["walk_steps"], st["batches"]),
+                     "traffic": estimator_traffic(st["walk_steps"], st["batches"], mc_kernel),
                      "traffic_basis": TRAFFIC_BASIS,
                      "kernel_ms": st["kernel_ms"], "launches": st["batches"],
                      "bytes_per_step": AESC_STEP_BYTES,

@@ -1001,6 +1001,7 @@ constexpr size_t kStageStatic = 256;  // room for the staged kernel's own LDS va
 constexpr int kMaxThreadsPerCu = 2048;
 constexpr int kStageTile = 32;     // chunks per tile (two per wavefront)
 constexpr int kStageMin = 16;      // a tile of fewer chunks is not worth staging the bitmap
+constexpr int kStageLoads = 8;     // bitmap words per thread in flight while staging
 __global__ __launch_bounds__(kBlock) void stage_tiles_kernel(const int64_t *__restrict__ eb,
                                                              int32_t nb,
                                                              const int64_t *__restrict__ coff,
@@ -1049,7 +1050,20 @@ __global__ __launch_bounds__(kStageBlock) void mc_walk_staged_kernel(
                 const Slot sl = a.slots[b];
                 const uint32_t *bm = (a.bs[b].finalbuf ? a.bmB : a.bmA) + sl.bmoff;
                 const int32_t words = (sl.gn + 31) >> 5;
-                for (int32_t w = threadIdx.x; w < words; w += kStageBlock) mc_stage[w] = bm[w];
+                // kStageLoads coalesced loads in flight per thread before their LDS stores
+                for (int32_t w0 = threadIdx.x; w0 < words; w0 += kStageLoads * kStageBlock) {
+                    uint32_t v[kStageLoads];
+#pragma unroll
+                    for (int u = 0; u < kStageLoads; ++u) {
+                        const int32_t w = w0 + u * kStageBlock;
+                        v[u] = w < words ? bm[w] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kStageLoads; ++u) {
+                        const int32_t w = w0 + u * kStageBlock;
+                        if (w < words) mc_stage[w] = v[u];
+                    }
+                }
                 staged = b;
                 __syncthreads();
             }
