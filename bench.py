@@ -58,7 +58,7 @@ TRAFFIC_BASIS = ("bytes the L2 requested from the memory fabric (FETCH_SIZE x 2.
 COUNTERS = os.path.join(ROOT, "profiles", "walk_bouquet_log_kernel_rmat20_counters.json")
 
 
-EST_COUNTERS = os.path.join(ROOT, "profiles", "mc_walk_kernel_chunglu1m_query1pct_counters.json")
+EST_COUNTERS = os.path.join(ROOT, "profiles", "mc_walk_staged_kernel_chunglu1m_query1pct_counters.json")
 
 
 def kernel_source_sha(files=("saba_internal.hpp", "walks.hip")) -> str:
