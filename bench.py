@@ -918,6 +918,7 @@ def bench_serve(args, saba, torch, np):
     prep_s = time.perf_counter() - t0
     ces = [graphgen.canonical_edges(g) for g in graphs]
     mg = saba.SabaGraph.from_graphs(graphs, trusted=True)
+    saba.set_config(mg, est_walk_queue=args.serve_walk_queue)
     budget = int(args.serve_mem_gib * (1 << 30))
 
     def server(**kw):
@@ -1016,7 +1017,7 @@ def bench_serve(args, saba, torch, np):
         res = {"workload": "serve_16_chung_lu_n1e4-1e6_k10_b2.5_q1-4096_eps0.1-0.3",
                "graphs": len(graphs), "vertices": sum(g.n for g in graphs),
                "edges": sum(g.m for g in graphs), "prep_s": prep_s, "lanes": args.serve_lanes,
-               "mem_budget_gib": args.serve_mem_gib}
+               "mem_budget_gib": args.serve_mem_gib, "knobs": saba.get_config(mg)}
         with server(max_queued_edges=args.serve_queue_edges) as srv:
             res["offered"] = open_loop(srv, args.serve_rate, args.serve_seconds, 11, "offered")
             res["offered"]["queue_bound_edges"] = args.serve_queue_edges
@@ -1039,7 +1040,7 @@ def bench_serve(args, saba, torch, np):
     res = {"workload": "serve_16_chung_lu_n1e4-1e6_k10_b2.5_q1-4096_eps0.1-0.3",
            "graphs": len(graphs), "vertices": sum(g.n for g in graphs),
            "edges": sum(g.m for g in graphs), "prep_s": prep_s, "lanes": args.serve_lanes,
-           "mem_budget_gib": args.serve_mem_gib}
+           "mem_budget_gib": args.serve_mem_gib, "knobs": saba.get_config(mg)}
     progress("serve workload: offered load")
     with server(max_queued_edges=args.serve_queue_edges) as srv:
         res["offered"] = open_loop(srv, args.serve_rate, args.serve_seconds, 11, "offered")
@@ -1127,6 +1128,9 @@ def main():
     ap.add_argument("--batch-frac", type=float, default=0.01,
                     help="fraction of every graph's edges queried in --workload batch")
     ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-walk-queue", type=int, default=0,
+                    help="walk-pair schedule of the served handle (est_walk_queue: 0 stride, "
+                         "1 work queues, 2 staged tiles)")
     ap.add_argument("--serve-mem-gib", type=float, default=32.0)
     ap.add_argument("--serve-max-batch", type=int, default=0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
