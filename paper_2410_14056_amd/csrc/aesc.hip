@@ -400,6 +400,45 @@ __device__ __forceinline__ void expand_entry(const int32_t *__restrict__ col,
     if (slot >= 0) set_bit(sbm, slot - sl.gpos);
 }
 
+// expand_entry for kPullWin entries per lane (e[u], valid positions; in[u]: the entry is
+// wanted), with the entry, hub-slot and support-word loads of all of them in flight together
+// before the atomic ORs.
+__device__ __forceinline__ void expand_entries(const int32_t *__restrict__ col,
+                                               const int32_t *__restrict__ slotv, const Slot &sl,
+                                               uint32_t *__restrict__ bm,
+                                               uint32_t *__restrict__ sbm,
+                                               const int32_t (&e)[kPullWin],
+                                               const bool (&in)[kPullWin]) {
+    int32_t x[kPullWin], sv[kPullWin];
+    uint32_t wx[kPullWin], ws[kPullWin];
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u) x[u] = col[e[u]] - sl.goff;
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u) sv[u] = slotv[e[u]];
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u)
+        wx[u] = __hip_atomic_load(bm + (x[u] >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u) {
+        ws[u] = ~0u;
+        if (sv[u] >= 0)
+            ws[u] = __hip_atomic_load(sbm + ((sv[u] - sl.gpos) >> 5), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u) {
+        const uint32_t bit = 1u << (x[u] & 31);
+        if (in[u] && !(wx[u] & bit)) atomicOr(bm + (x[u] >> 5), bit);
+    }
+#pragma unroll
+    for (int u = 0; u < kPullWin; ++u) {
+        if (!in[u] || sv[u] < 0) continue;
+        const int32_t i = sv[u] - sl.gpos;
+        const uint32_t bit = 1u << (i & 31);
+        if (!(ws[u] & bit)) atomicOr(sbm + (i >> 5), bit);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const int2 *__restrict__ vrec, const int32_t *__restrict__ col,
     const int32_t *__restrict__ slotv, const Slot *__restrict__ slots,
@@ -425,14 +464,20 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
         uint32_t *sbm = slotbm_all + sl.sboff;
         const WaveRows w = wave_rows(vrec, F, (gi - gc.gbase) * 64, fsz, true);
         if (lane == 0) visits += w.total;
-        for (int32_t j0 = 0; j0 < w.total; j0 += 64) {
+        for (int32_t j0 = 0; j0 < w.total; j0 += 64 * kPullWin) {
             // cross-lane reads happen with every lane active; only memory accesses are masked
-            const int32_t j = j0 + lane;
-            const bool inr = j < w.total;
-            const int32_t jc = inr ? j : w.total - 1;
-            const int o = wave_owner(w.pre, jc);
-            const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
-            if (inr) expand_entry(col, slotv, sl, bm, sbm, ost + (jc - opre));
+            int32_t e[kPullWin];
+            bool in[kPullWin];
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) {
+                const int32_t j = j0 + 64 * u + lane;
+                in[u] = j < w.total;
+                const int32_t jc = in[u] ? j : w.total - 1;
+                const int o = wave_owner(w.pre, jc);
+                const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
+                e[u] = ost + (jc - opre);
+            }
+            expand_entries(col, slotv, sl, bm, sbm, e, in);
         }
     }
     visits = wave_sum_ll((long long)visits);
@@ -612,13 +657,25 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
                 const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
                 e[u] = ost + (jc - opre);
             }
+            // every e[u] is a position in one of the group's rows (j is clamped to the last
+            // entry), so the entry and support-word loads need no guard and go out together;
+            // the value loads are all issued before the first LDS store waits on them
 #pragma unroll
-            for (int u = 0; u < kPullWin; ++u) y[u] = in[u] ? col[e[u]] - sl.goff : 0;
+            for (int u = 0; u < kPullWin; ++u) y[u] = col[e[u]] - sl.goff;
 #pragma unroll
-            for (int u = 0; u < kPullWin; ++u) wd[u] = in[u] ? bm[y[u] >> 5] : 0u;
+            for (int u = 0; u < kPullWin; ++u) wd[u] = bm[y[u] >> 5];
+            // the support bit as plain arithmetic, so no load is moved under a branch
+            uint32_t bit[kPullWin];
 #pragma unroll
-            for (int u = 0; u < kPullWin; ++u)
-                lds[64 * u + lane] = ((wd[u] >> (y[u] & 31)) & 1u) ? h[y[u]] : 0.0;
+            for (int u = 0; u < kPullWin; ++u) bit[u] = (wd[u] >> (y[u] & 31)) & (uint32_t)in[u];
+            double v[kPullWin];
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) {
+                v[u] = 0.0;
+                if (bit[u] & 1u) v[u] = h[y[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kPullWin; ++u) lds[64 * u + lane] = v[u];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
