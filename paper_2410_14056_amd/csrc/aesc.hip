@@ -1003,9 +1003,15 @@ __device__ __forceinline__ void mc_chunk(const McArgs &a, int64_t c) {
             ps.seed, (uint32_t)sloc, (uint32_t)tloc, (uint32_t)side, (uint64_t)k, ps.G, ps.S));
         WalkPos p = walk_pos(a.vrec, side ? t : sl.v);
         for (int32_t l = 1; l <= L; ++l) {
-            // the hash sees the graph's own vertex ids
-            p = walker_step_nbr_nt<SABA_SAMPLER_KEYED>(a.nbr, p, (uint32_t)(p.v - sl.goff),
-                                                       (uint32_t)l, wk);
+            // the hash sees the graph's own vertex ids; the entry read is non-temporal where the
+            // support bitmap is read from global memory (so that the random entry stream does
+            // not push it out of L2) and cached where the bitmap sits in LDS
+            if constexpr (kLds)
+                p = walker_step_nbr<SABA_SAMPLER_KEYED>(a.nbr, p, (uint32_t)(p.v - sl.goff),
+                                                        (uint32_t)l, wk);
+            else
+                p = walker_step_nbr_nt<SABA_SAMPLER_KEYED>(a.nbr, p, (uint32_t)(p.v - sl.goff),
+                                                           (uint32_t)l, wk);
             const int32_t xl = p.v - sl.goff;
             uint32_t word;
             if constexpr (kLds)
