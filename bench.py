@@ -513,10 +513,12 @@ def bench_omega(args, saba, torch, np):
     """The eigenpair form of the truncation on the 1% query workload of the 10^6-vertex
     Chung-Lu graph: for each omega, the cost of the leading eigenpairs (a fresh Lanczos run),
     the radius tau is taken from, and the estimator's time and walk steps with the pairs
-    cached.  omega = 0 is the plain series with the library's lambda."""
+    cached.  omega = 0 is the plain series with the library's lambda.  Walk pairs on the staged
+    schedule (support bitmaps in LDS; no knob changes a result)."""
     import graphgen
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
     sg = saba.SabaGraph.from_graph(g, trusted=True)
+    saba.set_config(sg, est_walk_queue=2)
     ce = graphgen.canonical_edges(g)
     perm = np.random.default_rng(7).permutation(g.m)
     k = max(1, int(round(args.aesc_frac * g.m)))
