@@ -97,6 +97,26 @@ def test_batch_streams_do_not_change_results(saba):
     saba.set_config(sg)
 
 
+def test_staged_schedule_falls_back_beyond_the_lds(saba):
+    """A graph of 1.39e6 vertices, whose support bitmap (174 KB) exceeds a block's LDS: the
+    staged schedule falls back to the work queues and gives the results of the other
+    schedules, bit for bit."""
+    import torch
+    g = graphgen.largest_component(graphgen.er_gnm(1400000, 3500000, 3))
+    assert (g.n + 31) // 32 * 4 > 160 * 1024
+    sg = saba.SabaGraph.from_graph(g, trusted=True)
+    ce = graphgen.canonical_edges(g)
+    pick = np.random.default_rng(4).choice(g.m, 64, replace=False)
+    q = torch.from_numpy(np.ascontiguousarray(ce[pick])).cuda()
+    outs = []
+    for wq in (0, 1, 2):
+        saba.set_config(sg, est_walk_queue=wq)
+        sc, st = saba.aesc_query(sg, q, 0.3, 0.0, 2, tau_cap=24)
+        outs.append((sc, st["walk_steps"]))
+    for sc, steps in outs[1:]:
+        assert torch.equal(sc, outs[0][0]) and steps == outs[0][1]
+
+
 def test_estimator_autotuner(saba):
     """saba_autotune_aesc picks a candidate grid, keeps it in the handle, and the sample's
     outputs and later results equal the untuned ones."""
