@@ -309,7 +309,7 @@ __device__ __forceinline__ int64_t upper_index(const int64_t *__restrict__ a, in
 // wavefronts.  Hub rows are not part of the groups' work: they go to the hub-row lists.
 constexpr int kPushGrid = 2048;
 constexpr int kHubGrid = 1024;  // blocks of the hub-row kernels
-constexpr int kPullWin = 4;     // 64-entry chunks per pass of the ordinary-row pull
+constexpr int kPullWin = 16;    // 64-entry chunks per pass of the ordinary-row push kernels
 
 __global__ __launch_bounds__(1024) void group_scan_kernel(const BatchState *__restrict__ bs,
                                                           int32_t nb, int parity,
@@ -472,6 +472,10 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
             for (int u = 0; u < kPullWin; ++u) {
                 const int32_t j = j0 + 64 * u + lane;
                 in[u] = j < w.total;
+                if (j0 + 64 * u >= w.total) {  // wave-uniform: a chunk past the group's end
+                    e[u] = e[0];                 // (a valid position; nothing is taken from it)
+                    continue;
+                }
                 const int32_t jc = in[u] ? j : w.total - 1;
                 const int o = wave_owner(w.pre, jc);
                 const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
@@ -652,6 +656,10 @@ __global__ __launch_bounds__(kBlock) void pull_kernel(
             for (int u = 0; u < kPullWin; ++u) {
                 const int32_t j = j0 + 64 * u + lane;
                 in[u] = j < w.total;
+                if (j0 + 64 * u >= w.total) {  // wave-uniform: a chunk past the group's end
+                    e[u] = e[0];                 // (a valid position; nothing is taken from it)
+                    continue;
+                }
                 const int32_t jc = in[u] ? j : w.total - 1;
                 const int o = wave_owner(w.pre, jc);
                 const int32_t ost = __shfl(w.start, o), opre = __shfl(w.pre, o);
