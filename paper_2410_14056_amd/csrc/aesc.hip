@@ -29,9 +29,12 @@
 // across lanes; the pull folds only the terms whose vertex is in the support bitmap (a zero
 // term leaves a sum of non-negative numbers unchanged), in row order, so every h value is
 // bit-identical to the sequential left fold over the whole row.  The walk pairs of all instance
-// edges of the batch are cut into chunks of 64 walks; one persistent launch covers all of them,
-// a wavefront reduces a chunk in a fixed butterfly order, and each edge sums its chunks in chunk
-// order, so results do not depend on the launch shape.
+// edges of the batch are cut into chunks of 64 walks; one persistent launch covers all of them
+// (a fixed wavefront stride, per-XCD work queues, or tiles of one source's chunks per block with
+// the source's support bitmap staged in LDS), a wavefront reduces a chunk in a fixed butterfly
+// order, and each edge sums its chunks in chunk order, so results do not depend on the schedule
+// or the launch shape.  The synchronous calls may run the levels of the next batch on a second
+// stream, with a second pool set, while the walk pairs of the current batch run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
