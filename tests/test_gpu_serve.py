@@ -62,9 +62,13 @@ def _submit(srv, lams, r):
                       tau_cap=r["tau_cap"])
 
 
-def test_served_results_equal_alone(saba, orc, graphs):
+@pytest.mark.parametrize("schedule", [0, 2])
+def test_served_results_equal_alone(saba, orc, graphs, schedule):
+    """Served results equal each request alone, with the served handle on the stride
+    schedule or on the staged one (two lanes each launching LDS-staged walk-pair kernels)."""
     gs, lams = graphs
     mg = saba.SabaGraph.from_graphs(gs)
+    saba.set_config(mg, est_walk_queue=schedule)
     reqs = _requests(gs, lams, 14, 1)
     expect = [_alone(saba, gs, lams, r) for r in reqs]
     with saba.SabaServer(mg, lanes=2, max_batch_sources=5) as srv:
