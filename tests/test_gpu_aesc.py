@@ -198,8 +198,10 @@ def test_chung_lu_query_matches_oracle(saba, orc):
 
 def test_chung_lu_1e6_query_sampled_edges_match_oracle(saba, orc):
     """The 10^6-vertex Chung-Lu graph at eps = 0.1 in the benchmark's launch configuration (the
-    1% query with the default source scratch): 24 of its edges, computed by the oracle on their
-    own, equal the GPU's entries (a query's entries do not depend on the other pairs)."""
+    1% query with the default source scratch, on the staged walk-pair schedule its autotuner
+    keeps): 24 of its edges, computed by the oracle on their own, equal the GPU's entries (a
+    query's entries do not depend on the other pairs), and every entry of the query equals the
+    one the fixed-stride schedule returns."""
     import os
     import torch
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
@@ -210,11 +212,16 @@ def test_chung_lu_1e6_query_sampled_edges_match_oracle(saba, orc):
     q = np.ascontiguousarray(ce[np.sort(perm[:k])])
     print(f"chung-lu 1e6 sampled parity n={g.n} m={g.m} q={k}", flush=True)
     sg = saba.SabaGraph.from_graph(g, trusted=True)
-    sq, st = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.1, lam, 1)
+    qd = torch.from_numpy(q).cuda()
+    saba.set_config(sg, est_walk_queue=2)
+    sq, st = saba.aesc_query(sg, qd, 0.1, lam, 1)
     pick = np.sort(np.random.default_rng(3).choice(k, 24, replace=False))
     so, _ = orc.aesc(g, 0.1, lam, seed=1, query=q[pick], nthreads=min(16, os.cpu_count() or 1))
     np.testing.assert_allclose(sq.cpu().numpy()[pick], so, rtol=RTOL, atol=1e-15)
     assert st["sources"] > 0 and st["walk_steps"] > 0
+    saba.set_config(sg, est_walk_queue=0)
+    s0, st0 = saba.aesc_query(sg, qd, 0.1, lam, 1)
+    assert torch.equal(s0, sq) and st0["walk_steps"] == st["walk_steps"]
 
 
 

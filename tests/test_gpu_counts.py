@@ -170,8 +170,9 @@ def test_chung_lu_1e6_counts_match_oracle(saba, orc):
     """The 10^6-vertex Chung-Lu graph at eps = 0.1: 24 edges of the benchmark's seeded 1% query
     (endpoints of degree <= 24) and a source whose row is above the hub threshold.  The integer internals of
     the edges' directed estimates and the histograms of their sources match the oracle, and
-    the query run in the benchmark's launch configuration returns g(u, v) + g(v, u) of exactly
-    these directed estimates."""
+    the query run in the benchmark's launch configuration (the staged walk-pair schedule its
+    autotuner keeps; the counts call itself runs on the work queues) returns g(u, v) + g(v, u)
+    of exactly these directed estimates."""
     import torch
     g = graphgen.largest_component(graphgen.chung_lu(1000000, 10, 2.5, 1))
     lam = graphgen.spectral_lambda(g)
@@ -185,6 +186,7 @@ def test_chung_lu_1e6_counts_match_oracle(saba, orc):
     sources = [int(x) for x in np.unique(q[pick].ravel())]
     print(f"chung-lu 1e6 counts n={g.n} m={g.m} q={k} sources={len(sources)}", flush=True)
     sg = saba.SabaGraph.from_graph(g, trusted=True)
+    saba.set_config(sg, est_walk_queue=2)
     sq, _ = saba.aesc_query(sg, torch.from_numpy(q).cuda(), 0.1, lam, 1)
     per, out, _ = saba.aesc_counts(sg, sources, 0.1, lam, 1)
     ref = _oracle_counts(orc, g, sources, 0.1, lam, 1)
