@@ -127,8 +127,9 @@ def rmat20():
 
 
 def test_rmat20_full_size(saba, orc, rmat20):
-    """The walk benchmark at full size (R-MAT scale 20, 2^24 walks of 64 steps, two visit-log
-    chunks) in its launch configuration (explicit uniform starts, autotuned knobs): the
+    """The walk benchmark at full size (R-MAT scale 20, 2^24 walks of 64 steps, the visit log in
+    the chunks the autotuner keeps) in its launch configuration (explicit uniform starts,
+    autotuned knobs): the
     endpoint and visit histograms of the bouquet and naive kernels equal the oracle's over
     the whole workload, for independent walks (G = 1) and grouped ones (G = 64, S = 20)."""
     import os
