@@ -1574,9 +1574,12 @@ int batch_walks(const Graph *g, Workspace &ws, const EdgeArrays &ea, const Batch
             stage_tiles_kernel<<<grid_for(nb, kBlock), kBlock, 0, s>>>(d_eb, nb, coff, ntile);
             SABA_HIP_TRY(hipGetLastError());
             SABA_TRY(scan_i64(ntile, toff, nb, E[B_SCAN].ptr, s));
+            // the limit is a property of the kernel, shared by every caller in the process: it
+            // is always set to the same value (the most a block may take), so calls from several
+            // host threads (the server's lanes, on graphs of different sizes) agree on it
             SABA_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&mc_walk_staged_kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)stage_lds));
+                                             max_lds - (int)kStageStatic));
         }
         if (staged || queue) SABA_HIP_TRY(hipMemsetAsync(fl->wq, 0, sizeof(fl->wq), s));
         if (timing) SABA_HIP_TRY(hipEventRecord(t0, s));
