@@ -198,7 +198,9 @@ def test_16_graph_server_full_size_served_match_alone_and_oracle(saba, orc):
     """The serving benchmark's 16 resident graphs at full size (Chung-Lu, n = 10^4 .. 10^6) under
     its server settings (2 lanes, 32 GiB of source scratch): a burst of 16 requests of 1-512
     edges (one of them on the 10^6-vertex graph) served together equals each request run alone,
-    and 6 edges of the largest graph's request and of another match the oracle."""
+    also with the served handle on the staged walk-pair schedule (both lanes then launch
+    LDS-staged kernels for graphs of different sizes at once), and 6 edges of the largest
+    graph's request and of another match the oracle."""
     import os
     import torch
     import bench
@@ -217,6 +219,13 @@ def test_16_graph_server_full_size_served_match_alone_and_oracle(saba, orc):
     with saba.SabaServer(mg, lanes=2, mem_budget=32 << 30) as srv:
         tickets = [_submit(srv, lams, r) for r in reqs]
         served = [srv.wait(t)[0].cpu().numpy() for t in tickets]
+    print("16-graph server at full size: the staged walk-pair schedule", flush=True)
+    saba.set_config(mg, est_walk_queue=2)
+    with saba.SabaServer(mg, lanes=2, mem_budget=32 << 30) as srv:
+        tickets = [_submit(srv, lams, r) for r in reqs]
+        for t, sc in zip(tickets, served):
+            assert np.array_equal(srv.wait(t)[0].cpu().numpy(), sc)
+    saba.set_config(mg)
     handles = {}
     for r, sc in zip(reqs, served):
         k = r["graph"]
