@@ -361,7 +361,10 @@ int saba_graph_lambda(saba_graph *g, const saba_lambda_params *p, saba_lambda_re
 int saba_graph_spectrum(saba_graph *g, const saba_spectrum_params *p, double *values,
                         double *d_vectors, saba_spectrum_result *out, void *stream);
 
-/* Read or replace the execution knobs of a handle (SABA_E_INVALID for values out of range). */
+/* Read or replace the execution knobs of a handle (SABA_E_INVALID for values out of range).
+ * The knobs are read without a lock by every call on the handle and by the lanes of a server
+ * over it: replace them (here or through an autotuner, which sets them while it times) only
+ * while no other call on g and no server over g runs. */
 int saba_graph_get_config(const saba_graph *g, saba_exec_config *out);
 int saba_graph_set_config(saba_graph *g, const saba_exec_config *cfg);
 
