@@ -464,9 +464,9 @@ int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, in
                saba_stats *stats, void *stream);
 
 /*
- * saba_walks for callers that cannot allocate device memory (code under HIP graph capture,
- * tight serving loops, harnesses that forbid hipMalloc): the same walks and the same
- * histograms, bit for bit, with every scratch buffer taken from a fixed 256 MiB region of
+ * saba_walks for callers that cannot allocate device memory (tight serving loops, harnesses
+ * that forbid hipMalloc): the same walks and the same histograms, bit for bit, with every
+ * scratch buffer taken from a fixed 256 MiB region of
  * device memory that the library holds on each device until the process ends.  The call
  * makes no hipMalloc, hipFree or other allocating call; the caller passes d_endpoint and
  * d_visits (device, n int64 each) and the sources.  Only mode SABA_WALK_BOUQUET with
@@ -475,7 +475,9 @@ int saba_walks(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint, in
  * visit log of a chunk of walks (chunks shrink to fit, down to 256 walks).  A call that does
  * not fit returns SABA_E_INVALID ("more scratch than the fixed region holds") before any walk
  * runs.  All calls on one device share the region: calls that overlap in time on one device
- * (other streams or threads) race and must not be issued.
+ * (other streams or threads) race and must not be issued.  Like saba_walks, the call clears
+ * its outputs and counters with hipMemsetAsync and synchronises `stream` before it returns
+ * (it reads the kernels' error flag), so it is not meant to be recorded into a HIP graph.
  * Errors: those of saba_walks, and SABA_E_INVALID for another mode or source mode.
  */
 int saba_walks_noalloc(saba_graph *g, const saba_walk_params *p, int64_t *d_endpoint,
