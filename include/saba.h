@@ -19,6 +19,9 @@
  *     is enqueued on it.  Calls that must read device results on the host
  *     (the estimator's level loop, statistics) synchronise that stream.
  *   - A graph handle may be used by one stream at a time.
+ *   - A graph handle belongs to the device that was current when it was created: make that
+ *     device current before every call on it (the library does not switch devices; a
+ *     server's own lane threads do so themselves).
  *   - Results depend only on (graph, parameters): bouquet width, launch shape
  *     and batching never change them.
  */
